@@ -1,0 +1,142 @@
+"""Seeded synthetic workloads shared by the CPU oracle and the GPU library.
+
+This module only *produces inputs*: Hamiltonian parameter sets, initial
+occupations, random MPS tensors and serving request streams.  It holds none
+of the TEBD arithmetic (no gates, no SVDs, no truncation, no measurement), so
+that the oracle and the HIP path stay independent of each other while being
+fed bit-identical inputs.
+
+Parameter sets follow the quench of Eq. (1) (Sec. I A): on-site interaction U,
+nearest-neighbour hopping J (=1, the unit of energy), next-nearest-neighbour
+hopping J_NNN and a harmonic trap of strength K centred at j_c, with sites
+numbered 1..L in the trap term.  The charge-density-wave start is the Fock
+product state of Sec. II B.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Model:
+    """Eq. (1) parameters.  ``jc`` is the trap centre in 1-based site units."""
+
+    L: int
+    d: int
+    U: float
+    J: float = 1.0
+    Jnnn: float = 0.0
+    K: float = 0.0
+    jc: float | None = None
+
+    def centre(self) -> float:
+        return (self.L + 1) / 2.0 if self.jc is None else float(self.jc)
+
+
+@dataclasses.dataclass(frozen=True)
+class Trunc:
+    """Truncation settings of Sec. II B: bond cap chi_max, discarded-weight
+    tolerance w_max and relative singular-value tolerance eps."""
+
+    chi_max: int
+    w_max: float = 1e-12
+    eps: float = 1e-12
+
+
+# The five workloads the library is exercised on.  Sizes, couplings and time
+# steps are fixed here once; tests shorten horizons, never shapes.
+CONFIGS = {
+    # L=8 open chain, d=3, exact bond dimension 81, U/J = 5, NN only.
+    "exact_L8_d3": dict(model=Model(L=8, d=3, U=5.0, J=1.0, Jnnn=0.0, K=0.0),
+                        trunc=Trunc(chi_max=81, w_max=0.0, eps=1e-14),
+                        dt=0.01, steps=100),
+    # L=32, d=5, NNN hopping and trap centred at 16.5, chi = 256.
+    "nnn_L32_d5_chi256": dict(model=Model(L=32, d=5, U=5.0, J=1.0, Jnnn=0.1, K=0.005, jc=16.5),
+                              trunc=Trunc(chi_max=256, w_max=1e-12, eps=1e-12),
+                              dt=0.01, steps=500),
+    # L=64 batched layers, chi grows from 1 to 512, truncation weight 1e-10.
+    "batched_L64_chi512": dict(model=Model(L=64, d=5, U=3.0, J=1.0, Jnnn=0.1, K=0.002, jc=32.5),
+                               trunc=Trunc(chi_max=512, w_max=1e-10, eps=1e-12),
+                               dt=0.01, steps=100),
+    # L=64 bulk chi = 1024 throughput workload, U/J = 2, no trap.
+    "bulk_L64_chi1024": dict(model=Model(L=64, d=5, U=2.0, J=1.0, Jnnn=0.1, K=0.0, jc=32.5),
+                             trunc=Trunc(chi_max=1024, w_max=1e-12, eps=1e-12),
+                             dt=0.01, steps=100),
+}
+
+
+def cdw_occupations(L: int, first_occupied: int = 1) -> List[int]:
+    """Occupations of the CDW start |1,0,1,0,...> (first_occupied=1) or
+    |0,1,0,1,...> (first_occupied=0); 0-based site i."""
+    if first_occupied not in (0, 1):
+        raise ValueError("first_occupied must be 0 or 1")
+    return [1 if (i % 2 == 0) == bool(first_occupied) else 0 for i in range(L)]
+
+
+def bulk_bond_dims(L: int, d: int, chi: int) -> List[int]:
+    """Bond dimensions chi_b = min(d^b, d^(L-b), chi), b = 0..L."""
+    out = []
+    for b in range(L + 1):
+        e = min(b, L - b)
+        v = 1
+        for _ in range(e):
+            v *= d
+            if v >= chi:
+                v = chi
+                break
+        out.append(min(v, chi))
+    return out
+
+
+def random_mps(L: int, d: int, chi: int, seed: int = 0, tau: float = 30.0,
+               bonds: List[int] | None = None) -> Tuple[List[np.ndarray], List[np.ndarray]]:
+    """Random MPS in (B, Lambda) form with right-orthonormal B tensors.
+
+    B_i has shape (chi_i, d, chi_{i+1}); its (chi_i) x (d chi_{i+1}) matrix
+    has orthonormal rows (drawn as the conjugate transpose of the Q factor
+    of a complex Gaussian).  Lambda_b is a decaying profile
+    s_k ~ exp(-k / tau) normalised to unit 2-norm; Lambda_0 = Lambda_L = [1].
+    The profile is imposed, not derived, so the state is right-canonical
+    but not left-canonical: a throughput input of the right shapes and of a
+    graded spectrum, fed identically to both implementations.
+    """
+    rng = np.random.default_rng(seed)
+    if bonds is None:
+        bonds = bulk_bond_dims(L, d, chi)
+    B = []
+    for i in range(L):
+        cl, cr = bonds[i], bonds[i + 1]
+        g = rng.standard_normal((d * cr, cl)) + 1j * rng.standard_normal((d * cr, cl))
+        q, _ = np.linalg.qr(g)
+        B.append(np.ascontiguousarray(q.conj().T.reshape(cl, d, cr)))
+    lam = []
+    for b in range(L + 1):
+        k = np.arange(bonds[b], dtype=np.float64)
+        s = np.exp(-k / tau)
+        lam.append(s / np.sqrt(np.sum(s * s)))
+    return B, lam
+
+
+def serving_requests(n: int = 64, seed: int = 5, rate: float = 1.0, small: bool = False):
+    """Poisson stream of quench requests (arrival times in seconds).
+
+    Each request draws L from {16,32,48,64}, chi_max from {128,...,1024}
+    (from {16,32,64} when ``small``), U ~ U[2,10], J_NNN = 0.1,
+    K ~ U[0, 0.01], horizon ~ U[1, 5] in units of hbar/J and dt = 0.01.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    chis = [16, 32, 64] if small else [128, 256, 512, 1024]
+    for r in range(n):
+        t += rng.exponential(1.0 / rate)
+        L = int(rng.choice([16, 32, 48, 64]))
+        out.append(dict(id=r, arrival=t,
+                        model=Model(L=L, d=5, U=float(rng.uniform(2.0, 10.0)), J=1.0, Jnnn=0.1,
+                                    K=float(rng.uniform(0.0, 0.01))),
+                        chi_max=int(rng.choice(chis)),
+                        horizon=float(rng.uniform(1.0, 5.0)), dt=0.01))
+    return out
