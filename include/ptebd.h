@@ -1,0 +1,170 @@
+/*
+ * ptebd.h -- C ABI of the MI355X three-site TEBD library.
+ *
+ * The library evolves a matrix product state (MPS) of the 1D Bose-Hubbard
+ * chain with nearest- and next-nearest-neighbour hopping and a harmonic trap
+ * (Eq. (1) of the paper), starting from a charge-density-wave product state
+ * (Sec. II B), by time-evolving block decimation: each Trotter layer applies
+ * commuting three-site gates exp(-i h_j tau) grouped by j mod 3, contracts
+ * theta, truncates it by SVD to the bond cap and updates the tensors
+ * (Sec. I, Sec. II B).  Local densities and NN / NNN correlators are then
+ * measured assuming orthonormality (Sec. II B; Eqs. (4), (7)).
+ *
+ * Conventions
+ *   - Sites i = 0..L-1; bonds b = 0..L, bond b sits left of site b.
+ *     Lambda_0 = Lambda_L = [1].  The trap term uses x = i + 1 (1-based), so
+ *     tebd_model.jc is a 1-based position.
+ *   - Stored form: B_i = Gamma_i Lambda_{i+1}, shape (chi_i, d, chi_{i+1}),
+ *     row-major with chi_{i+1} fastest; complex numbers are planar (all real
+ *     parts, then all imaginary parts).  Units: J = hbar = 1 (Sec. I A).
+ *   - Gate g_j acts on sites (j, j+1, j+2), j = 0..L-3; group = j mod 3.
+ *   - The three-site share of Eq. (1) is: the NNN hop (j, j+2) in full, each
+ *     NN hop divided by the number of windows containing its bond, each
+ *     on-site (U, K) term divided by the number of windows containing its
+ *     site, so that the shares sum to H exactly.
+ *   - Truncation (Sec. II B: bond cap chi_max, discarded-weight tolerance
+ *     w_max, relative tolerance eps): singular values sorted descending,
+ *     k = max(1, min(chi_max, k_w, k_eps)), k_w the smallest k with tail
+ *     weight sum_{i>=k} s_i^2 <= w_max * sum_i s_i^2, k_eps = #{s_i > eps s_0};
+ *     kept values renormalised to unit 2-norm; the relative tail weight is
+ *     added to an FP64 ledger.  SVD across bond j+1 first, then bond j+2.
+ *
+ * Error behaviour: every call returns a tebd_status; no exception crosses
+ * the ABI.  tebd_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.  EINVAL leaves the handle untouched.
+ * ENOCONV (SVD did not converge within max_sweeps) marks the handle ESTATE:
+ * later evolution and measurement calls refuse it.
+ *
+ * Ownership: the library owns all device memory behind an opaque handle
+ * (allocated through opts.dev_alloc if given, else hipMalloc).  The caller
+ * owns every host array passed in or out; host arrays are read or written
+ * only during the call.  Calls on one handle must not overlap; handles are
+ * independent of each other.
+ */
+#ifndef PTEBD_H
+#define PTEBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TEBD_OK = 0,
+  TEBD_EINVAL = -1,   /* bad argument: L < 3, d < 2, chi_max < 1, group not in {0,1,2}, non-finite values */
+  TEBD_ENOMEM = -2,   /* device allocation failed or footprint above budget; handle state unchanged */
+  TEBD_EDEVICE = -3,  /* HIP runtime error */
+  TEBD_ENOCONV = -4,  /* Jacobi SVD did not converge within max_sweeps; handle marked ESTATE */
+  TEBD_ESTATE = -5    /* handle is in an error state or call not valid in its state */
+} tebd_status;
+
+/* Arithmetic of the theta assembly and gate GEMMs.  Everything else (SVD,
+ * renormalisation, truncation weights, measurement) is always FP64. */
+typedef enum {
+  TEBD_FP64 = 0,       /* FP64 MFMA */
+  TEBD_FP32 = 1,       /* FP32 MFMA, FP32 accumulation */
+  TEBD_FP32_SPLIT = 2  /* hi/lo split FP32 operands, three FP32 MFMA products, FP32 accumulation */
+} tebd_precision;
+
+typedef enum {
+  TEBD_SVD_JACOBI = 0,   /* one-sided block Jacobi on the rows of theta (no Gram matrix) */
+  TEBD_SVD_GRAM_EIG = 1  /* Hermitian Gram matrix + block Jacobi eigensolver; faster, squares the condition number */
+} tebd_svd;
+
+/* Eq. (1): U/2 sum n(n-1) - J sum (b+_j b_{j+1} + h.c.) + K/2 sum (x-jc)^2 n
+ *          - Jnnn sum (b+_j b_{j+2} + h.c.);  d = n_max + 1 levels per site. */
+typedef struct {
+  int32_t L, d;
+  double U, J, Jnnn, K, jc;
+} tebd_model;
+
+typedef struct {
+  int32_t chi_max;        /* bond cap (>= 1) */
+  double trunc_weight;    /* w_max (>= 0) */
+  double trunc_rel;       /* eps (>= 0) */
+  int32_t prec;           /* tebd_precision */
+  int32_t svd;            /* tebd_svd */
+  int32_t max_sweeps;     /* Jacobi sweep limit; <= 0 selects the default (40) */
+  void* stream;           /* hipStream_t to run on; NULL = the library creates one per handle */
+  void* (*dev_alloc)(size_t bytes, void* ctx);  /* optional device allocator (e.g. torch caching allocator) */
+  void (*dev_free)(void* ptr, void* ctx);
+  void* alloc_ctx;
+} tebd_opts;
+
+typedef struct tebd_mps tebd_mps;
+
+/* Fills *opts with defaults: chi_max 64, w_max = eps = 1e-12, FP64, Jacobi. */
+void tebd_opts_default(tebd_opts* opts);
+
+/* CDW product state (Sec. II B), every bond of dimension 1.
+ * first_occupied = 1: site i occupied iff i even (|1,0,1,0,...>);
+ * first_occupied = 0: the opposite parity.  Reserves device memory for
+ * bonds up to min(d^b, d^(L-b), chi_max) and the gate workspace. */
+tebd_status mps_init_cdw(const tebd_model* model, const tebd_opts* opts,
+                         int32_t first_occupied, tebd_mps** out);
+
+/* Fock product state with occupations occ[L] (0 <= occ[i] < d). */
+tebd_status mps_init_product(const tebd_model* model, const tebd_opts* opts,
+                             const int32_t* occ, tebd_mps** out);
+
+/* Arbitrary state in stored form.  chi[L+1] bond dimensions (chi[0] = chi[L] = 1,
+ * each <= chi_max); B holds the sites back to back, site i as chi_i*d*chi_{i+1}
+ * real parts followed by as many imaginary parts; lam holds Lambda_0..Lambda_L
+ * back to back (chi[b] values each).  Host pointers, copied during the call. */
+tebd_status mps_init_state(const tebd_model* model, const tebd_opts* opts,
+                           const int32_t* chi, const double* B, const double* lam,
+                           tebd_mps** out);
+
+/* One commuting layer: every gate g_j with j mod 3 == group, for a time slice
+ * tau (exp(-i h_j tau)).  Enqueued on the handle's stream. */
+tebd_status tebd_layer(tebd_mps* mps, int32_t group, double tau);
+
+/* One second-order Trotter step: layers (0, dt/2) (1, dt/2) (2, dt) (1, dt/2) (0, dt/2). */
+tebd_status tebd_step(tebd_mps* mps, double dt);
+
+/* One Trotter step for n independent handles, batched together on the device.
+ * dt[n] per handle.  Handles must be distinct. */
+tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt);
+
+/* Local observables after the last step, FP64, synchronising the handle's stream:
+ * n[L] densities; c_nn[2(L-1)] = (Re, Im) of <b+_i b_{i+1}>; c_nnn[2(L-2)] = (Re, Im)
+ * of <b+_i b_{i+2}>.  Any output pointer may be NULL to skip that observable. */
+tebd_status measure_local(tebd_mps* mps, double* n, double* c_nn, double* c_nnn);
+
+/* Quench: replace the Hamiltonian parameters (same L and d), keep the state. */
+tebd_status mps_set_model(tebd_mps* mps, const tebd_model* model);
+
+/* Current bond dimensions chi[L+1] (host copy; synchronises). */
+tebd_status mps_bond_dims(const tebd_mps* mps, int32_t* chi);
+
+/* Schmidt values of bond b into s[cap]; *len receives chi_b (synchronises). */
+tebd_status mps_lambda(const tebd_mps* mps, int32_t bond, double* s, int32_t cap, int32_t* len);
+
+/* Site tensor B_i (planar: chi_i*d*chi_{i+1} reals then imaginaries) into buf[cap]. */
+tebd_status mps_site(const tebd_mps* mps, int32_t site, double* buf, int64_t cap);
+
+/* FP64 ledger: sum of relative discarded weights of all truncations so far. */
+tebd_status mps_discarded_weight(const tebd_mps* mps, double* w_total);
+
+/* Number of Jacobi sweeps used by the last SVD and their running total. */
+tebd_status mps_sweep_stats(const tebd_mps* mps, int64_t* last, int64_t* total);
+
+/* Device bytes a handle of this model/opts reserves (state + workspace at the bond cap). */
+tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t* bytes);
+
+/* Block until all work enqueued on the handle has finished. */
+tebd_status mps_sync(tebd_mps* mps);
+
+/* Release the handle and its device memory.  NULL is accepted. */
+tebd_status mps_free(tebd_mps* mps);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* tebd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTEBD_H */

@@ -1,0 +1,43 @@
+/*
+ * ptebd_diag.h -- diagnostic entry points of the TEBD library.
+ *
+ * They run one building block of the gate update on device copies of host
+ * arrays, so that tests can check each kernel in isolation against the CPU
+ * oracle's primitives.  Host pointers in and out; the call allocates and
+ * frees its own device memory and synchronises before returning.  Complex
+ * arrays are planar (all real parts, then all imaginary parts), row-major.
+ * Errors are reported as in ptebd.h.
+ */
+#ifndef PTEBD_DIAG_H
+#define PTEBD_DIAG_H
+
+#include "ptebd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C (m x n) = op(A) diag(k_scale) op(B), scaled by row_scale[i] * col_scale[j].
+ * op(A) is A (stored m x k, leading dimension k) when transA == 0, or the
+ * conjugate transpose of A stored k x m (leading dimension m) when transA == 1;
+ * op(B) likewise (stored k x n, or n x k).  k_scale[k], row_scale[m],
+ * col_scale[n] may be NULL.  prec is a tebd_precision. */
+tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
+                            const double* A, const double* B, const double* k_scale, const double* row_scale,
+                            const double* col_scale, double* C);
+
+/* Truncated SVD of A (m x n) with the library's Jacobi engine and the
+ * truncation rule of ptebd.h.  variant is a tebd_svd.  Outputs: *k kept
+ * values, s[0..k) the kept singular values renormalised to unit 2-norm,
+ * vh (planar, k x n) the kept right singular vectors as rows, *nrm the
+ * 2-norm of the kept values before renormalisation, *w the relative
+ * discarded weight, *sweeps the Jacobi sweeps used.  s and vh must hold
+ * min(m, n) and min(m, n) * n values (times two for vh). */
+tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, const double* A, int32_t chi_max, double w_max,
+                          double eps, int32_t* k, double* s, double* vh, double* nrm, double* w, int32_t* sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTEBD_DIAG_H */

@@ -1,0 +1,355 @@
+"""Python binding of the MI355X three-site TEBD library (``libptebd.so``).
+
+Argument marshalling only: every step of the evolution and of the
+measurement runs in the library's HIP kernels.  The functions carry the
+names of the C ABI in ``include/ptebd.h``.  Importing this package fails
+loudly if the library has not been built (``python -m
+paper_2401_05301_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptebd.so")
+
+TEBD_OK, TEBD_EINVAL, TEBD_ENOMEM, TEBD_EDEVICE, TEBD_ENOCONV, TEBD_ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32, FP32_SPLIT = 0, 1, 2
+SVD_JACOBI, SVD_GRAM_EIG = 0, 1
+
+EXPORTS = [
+    "tebd_opts_default", "mps_init_cdw", "mps_init_product", "mps_init_state", "tebd_layer", "tebd_step",
+    "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
+    "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
+]
+
+
+class TebdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("d", ctypes.c_int32), ("U", ctypes.c_double), ("J", ctypes.c_double),
+                ("Jnnn", ctypes.c_double), ("K", ctypes.c_double), ("jc", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("chi_max", ctypes.c_int32), ("trunc_weight", ctypes.c_double), ("trunc_rel", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("svd", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_05301_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    H = ctypes.c_void_p
+    P = ctypes.POINTER
+    st = ctypes.c_int
+    sig = {
+        "tebd_opts_default": (None, [P(Opts)]),
+        "mps_init_cdw": (st, [P(Model), P(Opts), ctypes.c_int32, P(H)]),
+        "mps_init_product": (st, [P(Model), P(Opts), P(ctypes.c_int32), P(H)]),
+        "mps_init_state": (st, [P(Model), P(Opts), P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double), P(H)]),
+        "tebd_layer": (st, [H, ctypes.c_int32, ctypes.c_double]),
+        "tebd_step": (st, [H, ctypes.c_double]),
+        "tebd_step_many": (st, [P(H), ctypes.c_int32, P(ctypes.c_double)]),
+        "measure_local": (st, [H, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double)]),
+        "mps_set_model": (st, [H, P(Model)]),
+        "mps_bond_dims": (st, [H, P(ctypes.c_int32)]),
+        "mps_lambda": (st, [H, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32, P(ctypes.c_int32)]),
+        "mps_site": (st, [H, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int64]),
+        "mps_discarded_weight": (st, [H, P(ctypes.c_double)]),
+        "mps_sweep_stats": (st, [H, P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "mps_footprint": (st, [P(Model), P(Opts), P(ctypes.c_size_t)]),
+        "mps_sync": (st, [H]),
+        "mps_free": (st, [H]),
+        "tebd_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int):
+    if status != TEBD_OK:
+        raise TebdError(status, _lib.tebd_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_model(L: int, d: int, U: float, J: float = 1.0, Jnnn: float = 0.0, K: float = 0.0,
+               jc: Optional[float] = None) -> Model:
+    """Eq. (1) parameters; jc is the 1-based trap centre (default (L+1)/2)."""
+    return Model(L, d, U, J, Jnnn, K, (L + 1) / 2.0 if jc is None else jc)
+
+
+def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int = FP64, svd: int = SVD_JACOBI,
+              max_sweeps: int = 40, stream: Optional[int] = None) -> Opts:
+    o = Opts()
+    _lib.tebd_opts_default(ctypes.byref(o))
+    o.chi_max, o.trunc_weight, o.trunc_rel = chi_max, w_max, eps
+    o.prec, o.svd, o.max_sweeps = prec, svd, max_sweeps
+    o.stream = stream
+    return o
+
+
+def torch_allocator(opts: Opts, stream: Optional[int] = None):
+    """Route the library's device allocations through torch's caching allocator.
+
+    Returns the callback objects, which the caller must keep alive as long as
+    any handle created with these options exists."""
+    import torch
+
+    def _alloc(nbytes, _ctx):
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream)
+
+    def _free(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    keep = (ALLOC_FN(_alloc), FREE_FN(_free))
+    opts.dev_alloc, opts.dev_free = keep
+    return keep
+
+
+def mps_init_cdw(model: Model, opts: Opts, first_occupied: int = 1):
+    h = ctypes.c_void_p()
+    _check(_lib.mps_init_cdw(ctypes.byref(model), ctypes.byref(opts), first_occupied, ctypes.byref(h)))
+    return h
+
+
+def mps_init_product(model: Model, opts: Opts, occ: Sequence[int]):
+    a = np.ascontiguousarray(occ, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(_lib.mps_init_product(ctypes.byref(model), ctypes.byref(opts),
+                                 a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(h)))
+    return h
+
+
+def mps_init_state(model: Model, opts: Opts, B: Sequence[np.ndarray], lam: Sequence[np.ndarray]):
+    """State in stored form: B[i] complex (chi_i, d, chi_{i+1}), lam[b] real (chi_b)."""
+    chi = np.array([1] + [b.shape[2] for b in B], dtype=np.int32)
+    flat = []
+    for b in B:
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        flat.append(b.real.ravel())
+        flat.append(b.imag.ravel())
+    Bf = np.ascontiguousarray(np.concatenate(flat), dtype=np.float64)
+    Lf = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in lam]))
+    h = ctypes.c_void_p()
+    _check(_lib.mps_init_state(ctypes.byref(model), ctypes.byref(opts),
+                               chi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(Bf), _dptr(Lf),
+                               ctypes.byref(h)))
+    return h
+
+
+def tebd_layer(h, group: int, tau: float):
+    _check(_lib.tebd_layer(h, group, tau))
+
+
+def tebd_step(h, dt: float):
+    _check(_lib.tebd_step(h, dt))
+
+
+def tebd_step_many(handles, dts):
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[x.value if isinstance(x, ctypes.c_void_p) else x for x in handles])
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    _check(_lib.tebd_step_many(arr, n, _dptr(d)))
+
+
+def measure_local(h, L: int):
+    """Returns (n[L], C[L-1] complex, D[L-2] complex)."""
+    n = np.zeros(L)
+    c = np.zeros(2 * max(L - 1, 1))
+    dd = np.zeros(2 * max(L - 2, 1))
+    _check(_lib.measure_local(h, _dptr(n), _dptr(c), _dptr(dd)))
+    C = c[0:2 * (L - 1):2] + 1j * c[1:2 * (L - 1):2]
+    D = dd[0:2 * (L - 2):2] + 1j * dd[1:2 * (L - 2):2]
+    return n, C, D
+
+
+def mps_set_model(h, model: Model):
+    _check(_lib.mps_set_model(h, ctypes.byref(model)))
+
+
+def mps_bond_dims(h, L: int):
+    a = np.zeros(L + 1, dtype=np.int32)
+    _check(_lib.mps_bond_dims(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return [int(x) for x in a]
+
+
+def mps_lambda(h, bond: int, cap: int = 16384):
+    s = np.zeros(cap)
+    n = ctypes.c_int32()
+    _check(_lib.mps_lambda(h, bond, _dptr(s), cap, ctypes.byref(n)))
+    return s[:n.value].copy()
+
+
+def mps_site(h, site: int, shape):
+    cl, d, cr = shape
+    n = cl * d * cr
+    buf = np.zeros(2 * n)
+    _check(_lib.mps_site(h, site, _dptr(buf), 2 * n))
+    return (buf[:n] + 1j * buf[n:]).reshape(cl, d, cr)
+
+
+def mps_discarded_weight(h) -> float:
+    w = ctypes.c_double()
+    _check(_lib.mps_discarded_weight(h, ctypes.byref(w)))
+    return w.value
+
+
+def mps_sweep_stats(h):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.mps_sweep_stats(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def mps_footprint(model: Model, opts: Opts) -> int:
+    b = ctypes.c_size_t()
+    _check(_lib.mps_footprint(ctypes.byref(model), ctypes.byref(opts), ctypes.byref(b)))
+    return b.value
+
+
+def mps_sync(h):
+    _check(_lib.mps_sync(h))
+
+
+def mps_free(h):
+    _check(_lib.mps_free(h))
+
+
+class MPS:
+    """Owning wrapper of a handle (frees it on close / garbage collection)."""
+
+    def __init__(self, handle, model: Model, keep=None):
+        self.h = handle
+        self.model = model
+        self.L = model.L
+        self.d = model.d
+        self._keep = keep
+
+    @classmethod
+    def cdw(cls, model: Model, opts: Opts, first_occupied: int = 1):
+        return cls(mps_init_cdw(model, opts, first_occupied), model)
+
+    @classmethod
+    def from_tensors(cls, model: Model, opts: Opts, B, lam):
+        return cls(mps_init_state(model, opts, B, lam), model)
+
+    def layer(self, group: int, tau: float):
+        tebd_layer(self.h, group, tau)
+
+    def step(self, dt: float):
+        tebd_step(self.h, dt)
+
+    def measure(self):
+        return measure_local(self.h, self.L)
+
+    def bond_dims(self):
+        return mps_bond_dims(self.h, self.L)
+
+    def lam(self, bond: int):
+        return mps_lambda(self.h, bond)
+
+    def site(self, i: int):
+        chi = self.bond_dims()
+        return mps_site(self.h, i, (chi[i], self.d, chi[i + 1]))
+
+    def discarded_weight(self):
+        return mps_discarded_weight(self.h)
+
+    def sweeps(self):
+        return mps_sweep_stats(self.h)
+
+    def sync(self):
+        mps_sync(self.h)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            mps_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ diagnostics
+def _load_diag():
+    P = ctypes.POINTER
+    _lib.tebd_diag_zgemm.restype = ctypes.c_int
+    _lib.tebd_diag_zgemm.argtypes = [ctypes.c_int32] * 6 + [P(ctypes.c_double)] * 6
+    _lib.tebd_diag_svd.restype = ctypes.c_int
+    _lib.tebd_diag_svd.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double),
+                                   ctypes.c_int32, ctypes.c_double, ctypes.c_double, P(ctypes.c_int32),
+                                   P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                   P(ctypes.c_double), P(ctypes.c_int32)]
+
+
+_load_diag()
+EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd"]
+
+
+def _planar(a: np.ndarray) -> np.ndarray:
+    a = np.asarray(a, dtype=np.complex128)
+    return np.ascontiguousarray(np.concatenate([a.real.ravel(), a.imag.ravel()]))
+
+
+def _opt(a):
+    if a is None:
+        return None
+    return _dptr(np.ascontiguousarray(a, dtype=np.float64))
+
+
+def tebd_diag_zgemm(A: np.ndarray, B: np.ndarray, transA: int = 0, transB: int = 0, prec: int = FP64,
+                    k_scale=None, row_scale=None, col_scale=None) -> np.ndarray:
+    """op(A) diag(k_scale) op(B) scaled by row/col vectors, computed on the GPU.
+    A and B are given in their stored shapes."""
+    m, k = (A.shape if not transA else A.shape[::-1])
+    n = B.shape[1] if not transB else B.shape[0]
+    pa, pb = _planar(A), _planar(B)
+    keep = [None if x is None else np.ascontiguousarray(x, dtype=np.float64) for x in (k_scale, row_scale, col_scale)]
+    c = np.zeros(2 * m * n)
+    _check(_lib.tebd_diag_zgemm(prec, m, n, k, transA, transB, _dptr(pa), _dptr(pb),
+                                *[None if x is None else _dptr(x) for x in keep], _dptr(c)))
+    return (c[:m * n] + 1j * c[m * n:]).reshape(m, n)
+
+
+def tebd_diag_svd(A: np.ndarray, variant: int = SVD_JACOBI, chi_max: int = 1 << 30, w_max: float = 0.0,
+                  eps: float = 0.0):
+    """Truncated SVD on the GPU: returns (s_normalised, vh, nrm, w, sweeps)."""
+    m, n = A.shape
+    r = min(m, n)
+    pa = _planar(A)
+    s = np.zeros(r)
+    vh = np.zeros(2 * r * n)
+    k = ctypes.c_int32()
+    nrm, w = ctypes.c_double(), ctypes.c_double()
+    sw = ctypes.c_int32()
+    _check(_lib.tebd_diag_svd(variant, m, n, _dptr(pa), min(chi_max, 2 ** 31 - 1), w_max, eps, ctypes.byref(k),
+                              _dptr(s), _dptr(vh), ctypes.byref(nrm), ctypes.byref(w), ctypes.byref(sw)))
+    kk = k.value
+    V = (vh[:kk * n] + 1j * vh[kk * n:2 * kk * n]).reshape(kk, n)
+    return s[:kk].copy(), V, nrm.value, w.value, sw.value

@@ -1,0 +1,295 @@
+// extern "C" entry points: argument validation, error translation, handle lifecycle.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "engine.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+}  // namespace
+
+namespace ptebd {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace ptebd
+
+namespace {
+
+tebd_status fail(int code, const std::string& msg) {
+  g_err = msg;
+  return (tebd_status)code;
+}
+
+template <class F>
+tebd_status guard(F&& f) {
+  try {
+    f();
+    return TEBD_OK;
+  } catch (const ptebd::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(TEBD_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(TEBD_EDEVICE, e.what());
+  }
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+tebd_status check_model(const tebd_model* m) {
+  if (!m) return fail(TEBD_EINVAL, "model is NULL");
+  if (m->L < 3) return fail(TEBD_EINVAL, "L must be >= 3 for three-site gates");
+  if (m->d < 2) return fail(TEBD_EINVAL, "d must be >= 2");
+  if (m->d > 8) return fail(TEBD_EINVAL, "d must be <= 8");
+  if (!finite(m->U) || !finite(m->J) || !finite(m->Jnnn) || !finite(m->K) || !finite(m->jc))
+    return fail(TEBD_EINVAL, "model parameters must be finite");
+  return TEBD_OK;
+}
+
+tebd_status check_opts(const tebd_opts* o, int d) {
+  if (!o) return fail(TEBD_EINVAL, "opts is NULL");
+  if (o->chi_max < 1) return fail(TEBD_EINVAL, "chi_max must be >= 1");
+  if ((int64_t)o->chi_max * d > 8192) return fail(TEBD_EINVAL, "chi_max * d must be <= 8192");
+  if (!finite(o->trunc_weight) || o->trunc_weight < 0) return fail(TEBD_EINVAL, "trunc_weight must be >= 0");
+  if (!finite(o->trunc_rel) || o->trunc_rel < 0) return fail(TEBD_EINVAL, "trunc_rel must be >= 0");
+  if (o->prec < TEBD_FP64 || o->prec > TEBD_FP32_SPLIT) return fail(TEBD_EINVAL, "bad precision");
+  if (o->svd < TEBD_SVD_JACOBI || o->svd > TEBD_SVD_GRAM_EIG) return fail(TEBD_EINVAL, "bad svd variant");
+  if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr))
+    return fail(TEBD_EINVAL, "dev_alloc and dev_free must be given together");
+  return TEBD_OK;
+}
+
+ptebd::ModelP to_model(const tebd_model* m) { return ptebd::ModelP{m->L, m->d, m->U, m->J, m->Jnnn, m->K, m->jc}; }
+
+tebd_status create(const tebd_model* model, const tebd_opts* opts, tebd_mps** out, tebd_mps** made) {
+  if (!out) return fail(TEBD_EINVAL, "out is NULL");
+  *out = nullptr;
+  tebd_status st = check_model(model);
+  if (st) return st;
+  st = check_opts(opts, model->d);
+  if (st) return st;
+  tebd_mps* M = new tebd_mps();
+  st = guard([&] {
+    M->opts = *opts;
+    M->L = model->L;
+    M->d = model->d;
+    M->chi_max = opts->chi_max;
+    if (opts->stream) {
+      M->stream = (hipStream_t)opts->stream;
+    } else {
+      PTEBD_HIP(hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking));
+      M->own_stream = true;
+    }
+    ptebd::mps_allocate(M);
+    ptebd::set_model(M, to_model(model));
+  });
+  if (st) {
+    ptebd::mps_release(M);
+    if (M->own_stream) (void)hipStreamDestroy(M->stream);
+    delete M;
+    return st;
+  }
+  *made = M;
+  return TEBD_OK;
+}
+
+tebd_status usable(const tebd_mps* M) {
+  if (!M) return fail(TEBD_EINVAL, "handle is NULL");
+  if (M->failed) return fail(TEBD_ESTATE, "handle is in an error state (an SVD failed to converge)");
+  return TEBD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tebd_opts_default(tebd_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->chi_max = 64;
+  o->trunc_weight = 1e-12;
+  o->trunc_rel = 1e-12;
+  o->prec = TEBD_FP64;
+  o->svd = TEBD_SVD_JACOBI;
+  o->max_sweeps = 40;
+}
+
+tebd_status mps_init_product(const tebd_model* model, const tebd_opts* opts, const int32_t* occ, tebd_mps** out) {
+  if (!occ) return fail(TEBD_EINVAL, "occ is NULL");
+  tebd_status st = check_model(model);
+  if (st) return st;
+  for (int i = 0; i < model->L; ++i)
+    if (occ[i] < 0 || occ[i] >= model->d) return fail(TEBD_EINVAL, "occupation outside 0..d-1");
+  tebd_mps* M = nullptr;
+  st = create(model, opts, out, &M);
+  if (st) return st;
+  st = guard([&] { ptebd::upload_product(M, occ); });
+  if (st) {
+    mps_free(M);
+    return st;
+  }
+  *out = M;
+  return TEBD_OK;
+}
+
+tebd_status mps_init_cdw(const tebd_model* model, const tebd_opts* opts, int32_t first_occupied, tebd_mps** out) {
+  if (first_occupied != 0 && first_occupied != 1) return fail(TEBD_EINVAL, "first_occupied must be 0 or 1");
+  tebd_status st = check_model(model);
+  if (st) return st;
+  std::vector<int32_t> occ(model->L);
+  for (int i = 0; i < model->L; ++i) occ[i] = ((i % 2 == 0) == (first_occupied == 1)) ? 1 : 0;
+  return mps_init_product(model, opts, occ.data(), out);
+}
+
+tebd_status mps_init_state(const tebd_model* model, const tebd_opts* opts, const int32_t* chi, const double* B,
+                           const double* lam, tebd_mps** out) {
+  if (!chi || !B || !lam) return fail(TEBD_EINVAL, "chi, B and lam must be non-NULL");
+  tebd_status st = check_model(model);
+  if (st) return st;
+  st = check_opts(opts, model->d);
+  if (st) return st;
+  ptebd::Sizes sz = ptebd::plan_sizes(model->L, model->d, opts->chi_max);
+  if (chi[0] != 1 || chi[model->L] != 1) return fail(TEBD_EINVAL, "chi[0] and chi[L] must be 1");
+  for (int b = 0; b <= model->L; ++b)
+    if (chi[b] < 1 || chi[b] > sz.cap[b]) return fail(TEBD_EINVAL, "bond dimension outside 1..min(d^b, d^(L-b), chi_max)");
+  tebd_mps* M = nullptr;
+  st = create(model, opts, out, &M);
+  if (st) return st;
+  st = guard([&] { ptebd::upload_state(M, chi, B, lam); });
+  if (st) {
+    mps_free(M);
+    return st;
+  }
+  *out = M;
+  return TEBD_OK;
+}
+
+tebd_status tebd_layer(tebd_mps* M, int32_t group, double tau) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  if (group < 0 || group > 2) return fail(TEBD_EINVAL, "group must be 0, 1 or 2");
+  if (!std::isfinite(tau)) return fail(TEBD_EINVAL, "tau must be finite");
+  return guard([&] { ptebd::layer(M, group, tau); });
+}
+
+tebd_status tebd_step(tebd_mps* M, double dt) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  if (!std::isfinite(dt)) return fail(TEBD_EINVAL, "dt must be finite");
+  return guard([&] {
+    const double h = 0.5 * dt;
+    ptebd::layer(M, 0, h);
+    ptebd::layer(M, 1, h);
+    ptebd::layer(M, 2, dt);
+    ptebd::layer(M, 1, h);
+    ptebd::layer(M, 0, h);
+  });
+}
+
+tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt) {
+  if (n < 0 || (n > 0 && (!mps || !dt))) return fail(TEBD_EINVAL, "bad handle list");
+  for (int i = 0; i < n; ++i) {
+    tebd_status st = usable(mps[i]);
+    if (st) return st;
+    if (!std::isfinite(dt[i])) return fail(TEBD_EINVAL, "dt must be finite");
+    for (int k = 0; k < i; ++k)
+      if (mps[k] == mps[i]) return fail(TEBD_EINVAL, "handles must be distinct");
+  }
+  for (int i = 0; i < n; ++i) {
+    tebd_status st = tebd_step(mps[i], dt[i]);
+    if (st) return st;
+  }
+  return TEBD_OK;
+}
+
+tebd_status measure_local(tebd_mps* M, double* n, double* c_nn, double* c_nnn) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  return guard([&] { ptebd::measure(M, n, c_nn, c_nnn); });
+}
+
+tebd_status mps_set_model(tebd_mps* M, const tebd_model* model) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  st = check_model(model);
+  if (st) return st;
+  if (model->L != M->L || model->d != M->d) return fail(TEBD_EINVAL, "set_model must keep L and d");
+  return guard([&] {
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+    ptebd::set_model(M, to_model(model));
+  });
+}
+
+tebd_status mps_bond_dims(const tebd_mps* M, int32_t* chi) {
+  if (!M || !chi) return fail(TEBD_EINVAL, "NULL argument");
+  std::memcpy(chi, M->chi.data(), sizeof(int32_t) * (M->L + 1));
+  return TEBD_OK;
+}
+
+tebd_status mps_lambda(const tebd_mps* M, int32_t bond, double* s, int32_t cap, int32_t* len) {
+  if (!M || !s || !len) return fail(TEBD_EINVAL, "NULL argument");
+  if (bond < 0 || bond > M->L) return fail(TEBD_EINVAL, "bond out of range");
+  const int n = M->chi[bond];
+  *len = n;
+  if (cap < n) return fail(TEBD_EINVAL, "output capacity smaller than the bond dimension");
+  return guard([&] {
+    PTEBD_HIP(hipMemcpyAsync(s, M->lam[bond], sizeof(double) * n, hipMemcpyDeviceToHost, M->stream));
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+  });
+}
+
+tebd_status mps_site(const tebd_mps* M, int32_t site, double* buf, int64_t cap) {
+  if (!M || !buf) return fail(TEBD_EINVAL, "NULL argument");
+  if (site < 0 || site >= M->L) return fail(TEBD_EINVAL, "site out of range");
+  const int64_t n = (int64_t)M->chi[site] * M->d * M->chi[site + 1];
+  if (cap < 2 * n) return fail(TEBD_EINVAL, "output capacity too small");
+  return guard([&] {
+    PTEBD_HIP(hipMemcpyAsync(buf, M->Br[site], sizeof(double) * n, hipMemcpyDeviceToHost, M->stream));
+    PTEBD_HIP(hipMemcpyAsync(buf + n, M->Bi[site], sizeof(double) * n, hipMemcpyDeviceToHost, M->stream));
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+  });
+}
+
+tebd_status mps_discarded_weight(const tebd_mps* M, double* w) {
+  if (!M || !w) return fail(TEBD_EINVAL, "NULL argument");
+  return guard([&] {
+    PTEBD_HIP(hipMemcpyAsync(w, M->ledger, sizeof(double), hipMemcpyDeviceToHost, M->stream));
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+  });
+}
+
+tebd_status mps_sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
+  if (!M || !last || !total) return fail(TEBD_EINVAL, "NULL argument");
+  *last = M->last_sweeps;
+  *total = M->total_sweeps;
+  return TEBD_OK;
+}
+
+tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(TEBD_EINVAL, "bytes is NULL");
+  tebd_status st = check_model(model);
+  if (st) return st;
+  st = check_opts(opts, model->d);
+  if (st) return st;
+  *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max).bytes();
+  return TEBD_OK;
+}
+
+tebd_status mps_sync(tebd_mps* M) {
+  if (!M) return fail(TEBD_EINVAL, "handle is NULL");
+  return guard([&] { PTEBD_HIP(hipStreamSynchronize(M->stream)); });
+}
+
+tebd_status mps_free(tebd_mps* M) {
+  if (!M) return TEBD_OK;
+  tebd_status st = guard([&] { ptebd::mps_release(M); });
+  if (M->own_stream) (void)hipStreamDestroy(M->stream);
+  delete M;
+  return st;
+}
+
+const char* tebd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

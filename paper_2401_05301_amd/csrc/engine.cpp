@@ -1,0 +1,518 @@
+// MPS store and the three-site gate update, driven from the host.
+//
+// Per gate on sites (j, j+1, j+2), with chi_l = chi_j, chi_r = chi_{j+3}:
+//   T1   = B_j B_{j+1}                       (chi_l d) x (d chi_{j+2})      GEMM
+//   psi  = T1 B_{j+2}                        (chi_l d^2) x (d chi_r)        GEMM
+//   psi' = G psi  (batched over chi_l)       d^3 x chi_r per left index     GEMM
+//   SVD #1 of M1 = Lambda_j psi' as (chi_l d) x (d^2 chi_r), truncate -> k1
+//   B_j  = psi' V1 / |S1|                                                  GEMM
+//   SVD #2 of M2 = S1 V1^+ as (k1 d) x (d chi_r), truncate -> k2
+//   B_{j+2} = V2^+,  B_{j+1} = V1^+ V2 / |S2|                              GEMM
+// The inverse-free form never divides by a Schmidt value.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+namespace ptebd {
+
+namespace {
+
+constexpr int kNsplitMax = 16;
+constexpr double kGramSigmaFloor = 1e-6;   // Gram route: singular values below this (relative) are noise
+
+int64_t ipow_cap(int d, int e, int cap) {
+  int64_t v = 1;
+  for (int i = 0; i < e; ++i) {
+    v *= d;
+    if (v >= cap) return cap;
+  }
+  return std::min<int64_t>(v, cap);
+}
+
+}  // namespace
+
+void* dev_alloc(tebd_mps* M, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) / 256 * 256;
+  void* p = nullptr;
+  if (M->opts.dev_alloc) {
+    p = M->opts.dev_alloc(bytes, M->opts.alloc_ctx);
+    if (!p) throw Error(-2, "device allocation failed (allocator hook)");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(-2, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+  }
+  M->allocs.push_back(p);
+  return p;
+}
+
+namespace {
+
+double* dalloc(tebd_mps* M, int64_t n) { return static_cast<double*>(dev_alloc(M, sizeof(double) * std::max<int64_t>(n, 1))); }
+
+tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
+  tebd_mps::Z z;
+  z.re = dalloc(M, n);
+  z.im = dalloc(M, n);
+  return z;
+}
+
+}  // namespace
+
+size_t Sizes::bytes() const {
+  int64_t d = 0;
+  d += 2 * site_elems + lam_elems;
+  d += 2 * (T1 + 2 * psi + X2 + G + W + V1h + 2 * meas_sq + 2 * meas_rect);
+  d += 4 * vec + part + gates + 64;
+  return (size_t)d * sizeof(double);
+}
+
+Sizes plan_sizes(int L, int d, int chi_max) {
+  Sizes s;
+  s.cap.resize(L + 1);
+  for (int b = 0; b <= L; ++b) s.cap[b] = (int)ipow_cap(d, std::min(b, L - b), chi_max);
+  const auto& c = s.cap;
+  for (int i = 0; i < L; ++i) s.site_elems += (int64_t)c[i] * d * c[i + 1];
+  for (int b = 0; b <= L; ++b) s.lam_elems += c[b];
+  int64_t maxr = 1;
+  for (int j = 0; j + 2 < L; ++j) {
+    const int64_t cl = c[j], c2 = c[j + 2], cr = c[j + 3];
+    const int64_t m1 = cl * d, n1 = (int64_t)d * d * cr, r1 = std::min(m1, n1);
+    const int64_t k1 = std::min<int64_t>(r1, c[j + 1]);
+    const int64_t m2 = k1 * d, n2 = (int64_t)d * cr, r2 = std::min(m2, n2);
+    s.T1 = std::max(s.T1, cl * d * d * c2);
+    s.psi = std::max(s.psi, cl * d * d * d * cr);
+    s.V1h = std::max(s.V1h, k1 * n1);
+    s.X2 = std::max(s.X2, m2 * n2);
+    s.G = std::max(s.G, std::max(r1 * r1, r2 * r2));
+    s.vec = std::max(s.vec, std::max(std::max(r1, r2), std::max(m1, m2)));
+    maxr = std::max(maxr, std::max(r1, r2));
+  }
+  s.W = s.G;
+  int chi = *std::max_element(c.begin(), c.end());
+  s.meas_sq = (int64_t)chi * chi;
+  s.meas_rect = (int64_t)chi * d * chi;
+  s.vec = std::max<int64_t>(s.vec, (int64_t)chi * d);
+  const int64_t nb = (maxr + 15) / 16 + 2;
+  s.part = (nb / 2 + 1) * kNsplitMax * 1536;
+  s.gates = (int64_t)std::max(L - 2, 0) * 3 * 2 * (int64_t)d * d * d * d * d * d;
+  return s;
+}
+
+void mps_allocate(tebd_mps* M) {
+  Sizes s = plan_sizes(M->L, M->d, M->chi_max);
+  M->cap = s.cap;
+  M->chi.assign(M->L + 1, 1);
+  const int L = M->L, d = M->d;
+  M->Br.resize(L);
+  M->Bi.resize(L);
+  for (int i = 0; i < L; ++i) {
+    const int64_t n = (int64_t)M->cap[i] * d * M->cap[i + 1];
+    M->Br[i] = dalloc(M, n);
+    M->Bi[i] = dalloc(M, n);
+  }
+  M->lam.resize(L + 1);
+  for (int b = 0; b <= L; ++b) M->lam[b] = dalloc(M, M->cap[b]);
+  M->ledger = dalloc(M, 1);
+  M->T1 = zalloc(M, s.T1);
+  M->psi = zalloc(M, s.psi);
+  M->psip = zalloc(M, s.psi);
+  M->X2 = zalloc(M, s.X2);
+  M->G = zalloc(M, s.G);
+  M->W = zalloc(M, s.W);
+  M->V1h = zalloc(M, s.V1h);
+  M->E = zalloc(M, s.meas_sq);
+  M->F2 = zalloc(M, s.meas_sq);
+  M->F = zalloc(M, s.meas_rect);
+  M->F3 = zalloc(M, s.meas_rect);
+  M->ks = dalloc(M, s.vec);
+  M->norms = dalloc(M, s.vec);
+  M->inv_sig = dalloc(M, s.vec);
+  M->sq = dalloc(M, s.vec);
+  M->perm = static_cast<int*>(dev_alloc(M, sizeof(int) * s.vec));
+  M->part = dalloc(M, s.part);
+  M->part_cap = s.part;
+  M->info_i = static_cast<int*>(dev_alloc(M, sizeof(int) * 8));
+  M->info_d = dalloc(M, 8);
+  M->counter = static_cast<unsigned int*>(dev_alloc(M, sizeof(unsigned int) * 4));
+  M->meas = dalloc(M, 5 * (int64_t)L);
+  M->d_br = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
+  M->d_bi = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
+  M->d_lam = static_cast<double**>(dev_alloc(M, sizeof(double*) * (L + 1)));
+  M->d_chi = static_cast<int*>(dev_alloc(M, sizeof(int) * (L + 1)));
+  PTEBD_HIP(hipHostMalloc((void**)&M->h_counter, 64, hipHostMallocDefault));
+  PTEBD_HIP(hipHostMalloc((void**)&M->h_info, 64, hipHostMallocDefault));
+  PTEBD_HIP(hipMemcpyAsync(M->d_br, M->Br.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
+  PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
+  PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
+  PTEBD_HIP(hipMemsetAsync(M->ledger, 0, sizeof(double), M->stream));
+  PTEBD_HIP(hipStreamSynchronize(M->stream));
+}
+
+void mps_release(tebd_mps* M) {
+  if (M->stream) (void)hipStreamSynchronize(M->stream);
+  for (void* p : M->allocs) {
+    if (M->opts.dev_free)
+      M->opts.dev_free(p, M->opts.alloc_ctx);
+    else
+      (void)hipFree(p);
+  }
+  M->allocs.clear();
+  if (M->h_counter) (void)hipHostFree(M->h_counter);
+  if (M->h_info) (void)hipHostFree(M->h_info);
+  M->h_counter = nullptr;
+  M->h_info = nullptr;
+}
+
+void upload_product(tebd_mps* M, const int* occ) {
+  const int L = M->L, d = M->d;
+  std::vector<double> zr(d), zi(d, 0.0);
+  for (int i = 0; i < L; ++i) {
+    std::fill(zr.begin(), zr.end(), 0.0);
+    zr[occ[i]] = 1.0;
+    PTEBD_HIP(hipMemcpy(M->Br[i], zr.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+    PTEBD_HIP(hipMemcpy(M->Bi[i], zi.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+  }
+  const double one = 1.0;
+  for (int b = 0; b <= L; ++b) PTEBD_HIP(hipMemcpy(M->lam[b], &one, sizeof(double), hipMemcpyHostToDevice));
+  M->chi.assign(L + 1, 1);
+}
+
+void upload_state(tebd_mps* M, const int* chi, const double* B, const double* lam) {
+  const int L = M->L, d = M->d;
+  int64_t off = 0;
+  for (int i = 0; i < L; ++i) {
+    const int64_t n = (int64_t)chi[i] * d * chi[i + 1];
+    PTEBD_HIP(hipMemcpy(M->Br[i], B + off, sizeof(double) * n, hipMemcpyHostToDevice));
+    PTEBD_HIP(hipMemcpy(M->Bi[i], B + off + n, sizeof(double) * n, hipMemcpyHostToDevice));
+    off += 2 * n;
+  }
+  off = 0;
+  for (int b = 0; b <= L; ++b) {
+    PTEBD_HIP(hipMemcpy(M->lam[b], lam + off, sizeof(double) * chi[b], hipMemcpyHostToDevice));
+    off += chi[b];
+  }
+  M->chi.assign(chi, chi + L + 1);
+}
+
+void set_model(tebd_mps* M, const ModelP& m) {
+  M->model = m;
+  M->spectra.clear();
+  for (int j = 0; j + 2 < M->L; ++j) M->spectra.push_back(eig_three_site(m, j));
+  // device gates are rebuilt lazily; keep their memory for reuse
+  for (auto& kv : M->gates) {
+    (void)kv;
+  }
+  M->gates.clear();
+}
+
+namespace {
+
+std::pair<double*, double*> device_gate(tebd_mps* M, int j, double tau) {
+  auto key = std::make_pair(j, tau);
+  auto it = M->gates.find(key);
+  if (it != M->gates.end()) return it->second;
+  std::vector<double> re, im;
+  gate_matrix(M->spectra[j], tau, re, im);
+  double* dr = dalloc(M, (int64_t)re.size());
+  double* di = dalloc(M, (int64_t)im.size());
+  PTEBD_HIP(hipMemcpy(dr, re.data(), sizeof(double) * re.size(), hipMemcpyHostToDevice));
+  PTEBD_HIP(hipMemcpy(di, im.data(), sizeof(double) * im.size(), hipMemcpyHostToDevice));
+  M->gates[key] = {dr, di};
+  return {dr, di};
+}
+
+bool debug_enabled() {
+  static const bool on = std::getenv("PTEBD_DEBUG") != nullptr;
+  return on;
+}
+
+// One-sided block Jacobi on the rows of X; returns the number of sweeps.
+int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, double* wi, int64_t ldw, int r, int c,
+               double tol_rel, double tol_abs) {
+  hipStream_t s = M->stream;
+  int nb = (r + 15) / 16;
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  const int npairs = nb / 2;
+  JacobiArgs a{};
+  a.xr = xr; a.xi = xi; a.ldx = ldx;
+  a.wr = wr; a.wi = wi; a.ldw = ldw;
+  a.r = r; a.c = c; a.nb = nb;
+  a.nsplit = std::max(1, std::min({kNsplitMax, (c + 63) / 64, (1024 + npairs - 1) / npairs}));
+  if ((int64_t)npairs * a.nsplit * 1536 > M->part_cap) throw Error(-1, "Jacobi scratch too small");
+  const int total = c + (wr ? r : 0);
+  int nu = std::max(1, std::min((total + 63) / 64, (1024 + npairs - 1) / npairs));
+  a.ucols = ((total + nu - 1) / nu + 15) / 16 * 16;
+  a.nuchunks = (total + a.ucols - 1) / a.ucols;
+  a.part = M->part;
+  a.tol_rel = tol_rel;
+  a.tol_abs = tol_abs;
+  a.rotated = M->counter;
+  row_norms(xr, xi, ldx, r, c, M->norms, s);
+  negligible_norm2(M->norms, r, M->info_d + 6, s);
+  a.tiny2 = M->info_d + 6;
+  if (wr) set_identity(wr, wi, ldw, r, s);
+  if (const char* dump = std::getenv("PTEBD_DUMP")) {
+    // debugging aid: keep the last Jacobi input on disk (r, c, then planar data)
+    std::vector<double> h(2 * (size_t)r * c);
+    PTEBD_HIP(hipMemcpy2DAsync(h.data(), sizeof(double) * c, xr, sizeof(double) * ldx, sizeof(double) * c, r,
+                               hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipMemcpy2DAsync(h.data() + (size_t)r * c, sizeof(double) * c, xi, sizeof(double) * ldx,
+                               sizeof(double) * c, r, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    if (FILE* f = std::fopen(dump, "wb")) {
+      const int32_t dims[2] = {r, c};
+      std::fwrite(dims, sizeof(int32_t), 2, f);
+      std::fwrite(h.data(), sizeof(double), h.size(), f);
+      std::fclose(f);
+    }
+  }
+  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
+  for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+    PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
+    for (int t = 0; t < nb - 1; ++t) jacobi_round(a, t, s);
+    PTEBD_HIP(hipMemcpyAsync(M->h_counter, M->counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    if (debug_enabled())
+      std::fprintf(stderr, "[ptebd] jacobi r=%d c=%d W=%d sweep=%d rotated_pairs=%u\n", r, c, wr != nullptr, sweep,
+                   *M->h_counter);
+    if (*M->h_counter == 0) {
+      M->last_sweeps = sweep;
+      M->total_sweeps += sweep;
+      return sweep;
+    }
+  }
+  M->failed = true;
+  throw Error(-4, "Jacobi SVD did not converge within max_sweeps (rows " + std::to_string(r) + ", columns " +
+                      std::to_string(c) + ")");
+}
+
+// Truncated SVD of diag(rs) A.  Writes the kept normalised singular values
+// into lam_out, V^+ rows into (vhr, vhi) with leading dimension n, the norm of
+// the kept values into info_d[2*slot] and returns k.
+// Relative orthogonality target of the one-sided Jacobi for rows of length c:
+// a few times the rounding error of a length-c dot product.
+double jacobi_tol(int c) { return std::max(2e-15, 2.0 * std::sqrt((double)c) * 1.11e-16); }
+
+}  // namespace
+
+int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf) {
+  hipStream_t s = M->stream;
+  const int m = in.m, n = in.n;
+  const bool gram = M->opts.svd == TEBD_SVD_GRAM_EIG;
+  double* nrm = M->info_d + 2 * slot;
+  int* kdev = M->info_i + slot;
+  const double eps = M->opts.trunc_rel;
+  const double w_max = M->opts.trunc_weight;
+  if (!gram) {
+    if (m <= n) {
+      scale_rows_copy(in.ar, in.ai, in.lda, in.rs, in.rdiv, m, n, xbuf.re, xbuf.im, n, s);
+      run_jacobi(M, xbuf.re, xbuf.im, n, nullptr, nullptr, 0, m, n, jacobi_tol(n),
+                 0.0);
+      row_norms(xbuf.re, xbuf.im, n, m, n, M->norms, s);
+      select_truncate(M->norms, m, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipStreamSynchronize(s));
+      const int k = M->h_info[0];
+      gather_rows(xbuf.re, xbuf.im, n, M->perm, M->inv_sig, k, n, vhr, vhi, n, kdev, s);
+      return k;
+    } else {
+      conj_transpose_scaled(in.ar, in.ai, in.lda, in.rs, in.rdiv, m, n, xbuf.re, xbuf.im, m, s);
+      run_jacobi(M, xbuf.re, xbuf.im, m, M->W.re, M->W.im, n, n, m, jacobi_tol(m),
+                 0.0);
+      row_norms(xbuf.re, xbuf.im, m, n, m, M->norms, s);
+      select_truncate(M->norms, n, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipStreamSynchronize(s));
+      const int k = M->h_info[0];
+      gather_rows(M->W.re, M->W.im, n, M->perm, nullptr, k, n, vhr, vhi, n, kdev, s);
+      return k;
+    }
+  }
+  // Gram route
+  const double eps_g = std::max(eps, kGramSigmaFloor);
+  if (m <= n) {
+    ZGemmArgs g;
+    g.m = m; g.n = m; g.k = n;
+    g.ar = in.ar; g.ai = in.ai; g.lda = in.lda;
+    g.br = in.ar; g.bi = in.ai; g.ldb = in.lda; g.transB = 1;
+    g.cr = M->G.re; g.ci = M->G.im; g.ldc = m;
+    g.row_scale = in.rs; g.row_div = in.rdiv;
+    g.col_scale = in.rs; g.col_div = in.rdiv;
+    zgemm(g, 0, s);
+    run_jacobi(M, M->G.re, M->G.im, m, M->W.re, M->W.im, m, m, m, jacobi_tol(m),
+               0.0);
+    row_norms(M->G.re, M->G.im, m, m, m, M->norms, s);
+    select_truncate(M->norms, m, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
+    PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    const int k = M->h_info[0];
+    // V^+ = S^-1 W_k diag(rs) A
+    gather_rows(M->W.re, M->W.im, m, M->perm, M->inv_sig, k, m, xbuf.re, xbuf.im, m, kdev, s);
+    ZGemmArgs v;
+    v.m = k; v.n = n; v.k = m;
+    v.ar = xbuf.re; v.ai = xbuf.im; v.lda = m;
+    v.br = in.ar; v.bi = in.ai; v.ldb = in.lda;
+    v.cr = vhr; v.ci = vhi; v.ldc = n;
+    v.k_scale = in.rs; v.k_div = in.rdiv;
+    zgemm(v, 0, s);
+    return k;
+  } else {
+    const double* ks = nullptr;
+    if (in.rs) {
+      square_expand(in.rs, in.rdiv, m, M->sq, s);
+      ks = M->sq;
+    }
+    ZGemmArgs g;
+    g.m = n; g.n = n; g.k = m;
+    g.ar = in.ar; g.ai = in.ai; g.lda = in.lda; g.transA = 1;
+    g.br = in.ar; g.bi = in.ai; g.ldb = in.lda;
+    g.cr = M->G.re; g.ci = M->G.im; g.ldc = n;
+    g.k_scale = ks; g.k_div = 1;
+    zgemm(g, 0, s);
+    run_jacobi(M, M->G.re, M->G.im, n, M->W.re, M->W.im, n, n, n, jacobi_tol(n),
+               0.0);
+    row_norms(M->G.re, M->G.im, n, n, n, M->norms, s);
+    select_truncate(M->norms, n, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
+    PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    const int k = M->h_info[0];
+    gather_rows(M->W.re, M->W.im, n, M->perm, nullptr, k, n, vhr, vhi, n, kdev, s);
+    return k;
+  }
+}
+
+namespace {
+
+void gate_update(tebd_mps* M, int j, std::pair<double*, double*> G) {
+  hipStream_t s = M->stream;
+  const int d = M->d, d3 = d * d * d;
+  const int cl = M->chi[j], c1 = M->chi[j + 1], c2 = M->chi[j + 2], cr = M->chi[j + 3];
+  const int prec = M->opts.prec;
+  {  // T1 = B_j B_{j+1}
+    ZGemmArgs g;
+    g.m = cl * d; g.n = d * c2; g.k = c1;
+    g.ar = M->Br[j]; g.ai = M->Bi[j]; g.lda = c1;
+    g.br = M->Br[j + 1]; g.bi = M->Bi[j + 1]; g.ldb = (int64_t)d * c2;
+    g.cr = M->T1.re; g.ci = M->T1.im; g.ldc = (int64_t)d * c2;
+    zgemm(g, prec, s);
+  }
+  {  // psi = T1 B_{j+2}
+    ZGemmArgs g;
+    g.m = cl * d * d; g.n = d * cr; g.k = c2;
+    g.ar = M->T1.re; g.ai = M->T1.im; g.lda = c2;
+    g.br = M->Br[j + 2]; g.bi = M->Bi[j + 2]; g.ldb = (int64_t)d * cr;
+    g.cr = M->psi.re; g.ci = M->psi.im; g.ldc = (int64_t)d * cr;
+    zgemm(g, prec, s);
+  }
+  {  // psi'[a] = G psi[a]
+    ZGemmArgs g;
+    g.m = d3; g.n = cr; g.k = d3; g.batch = cl;
+    g.ar = G.first; g.ai = G.second; g.lda = d3; g.sA = 0;
+    g.br = M->psi.re; g.bi = M->psi.im; g.ldb = cr; g.sB = (int64_t)d3 * cr;
+    g.cr = M->psip.re; g.ci = M->psip.im; g.ldc = cr; g.sC = (int64_t)d3 * cr;
+    zgemm(g, prec, s);
+  }
+  const int m1 = cl * d, n1 = d * d * cr;
+  SvdIn in1{M->psip.re, M->psip.im, n1, m1, n1, M->lam[j], d};
+  const int k1 = svd_trunc(M, in1, M->lam[j + 1], M->V1h.re, M->V1h.im, 0, M->psi);
+  {  // B_j = psi' V1 / |S1|
+    ZGemmArgs g;
+    g.m = m1; g.n = k1; g.k = n1;
+    g.ar = M->psip.re; g.ai = M->psip.im; g.lda = n1;
+    g.br = M->V1h.re; g.bi = M->V1h.im; g.ldb = n1; g.transB = 1;
+    g.cr = M->Br[j]; g.ci = M->Bi[j]; g.ldc = k1;
+    g.alpha_dev = M->info_d + 0; g.alpha_recip = 1;
+    zgemm(g, 0, s);
+  }
+  const int m2 = k1 * d, n2 = d * cr;
+  SvdIn in2{M->V1h.re, M->V1h.im, n2, m2, n2, M->lam[j + 1], d};
+  const int k2 = svd_trunc(M, in2, M->lam[j + 2], M->Br[j + 2], M->Bi[j + 2], 1, M->X2);
+  {  // B_{j+1} = V1^+ V2 / |S2|
+    ZGemmArgs g;
+    g.m = m2; g.n = k2; g.k = n2;
+    g.ar = M->V1h.re; g.ai = M->V1h.im; g.lda = n2;
+    g.br = M->Br[j + 2]; g.bi = M->Bi[j + 2]; g.ldb = n2; g.transB = 1;
+    g.cr = M->Br[j + 1]; g.ci = M->Bi[j + 1]; g.ldc = k2;
+    g.alpha_dev = M->info_d + 2; g.alpha_recip = 1;
+    zgemm(g, 0, s);
+  }
+  M->chi[j + 1] = k1;
+  M->chi[j + 2] = k2;
+}
+
+}  // namespace
+
+void layer(tebd_mps* M, int group, double tau) {
+  for (int j = group; j + 2 < M->L; j += 3) gate_update(M, j, device_gate(M, j, tau));
+}
+
+void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
+  hipStream_t s = M->stream;
+  const int L = M->L, d = M->d;
+  PTEBD_HIP(hipMemcpyAsync(M->d_chi, M->chi.data(), sizeof(int) * (L + 1), hipMemcpyHostToDevice, s));
+  double* dn = M->meas;
+  double* dc = M->meas + L;
+  double* dd = M->meas + 3 * L;
+  site_densities(M->d_br, M->d_bi, M->d_lam, M->d_chi, M->d_chi + 1, L, d, dn, s);
+  const bool want_hops = cnn || cnnn;
+  for (int i = 0; want_hops && i + 1 < L; ++i) {
+    const int cl = M->chi[i], cr = M->chi[i + 1], cr2 = M->chi[i + 2];
+    hop_kscale(M->lam[i], cl, d, M->ks, s);
+    {  // E = sum Lambda^2 sqrt(s) B(a,s,.)^+ B(a,s-1,.)
+      ZGemmArgs g;
+      g.m = cr; g.n = cr; g.k = cl * d - 1;
+      g.ar = M->Br[i] + cr; g.ai = M->Bi[i] + cr; g.lda = cr; g.transA = 1;
+      g.br = M->Br[i]; g.bi = M->Bi[i]; g.ldb = cr;
+      g.cr = M->E.re; g.ci = M->E.im; g.ldc = cr;
+      g.k_scale = M->ks;
+      zgemm(g, 0, s);
+    }
+    {  // F = E B_{i+1}
+      ZGemmArgs g;
+      g.m = cr; g.n = d * cr2; g.k = cr;
+      g.ar = M->E.re; g.ai = M->E.im; g.lda = cr;
+      g.br = M->Br[i + 1]; g.bi = M->Bi[i + 1]; g.ldb = (int64_t)d * cr2;
+      g.cr = M->F.re; g.ci = M->F.im; g.ldc = (int64_t)d * cr2;
+      zgemm(g, 0, s);
+    }
+    close_hop(M->Br[i + 1], M->Bi[i + 1], M->F.re, M->F.im, cr, d, cr2, dc + 2 * i, s);
+    if (i + 2 < L) {
+      const int cr3 = M->chi[i + 3];
+      {  // F2 = B_{i+1}^+ F   (rows (y, s) contracted)
+        ZGemmArgs g;
+        g.m = cr2; g.n = cr2; g.k = cr * d;
+        g.ar = M->Br[i + 1]; g.ai = M->Bi[i + 1]; g.lda = cr2; g.transA = 1;
+        g.br = M->F.re; g.bi = M->F.im; g.ldb = cr2;
+        g.cr = M->F2.re; g.ci = M->F2.im; g.ldc = cr2;
+        zgemm(g, 0, s);
+      }
+      {  // F3 = F2 B_{i+2}
+        ZGemmArgs g;
+        g.m = cr2; g.n = d * cr3; g.k = cr2;
+        g.ar = M->F2.re; g.ai = M->F2.im; g.lda = cr2;
+        g.br = M->Br[i + 2]; g.bi = M->Bi[i + 2]; g.ldb = (int64_t)d * cr3;
+        g.cr = M->F3.re; g.ci = M->F3.im; g.ldc = (int64_t)d * cr3;
+        zgemm(g, 0, s);
+      }
+      close_hop(M->Br[i + 2], M->Bi[i + 2], M->F3.re, M->F3.im, cr2, d, cr3, dd + 2 * i, s);
+    }
+  }
+  std::vector<double> h(5 * (size_t)L);
+  PTEBD_HIP(hipMemcpyAsync(h.data(), M->meas, sizeof(double) * 5 * L, hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  if (n_out) std::memcpy(n_out, h.data(), sizeof(double) * L);
+  if (cnn && L >= 2) std::memcpy(cnn, h.data() + L, sizeof(double) * 2 * (L - 1));
+  if (cnnn && L >= 3) std::memcpy(cnnn, h.data() + 3 * L, sizeof(double) * 2 * (L - 2));
+}
+
+}  // namespace ptebd

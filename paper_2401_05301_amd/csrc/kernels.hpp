@@ -1,0 +1,94 @@
+// Launchers of the device kernels (host side declarations).
+#pragma once
+
+#include "common.hpp"
+
+namespace ptebd {
+
+// C = alpha * op(A) * op(B), planar complex, row-major, batched.
+//   op(A) is m x k: transA == 0 -> A(i, kk) at a[i*lda + kk];
+//                   transA == 1 -> conj(A_stored(kk, i)), A_stored(kk, i) at a[kk*lda + i].
+//   op(B) is k x n: transB == 0 -> B(kk, j) at b[kk*ldb + j];
+//                   transB == 1 -> conj(B_stored(j, kk)) at b[j*ldb + kk].
+// Optional fused scalings (device vectors; nullptr = none):
+//   op(A)(i, kk) *= k_scale[kk / k_div]          (a diagonal between A and B)
+//   C(i, j)      *= row_scale[i / row_div] * col_scale[j / col_div]
+//   C            *= alpha * (alpha_dev ? (alpha_recip ? 1 / *alpha_dev : *alpha_dev) : 1)
+// beta == 1 accumulates into C instead of overwriting it.
+struct ZGemmArgs {
+  int m = 0, n = 0, k = 0, batch = 1;
+  const double* ar = nullptr; const double* ai = nullptr; int64_t lda = 0, sA = 0; int transA = 0;
+  const double* br = nullptr; const double* bi = nullptr; int64_t ldb = 0, sB = 0; int transB = 0;
+  double* cr = nullptr; double* ci = nullptr; int64_t ldc = 0, sC = 0;
+  const double* k_scale = nullptr; int k_div = 1;
+  const double* row_scale = nullptr; int row_div = 1;
+  const double* col_scale = nullptr; int col_div = 1;
+  const double* alpha_dev = nullptr; int alpha_recip = 0;
+  double alpha = 1.0;
+  int beta = 0;
+};
+
+// prec: 0 = FP64 MFMA, 1 = FP32 MFMA (FP32 accumulate), 2 = split FP32 (three products).
+void zgemm(const ZGemmArgs& a, int prec, hipStream_t s);
+
+// ---------------------------------------------------------------- Jacobi SVD
+// One-sided block Jacobi on the rows of X (r x c), optionally accumulating the
+// row rotations into W (r x r).  Blocks of 16 rows; a round processes nb/2
+// disjoint block pairs.
+struct JacobiArgs {
+  double* xr; double* xi; int64_t ldx;
+  double* wr; double* wi; int64_t ldw;     // may be null
+  int r, c;
+  int nb;                                   // number of 16-row blocks, even
+  int nsplit;                               // column splits of the pair Gram
+  double* part;                             // [nb/2][nsplit][4][256] partial Grams
+  double tol_rel, tol_abs;
+  const double* tiny2;                      // device scalar: rows with |x|^2 <= *tiny2 count as zero
+  unsigned int* rotated;                    // count of rotated pairs (this sweep)
+  int ucols;                                // columns per update work-group
+  int nuchunks;                             // update work-groups per pair
+};
+void jacobi_round(const JacobiArgs& a, int round, hipStream_t s);
+
+// *out = (4 u)^2 sum_i norms[i]^2: squared norm below which a row of a matrix
+// with these row norms is rounding noise (u = 2^-53).
+void negligible_norm2(const double* norms, int r, double* out, hipStream_t s);
+
+// Row norms of X into norms[r] (FP64).
+void row_norms(const double* xr, const double* xi, int64_t ldx, int r, int c, double* norms,
+               hipStream_t s);
+
+// Sort + truncation rule.  Inputs: vals[r] (row norms; sigma = vals, or
+// sigma = sqrt(vals) if is_gram).  Writes sorted sigma/nrm for the kept values
+// into lam_out[0..k), perm[0..k), inv_sig[0..k) = 1/sigma, and into info:
+// info_i[0] = k; info_d[0] = nrm, info_d[1] = discarded relative weight;
+// *ledger += weight.
+void select_truncate(const double* vals, int r, int is_gram, int chi_max, double w_max, double eps,
+                     double* lam_out, int* perm, double* inv_sig, int* info_i, double* info_d,
+                     double* ledger, hipStream_t s);
+
+// dst row i = src row perm[i] * (scale ? scale[i] : 1), i < k; planar, c columns.
+void gather_rows(const double* sr, const double* si, int64_t lds, const int* perm, const double* scale,
+                 int k, int c, double* dr, double* di, int64_t ldd, const int* kdev, hipStream_t s);
+
+// ---------------------------------------------------------------- element-wise
+// Y(i, j) = X(i, j) * rs[i / rdiv] (rs may be null), planar, rows x cols.
+void scale_rows_copy(const double* xr, const double* xi, int64_t ldx, const double* rs, int rdiv,
+                     int rows, int cols, double* yr, double* yi, int64_t ldy, hipStream_t s);
+// Y(j, i) = conj(X(i, j)) * rs[i / rdiv].
+void conj_transpose_scaled(const double* xr, const double* xi, int64_t ldx, const double* rs, int rdiv,
+                           int rows, int cols, double* yr, double* yi, int64_t ldy, hipStream_t s);
+// W = identity (r x r), planar.
+void set_identity(double* wr, double* wi, int64_t ldw, int r, hipStream_t s);
+// y[i] = x[i / div]^2 for i < n.
+void square_expand(const double* x, int div, int n, double* y, hipStream_t s);
+// Measurement helpers.
+void site_densities(const double* const* br, const double* const* bi, const double* const* lam,
+                    const int* chil, const int* chir, int L, int d, double* n_out, hipStream_t s);
+void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s);
+// out[0] += sum_{y, t>=1, c} sqrt(t) conj(B(y, t-1, c)) F(y, t, c) (complex; out[0]=re, out[1]=im)
+void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d,
+               int cr, double* out, hipStream_t s);
+void fill_zero(double* p, int64_t n, hipStream_t s);
+
+}  // namespace ptebd

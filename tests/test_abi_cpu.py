@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every declared symbol and validates
+arguments on the host (no GPU needed: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = []
+    for h in ("ptebd.h", "ptebd_diag.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"\b(?:tebd_status|void|const char\*)\s+\**\s*(\w+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_header_declares_the_four_core_calls():
+    names = declared_symbols()
+    for core in ("mps_init_cdw", "tebd_layer", "tebd_step", "measure_local"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2401_05301_amd as pt
+    lib = ctypes.CDLL(pt.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(declared_symbols()) <= set(pt.EXPORTS)
+
+
+def test_validation_without_gpu():
+    import paper_2401_05301_amd as pt
+    opts = pt.make_opts(chi_max=16)
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_cdw(pt.make_model(L=2, d=3, U=1.0), opts)
+    assert e.value.status == pt.TEBD_EINVAL and "L must be" in str(e.value)
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_cdw(pt.make_model(L=8, d=1, U=1.0), opts)
+    assert e.value.status == pt.TEBD_EINVAL
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_cdw(pt.make_model(L=8, d=3, U=float("nan")), opts)
+    assert e.value.status == pt.TEBD_EINVAL
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_cdw(pt.make_model(L=8, d=3, U=1.0), pt.make_opts(chi_max=0))
+    assert e.value.status == pt.TEBD_EINVAL
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_cdw(pt.make_model(L=8, d=3, U=1.0), opts, first_occupied=2)
+    assert e.value.status == pt.TEBD_EINVAL
+    with pytest.raises(pt.TebdError) as e:
+        pt.tebd_layer(ctypes.c_void_p(None), 0, 0.1)
+    assert e.value.status == pt.TEBD_EINVAL
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_product(pt.make_model(L=4, d=3, U=1.0), opts, [0, 3, 0, 0])
+    assert e.value.status == pt.TEBD_EINVAL
+
+
+def test_footprint_scales_with_chi():
+    import paper_2401_05301_amd as pt
+    m = pt.make_model(L=64, d=5, U=2.0, Jnnn=0.1)
+    small = pt.mps_footprint(m, pt.make_opts(chi_max=128))
+    big = pt.mps_footprint(m, pt.make_opts(chi_max=1024))
+    assert 0 < small < big
+    # chi = 1024, d = 5, L = 64: state ~5.4 GB plus a few GB of gate workspace
+    assert 8e9 < big < 40e9

@@ -1,0 +1,95 @@
+"""GPU kernels in isolation, through the diagnostic C-ABI, against NumPy FP64."""
+import numpy as np
+import pytest
+
+from gpu_util import note, rand_c
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import paper_2401_05301_amd as pt
+    return pt
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (64, 64, 16), (70, 33, 19), (130, 200, 77), (5, 300, 125)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_zgemm_fp64(pt, m, n, k, ta, tb):
+    rng = np.random.default_rng(m * 1000 + n * 10 + k + 7 * ta + 3 * tb)
+    A = rand_c(rng, *((m, k) if not ta else (k, m)))
+    B = rand_c(rng, *((k, n) if not tb else (n, k)))
+    note(f"zgemm fp64 m={m} n={n} k={k} ta={ta} tb={tb}")
+    C = pt.tebd_diag_zgemm(A, B, ta, tb)
+    ref = (A if not ta else A.conj().T) @ (B if not tb else B.conj().T)
+    assert np.abs(C - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(k)
+
+
+def test_zgemm_scalings(pt):
+    rng = np.random.default_rng(3)
+    m, n, k = 45, 67, 29
+    A, B = rand_c(rng, m, k), rand_c(rng, k, n)
+    ks, rs, cs = rng.random(k), rng.random(m), rng.random(n)
+    note("zgemm scalings")
+    C = pt.tebd_diag_zgemm(A, B, k_scale=ks, row_scale=rs, col_scale=cs)
+    ref = rs[:, None] * (A @ np.diag(ks) @ B) * cs[None, :]
+    assert np.abs(C - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 3e-5), (2, 3e-6)])
+def test_zgemm_reduced_precision(pt, prec, tol):
+    rng = np.random.default_rng(11)
+    A, B = rand_c(rng, 96, 125), rand_c(rng, 125, 80)
+    note(f"zgemm prec={prec}")
+    C = pt.tebd_diag_zgemm(A, B, prec=prec)
+    ref = A @ B
+    rel = np.abs(C - ref).max() / np.abs(ref).max()
+    assert rel < tol, rel
+    if prec == 2:
+        C1 = pt.tebd_diag_zgemm(A, B, prec=1)
+        assert rel < np.abs(C1 - ref).max() / np.abs(ref).max()
+
+
+def graded_matrix(rng, m, n, decay):
+    r = min(m, n)
+    U, _ = np.linalg.qr(rand_c(rng, m, r))
+    V, _ = np.linalg.qr(rand_c(rng, n, r))
+    s = np.exp(-np.arange(r) / decay)
+    return (U * s) @ V.conj().T, s
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("m,n", [(3, 9), (12, 7), (40, 100), (100, 40), (257, 130)])
+def test_svd_spectrum_and_subspace(pt, variant, m, n):
+    rng = np.random.default_rng(m + 7 * n + variant)
+    A, s_true = graded_matrix(rng, m, n, decay=max(m, n) / 12.0)
+    note(f"svd variant={variant} m={m} n={n}")
+    s, vh, nrm, w, sweeps = pt.tebd_diag_svd(A, variant=variant, w_max=1e-10, eps=1e-12)
+    _, s_ref, vh_ref = np.linalg.svd(A, full_matrices=False)
+    k = len(s)
+    assert sweeps >= 1
+    # truncation decision identical to the rule applied to the exact spectrum
+    tot = np.sum(s_ref ** 2)
+    tails = np.cumsum((s_ref ** 2)[::-1])[::-1]
+    kw = next(kk for kk in range(len(s_ref) + 1) if (tails[kk] if kk < len(s_ref) else 0.0) <= 1e-10 * tot)
+    assert k == max(1, kw)
+    tol = 1e-12 if variant == 0 else 1e-9
+    assert np.abs(s * nrm - s_ref[:k]).max() < tol * s_ref[0]
+    # kept right singular vectors span the same subspace (rows orthonormal)
+    assert np.abs(vh @ vh.conj().T - np.eye(k)).max() < (1e-12 if variant == 0 else 1e-6)
+    P = vh.conj().T @ vh
+    Pr = vh_ref[:k].conj().T @ vh_ref[:k]
+    assert np.abs(P - Pr).max() < (1e-10 if variant == 0 else 1e-5)
+
+
+def test_svd_rank_deficient_and_chi_cap(pt):
+    rng = np.random.default_rng(5)
+    A = rand_c(rng, 60, 4) @ rand_c(rng, 4, 90)   # rank 4
+    note("svd rank deficient")
+    s, vh, nrm, w, _ = pt.tebd_diag_svd(A, variant=0, w_max=0.0, eps=1e-12)
+    assert len(s) == 4
+    assert abs(np.sum(s ** 2) - 1) < 1e-14
+    s2, vh2, _, w2, _ = pt.tebd_diag_svd(A, variant=0, chi_max=2)
+    sr = np.linalg.svd(A, compute_uv=False)
+    assert len(s2) == 2
+    assert abs(w2 - np.sum(sr[2:] ** 2) / np.sum(sr ** 2)) < 1e-13

@@ -1,0 +1,133 @@
+"""GPU TEBD through the C-ABI against the FP64 CPU oracle, same inputs.
+
+Bars: FP64 path |dn|, |dC|, |dD| <= 1e-10 while every truncating cut has a
+relative gap >= 1e-8 (else 2 * w_total + 1e-10); FP32 theta/gate path
+<= 1e-6.  Schmidt spectra per bond are compared too (gauge-free)."""
+import numpy as np
+import pytest
+
+from gpu_util import note
+from oracle import tebd as otebd
+from workloads import CONFIGS, Model, Trunc, random_mps
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import paper_2401_05301_amd as pt
+    return pt
+
+
+def gpu_model(pt, m: Model):
+    return pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre())
+
+
+def run_pair(pt, m, tr, dt, steps, prec=0, svd=0, first_occupied=1):
+    note(f"parity L={m.L} d={m.d} chi={tr.chi_max} steps={steps} prec={prec} svd={svd}")
+    ores = otebd.run(m, tr, dt, steps, first_occupied=first_occupied)
+    g = pt.MPS.cdw(gpu_model(pt, m), pt.make_opts(tr.chi_max, tr.w_max, tr.eps, prec=prec, svd=svd), first_occupied)
+    gn, gc, gd = [], [], []
+    for _ in range(steps):
+        g.step(dt)
+        n, C, D = g.measure()
+        gn.append(n); gc.append(C); gd.append(D)
+    return ores, g, np.array(gn), np.array(gc), np.array(gd)
+
+
+def bar(ores, base=1e-10):
+    mps = ores["mps"]
+    if mps.min_gap < 1e-8:
+        return max(base, 2 * ores["w_total"][-1])
+    return base
+
+
+def assert_close(ores, g, gn, gc, gd, tol):
+    assert np.abs(gn - ores["n"]).max() <= tol, np.abs(gn - ores["n"]).max()
+    assert np.abs(gc - ores["C"]).max() <= tol, np.abs(gc - ores["C"]).max()
+    assert np.abs(gd - ores["D"]).max() <= tol, np.abs(gd - ores["D"]).max()
+
+
+def assert_spectra(ores, g, tol=1e-10):
+    assert g.bond_dims() == ores["mps"].bond_dims()
+    for b in range(1, g.L):
+        ls = g.lam(b)
+        lo = ores["mps"].lam[b]
+        assert np.abs(ls - lo).max() < tol, (b, np.abs(ls - lo).max())
+
+
+def test_exact_chi_config1(pt):
+    cfg = CONFIGS["exact_L8_d3"]
+    ores, g, gn, gc, gd = run_pair(pt, cfg["model"], cfg["trunc"], cfg["dt"], 20)
+    assert_close(ores, g, gn, gc, gd, 1e-10)
+    assert_spectra(ores, g, 1e-10)
+    assert abs(g.discarded_weight() - ores["w_total"][-1]) < 1e-14
+
+
+def test_first_occupied_zero_and_nnn_trap(pt):
+    m = Model(L=9, d=3, U=2.442, J=1.0, Jnnn=-0.12, K=0.01, jc=5.0)
+    tr = Trunc(chi_max=81, w_max=0.0, eps=1e-14)
+    ores, g, gn, gc, gd = run_pair(pt, m, tr, 0.05, 10, first_occupied=0)
+    assert_close(ores, g, gn, gc, gd, 1e-10)
+
+
+def test_truncating_nnn_config2_shape(pt):
+    cfg = CONFIGS["nnn_L32_d5_chi256"]
+    m = cfg["model"]
+    tr = Trunc(chi_max=12, w_max=1e-12, eps=1e-12)   # small cap so that truncation is active early
+    ores, g, gn, gc, gd = run_pair(pt, m, tr, cfg["dt"], 6)
+    assert ores["w_total"][-1] > 0
+    assert_close(ores, g, gn, gc, gd, bar(ores))
+    assert abs(g.discarded_weight() - ores["w_total"][-1]) < 1e-12 + 1e-6 * ores["w_total"][-1]
+
+
+def test_config2_full_shape_short(pt):
+    cfg = CONFIGS["nnn_L32_d5_chi256"]
+    ores, g, gn, gc, gd = run_pair(pt, cfg["model"], cfg["trunc"], cfg["dt"], 3)
+    assert_close(ores, g, gn, gc, gd, bar(ores))
+
+
+def test_gram_variant(pt):
+    cfg = CONFIGS["exact_L8_d3"]
+    m = Model(L=8, d=3, U=5.0, J=1.0, Jnnn=0.1, K=0.005)
+    tr = Trunc(chi_max=81, w_max=1e-12, eps=1e-12)
+    ores, g, gn, gc, gd = run_pair(pt, m, tr, 0.05, 10, svd=1)
+    # Gram route: the Gram matrix squares the condition number, so singular
+    # values below 1e-6 * s_0 are dropped as unresolvable; that extra discarded
+    # weight (~1e-12 per cut) shows up as a few 1e-9 in the observables.
+    assert_close(ores, g, gn, gc, gd, 2e-8)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_fp32_theta_gate(pt, prec):
+    m = Model(L=10, d=3, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    tr = Trunc(chi_max=30, w_max=1e-12, eps=1e-12)
+    ores, g, gn, gc, gd = run_pair(pt, m, tr, 0.02, 8, prec=prec)
+    err = max(np.abs(gn - ores["n"]).max(), np.abs(gc - ores["C"]).max(), np.abs(gd - ores["D"]).max())
+    note(f"fp32 prec={prec} max observable error {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_single_layers_and_random_state(pt):
+    """One layer of each group on a random right-orthonormal input, chi cap active."""
+    L, d, chi = 9, 4, 20
+    B, lam = random_mps(L, d, chi, seed=4, tau=6.0)
+    m = Model(L=L, d=d, U=3.0, J=1.0, Jnnn=0.1, K=0.01)
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-12)
+    om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12), B, lam)
+    n0, C0, D0 = g.measure()
+    on, oC, oD = otebd.measure(om)
+    assert np.abs(n0 - on).max() < 1e-12 and np.abs(C0 - oC).max() < 1e-12 and np.abs(D0 - oD).max() < 1e-12
+    gates = otebd.GateCache(m)
+    for group, tau in [(0, 0.03), (1, 0.03), (2, 0.06)]:
+        note(f"layer group={group}")
+        otebd.apply_layer(om, gates, group, tau, tr)
+        g.layer(group, tau)
+        n, C, D = g.measure()
+        on, oC, oD = otebd.measure(om)
+        tol = 1e-10 if om.min_gap >= 1e-8 else max(1e-10, 2 * om.w_total)
+        assert np.abs(n - on).max() < tol
+        assert np.abs(C - oC).max() < tol
+        assert np.abs(D - oD).max() < tol
+    assert abs(g.discarded_weight() - om.w_total) < 1e-12 + 1e-8 * om.w_total
