@@ -1,0 +1,192 @@
+#!/usr/bin/env python
+"""Three-site TEBD throughput on one MI355X: gate-updates/s at chi = 1024, d = 5.
+
+One timed "step" is one second-order Trotter step of the whole chain (five
+commuting layers, 104 three-site gate updates at L = 64) followed by the local
+measurement of n_i, <b+_i b_{i+1}> and <b+_i b_{i+2}>, on a synthetic state of
+the bulk chi = 1024 workload (L = 64, d = 5, U = 2, J_NNN = 0.1, K = 0,
+dt = 0.01).  The state, the gates and all workspace are resident in HBM before
+the timed region starts.  Prints one JSON line on stdout; progress on stderr.
+
+    python bench.py [--steps K] [--warmup W] [--svd gram|jacobi] [--prec fp64|fp32|split]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "3-site TEBD gate-updates/s at χ=1024,d=5 (MFMA roofline %); quench p50/p99"
+PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 matrix
+F_GU = 7.79e12        # algorithmic flops of one bulk gate update at chi = 1024, d = 5
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gate_updates_per_step(L: int) -> int:
+    layers = [(0, 0.5), (1, 0.5), (2, 1.0), (1, 0.5), (0, 0.5)]
+    return sum(len(range(g, L - 2, 3)) for g, _ in layers)
+
+
+def cpu_baseline(chi: int, L_ref: int, steps_scale: float):
+    """Time the FP64 CPU oracle on one bulk gate update at bond dimension chi
+    and scale its rate by (chi / 1024)^3 to the chi = 1024 unit."""
+    import numpy as np
+    from oracle import model as mdl
+    from oracle import tebd as otebd
+    from workloads import Model, Trunc, random_mps
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
+    except Exception:
+        threads = None
+    L = 14
+    B, lam = random_mps(L, 5, chi, seed=0, tau=110.0)
+    mps = otebd.MPS(B, lam)
+    m = Model(L=L, d=5, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    G = mdl.gate(m, 5, 0.005)
+    t0 = time.perf_counter()
+    otebd.apply_gate(mps, 5, G, Trunc(chi_max=chi))
+    dt = time.perf_counter() - t0
+    rate = (1.0 / dt) * (chi / 1024.0) ** 3
+    return {"value": rate, "unit": "gate-updates/s", "cores": threads or os.cpu_count(), "kind": "oracle",
+            "sample": (f"one bulk gate update (bonds {chi},{chi},{chi},{chi}, d=5) of the same Hamiltonian on a "
+                       f"random right-orthonormal L=14 chain took {dt:.1f} s; rate scaled by ({chi}/1024)^3 "
+                       f"to the chi=1024 unit")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--chi", type=int, default=1024)
+    ap.add_argument("--svd", choices=["gram", "jacobi"], default="gram")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "split"], default="fp64")
+    ap.add_argument("--tau", type=float, default=110.0, help="decay length of the synthetic Schmidt profile")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-canonicalize", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-chi", type=int, default=512)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build evolves one chain per GPU and has no multi-GPU path "
+              "(see the sharding design); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2401_05301_amd as pt
+    from workloads import CONFIGS, random_mps
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    cfg = CONFIGS["bulk_L64_chi1024"]
+    mdl = cfg["model"]
+    dt = cfg["dt"]
+    L, d, chi = args.L, mdl.d, args.chi
+    prec = {"fp64": pt.FP64, "fp32": pt.FP32, "split": pt.FP32_SPLIT}[args.prec]
+    svd = {"gram": pt.SVD_GRAM_EIG, "jacobi": pt.SVD_JACOBI}[args.svd]
+
+    t0 = time.perf_counter()
+    B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau)
+    log(f"synthetic input L={L} d={d} chi={chi} generated in {time.perf_counter() - t0:.1f} s")
+    model = pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre())
+    opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream)
+    keep = pt.torch_allocator(opts, stream=stream)
+    g = pt.MPS.from_tensors(model, opts, B, lam)
+    g._keep = keep
+    del B, lam
+    if not args.no_canonicalize:
+        t0 = time.perf_counter()
+        g.canonicalize()
+        g.sync()
+        log(f"canonicalised by an identity sweep in {time.perf_counter() - t0:.1f} s, bonds {g.bond_dims()}")
+    g.prepare(dt)
+    nsteps_gu = gate_updates_per_step(L)
+
+    for w in range(args.warmup):
+        g.step(dt)
+        g.measure()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+
+    w0 = g.discarded_weight()
+    g.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(args.steps):
+        g.step(dt)
+        n, C, D = g.measure()
+        log(f"timed step {k + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = e0.elapsed_time(e1)
+    prof = g.profile_read()
+    g.profile(False)
+    w1 = g.discarded_weight()
+    chis = g.bond_dims()
+
+    secs = dev_ms / 1e3
+    value = nsteps_gu * args.steps / secs
+    # dominant kernel by device time
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    gemm_ms, gemm_n, gemm_fl = prof["gemm_fp64"] if prec == pt.FP64 else prof["gemm_fp32"]
+    achieved = gemm_fl / (gemm_ms / 1e3) / 1e12 if gemm_ms > 0 else 0.0
+    peak = PEAK_FP64 if prec == pt.FP64 else 157.3
+    roof = {"bound": "mfma", "kernel": "zgemm_kernel<0>" if prec == pt.FP64 else "zgemm_kernel<fp32>",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "launches": gemm_n, "avg_launch_ms": gemm_ms / max(gemm_n, 1),
+            "flops_per_launch": gemm_fl / max(gemm_n, 1)}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "gate-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dev_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == pt.FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "bulk_L64_chi1024", "L": L, "d": d, "chi_max": chi, "U": mdl.U, "J": mdl.J,
+                   "Jnnn": mdl.Jnnn, "K": mdl.K, "dt": dt, "svd": args.svd, "theta_gate_prec": args.prec,
+                   "gate_updates_per_step": nsteps_gu, "w_max": 1e-12, "eps": 1e-12,
+                   "input": (f"random right-orthonormal MPS (seed {args.seed}), Schmidt profile exp(-k/{args.tau:g}), "
+                             + ("canonicalised by an identity sweep" if not args.no_canonicalize else "as generated"))},
+        "roofline": roof,
+        "path_roofline": {"unit_flops": F_GU, "achieved_TFLOPs": F_GU * value / 1e12, "peak": PEAK_FP64,
+                          "frac": F_GU * value / 1e12 / PEAK_FP64},
+        "wall_s": wall,
+        "kernel_ms": {k: v[0] for k, v in prof.items()},
+        "dominant_kernel_class": dom[0],
+        "discarded_weight_per_step": (w1 - w0) / args.steps,
+        "max_bond": max(chis),
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        log(f"timing the CPU oracle on one chi={args.cpu_chi} gate update")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_chi, L, 1.0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

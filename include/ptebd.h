@@ -154,6 +154,35 @@ tebd_status mps_sweep_stats(const tebd_mps* mps, int64_t* last, int64_t* total);
 /* Device bytes a handle of this model/opts reserves (state + workspace at the bond cap). */
 tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t* bytes);
 
+/* Build and upload the gates of a Strang step of size dt ahead of time, so
+ * that the step itself allocates and transfers nothing.  No state change. */
+tebd_status tebd_prepare(tebd_mps* mps, double dt);
+
+/* Canonical (Vidal) form of a state loaded with mps_init_state whose B
+ * tensors are right-orthonormal: identity gates are swept over j = 0..L-3, so
+ * that every bond receives its exact Schmidt values given the bond to its
+ * left (the handle's truncation settings apply). */
+tebd_status mps_canonicalize(tebd_mps* mps);
+
+/* Kernel classes timed by the profiler. */
+typedef enum {
+  TEBD_K_GEMM_FP64 = 0,   /* complex GEMM on FP64 MFMA (theta, gate, Gram, projections, updates, measurement) */
+  TEBD_K_GEMM_FP32 = 1,   /* complex GEMM on FP32 MFMA (FP32 and split-FP32 theta/gate) */
+  TEBD_K_HERM_EIG = 2,    /* two-sided Jacobi: 32 x 32 pair eigensolves */
+  TEBD_K_HERM_APPLY = 3,  /* two-sided Jacobi: block rotations of H and W */
+  TEBD_K_JAC_GRAM = 4,    /* one-sided Jacobi: pair Gram matrices */
+  TEBD_K_JAC_ROTATE = 5   /* one-sided Jacobi: pair eigensolve and row rotation */
+} tebd_kernel_class;
+
+/* enable != 0: clear previous records and time every later kernel launch of
+ * the handle with a pair of HIP events on its stream; 0: stop recording. */
+tebd_status mps_profile(tebd_mps* mps, int32_t enable);
+
+/* Totals over the recorded launches of one kernel class (synchronises):
+ * device milliseconds, number of launches and algorithmic flops (complex
+ * GEMM 8 m n k, Hermitian Gram products 4 m^2 k; 0 for the Jacobi kernels). */
+tebd_status mps_profile_read(tebd_mps* mps, int32_t kclass, double* ms, int64_t* launches, double* flops);
+
 /* Block until all work enqueued on the handle has finished. */
 tebd_status mps_sync(tebd_mps* mps);
 

@@ -36,6 +36,11 @@ tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32
 tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, const double* A, int32_t chi_max, double w_max,
                           double eps, int32_t* k, double* s, double* vh, double* nrm, double* w, int32_t* sweeps);
 
+/* Average device time (ms, HIP events) of `reps` launches of the complex GEMM
+ * kernel on device-resident m x k and k x n operands (contents unspecified,
+ * finite), C = A B. */
+tebd_status tebd_diag_zgemm_time(int32_t prec, int32_t m, int32_t n, int32_t k, int32_t reps, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ EXPORTS = [
     "tebd_opts_default", "mps_init_cdw", "mps_init_product", "mps_init_state", "tebd_layer", "tebd_step",
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
+    "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize",
 ]
+KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "herm_eig": 2, "herm_apply": 3, "jac_gram": 4, "jac_rotate": 5}
 
 
 class TebdError(RuntimeError):
@@ -52,7 +54,7 @@ class Opts(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_05301_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2401_05301_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     H = ctypes.c_void_p
     P = ctypes.POINTER
@@ -76,6 +78,10 @@ def _load():
         "mps_sync": (st, [H]),
         "mps_free": (st, [H]),
         "tebd_last_error": (ctypes.c_char_p, []),
+        "tebd_prepare": (st, [H, ctypes.c_double]),
+        "mps_canonicalize": (st, [H]),
+        "mps_profile": (st, [H, ctypes.c_int32]),
+        "mps_profile_read": (st, [H, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -230,6 +236,25 @@ def mps_footprint(model: Model, opts: Opts) -> int:
     return b.value
 
 
+def tebd_prepare(h, dt: float):
+    _check(_lib.tebd_prepare(h, dt))
+
+
+def mps_canonicalize(h):
+    _check(_lib.mps_canonicalize(h))
+
+
+def mps_profile(h, enable: bool):
+    _check(_lib.mps_profile(h, 1 if enable else 0))
+
+
+def mps_profile_read(h, kclass: int):
+    """(device ms, launches, algorithmic flops) of one kernel class."""
+    ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(_lib.mps_profile_read(h, kclass, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
+    return ms.value, n.value, fl.value
+
+
 def mps_sync(h):
     _check(_lib.mps_sync(h))
 
@@ -284,6 +309,18 @@ class MPS:
     def sync(self):
         mps_sync(self.h)
 
+    def canonicalize(self):
+        mps_canonicalize(self.h)
+
+    def prepare(self, dt: float):
+        tebd_prepare(self.h, dt)
+
+    def profile(self, enable: bool = True):
+        mps_profile(self.h, enable)
+
+    def profile_read(self):
+        return {name: mps_profile_read(self.h, k) for name, k in KERNEL_CLASSES.items()}
+
     def close(self):
         if self.h is not None and self.h.value:
             mps_free(self.h)
@@ -308,8 +345,19 @@ def _load_diag():
                                    P(ctypes.c_double), P(ctypes.c_int32)]
 
 
+    _lib.tebd_diag_zgemm_time.restype = ctypes.c_int
+    _lib.tebd_diag_zgemm_time.argtypes = [ctypes.c_int32] * 5 + [P(ctypes.c_double)]
+
+
 _load_diag()
-EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd"]
+EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time"]
+
+
+def tebd_diag_zgemm_time(m: int, n: int, k: int, prec: int = FP64, reps: int = 5) -> float:
+    """Average device milliseconds of one m x n x k complex GEMM launch."""
+    ms = ctypes.c_double()
+    _check(_lib.tebd_diag_zgemm_time(prec, m, n, k, reps, ctypes.byref(ms)))
+    return ms.value
 
 
 def _planar(a: np.ndarray) -> np.ndarray:

@@ -1,6 +1,6 @@
 """Build the gfx950 shared library ``libptebd.so`` in-tree with hipcc.
 
-    python -m paper_2401_05301_amd.build         # or build() from Python
+    python paper_2401_05301_amd/build.py         # or build() from Python
 
 Every source under ``csrc/`` is compiled for gfx950 only; objects go to
 ``_build/`` at the repository root and the library next to this file.

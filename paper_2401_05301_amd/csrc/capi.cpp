@@ -22,6 +22,13 @@ tebd_status fail(int code, const std::string& msg) {
   return (tebd_status)code;
 }
 
+// Routes the launchers' timing records to the handle's profiler for the
+// duration of one call.
+struct ProfBind {
+  ProfBind(tebd_mps* M) { ptebd::active_profiler() = (M && M->prof_on) ? &M->prof : nullptr; }
+  ~ProfBind() { ptebd::active_profiler() = nullptr; }
+};
+
 template <class F>
 tebd_status guard(F&& f) {
   try {
@@ -171,6 +178,7 @@ tebd_status tebd_layer(tebd_mps* M, int32_t group, double tau) {
   if (st) return st;
   if (group < 0 || group > 2) return fail(TEBD_EINVAL, "group must be 0, 1 or 2");
   if (!std::isfinite(tau)) return fail(TEBD_EINVAL, "tau must be finite");
+  ProfBind pb(M);
   return guard([&] { ptebd::layer(M, group, tau); });
 }
 
@@ -178,6 +186,7 @@ tebd_status tebd_step(tebd_mps* M, double dt) {
   tebd_status st = usable(M);
   if (st) return st;
   if (!std::isfinite(dt)) return fail(TEBD_EINVAL, "dt must be finite");
+  ProfBind pb(M);
   return guard([&] {
     const double h = 0.5 * dt;
     ptebd::layer(M, 0, h);
@@ -207,6 +216,7 @@ tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt) {
 tebd_status measure_local(tebd_mps* M, double* n, double* c_nn, double* c_nnn) {
   tebd_status st = usable(M);
   if (st) return st;
+  ProfBind pb(M);
   return guard([&] { ptebd::measure(M, n, c_nn, c_nnn); });
 }
 
@@ -275,6 +285,54 @@ tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t
   if (st) return st;
   *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max).bytes();
   return TEBD_OK;
+}
+
+tebd_status tebd_prepare(tebd_mps* M, double dt) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  if (!std::isfinite(dt)) return fail(TEBD_EINVAL, "dt must be finite");
+  return guard([&] {
+    ptebd::prepare_gates(M, 0, 0.5 * dt);
+    ptebd::prepare_gates(M, 1, 0.5 * dt);
+    ptebd::prepare_gates(M, 2, dt);
+  });
+}
+
+tebd_status mps_canonicalize(tebd_mps* M) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  ProfBind pb(M);
+  return guard([&] { ptebd::canonicalize(M); });
+}
+
+tebd_status mps_profile(tebd_mps* M, int32_t enable) {
+  if (!M) return fail(TEBD_EINVAL, "handle is NULL");
+  return guard([&] {
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+    M->prof.clear();
+    M->prof_on = enable != 0;
+  });
+}
+
+tebd_status mps_profile_read(tebd_mps* M, int32_t kclass, double* ms, int64_t* launches, double* flops) {
+  if (!M || !ms || !launches || !flops) return fail(TEBD_EINVAL, "NULL argument");
+  if (kclass < 0 || kclass >= ptebd::K_NCLASS) return fail(TEBD_EINVAL, "unknown kernel class");
+  return guard([&] {
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+    double t = 0.0, f = 0.0;
+    int64_t n = 0;
+    for (auto& r : M->prof.recs) {
+      if (r.cls != kclass) continue;
+      float e = 0.f;
+      PTEBD_HIP(hipEventElapsedTime(&e, r.a, r.b));
+      t += e;
+      f += r.flops;
+      ++n;
+    }
+    *ms = t;
+    *launches = n;
+    *flops = f;
+  });
 }
 
 tebd_status mps_sync(tebd_mps* M) {

@@ -86,16 +86,33 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     M.inv_sig = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));
     M.sq = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));
     M.perm = static_cast<int*>(ptebd::dev_alloc(&M, sizeof(int) * mx));
+    M.flags = static_cast<int*>(ptebd::dev_alloc(&M, sizeof(int) * mx));
+    const int sp = ptebd::subspace_width((int)r, chi_max);
+    if (variant == TEBD_SVD_GRAM_EIG && sp > 0) {
+      M.sub_p = sp;
+      M.sZ = z((int64_t)sp * r);
+      M.sY = z((int64_t)sp * r);
+      M.sZ2 = z((int64_t)sp * r);
+      M.sY2 = z((int64_t)sp * r);
+      M.sH = z((int64_t)sp * sp);
+      M.sW = z((int64_t)sp * sp);
+      M.nY = z((int64_t)sp * sp);
+      M.nZ = z((int64_t)sp * sp);
+      M.nY2 = z((int64_t)sp * sp);
+      M.nZ2 = z((int64_t)sp * sp);
+      M.ns_part = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * 256));
+    }
     const int64_t nbk = (r + 15) / 16 + 2;
     M.part_cap = (nbk / 2 + 1) * 16 * 1536;
     M.part = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * M.part_cap));
     M.info_i = static_cast<int*>(ptebd::dev_alloc(&M, sizeof(int) * 8));
-    M.info_d = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * 8));
+    M.info_d = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * 16));
     M.counter = static_cast<unsigned int*>(ptebd::dev_alloc(&M, 64));
     M.ledger = static_cast<double*>(ptebd::dev_alloc(&M, 64));
     double* lam_out = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * r));
     PTEBD_HIP(hipHostMalloc((void**)&M.h_counter, 64, hipHostMallocDefault));
     PTEBD_HIP(hipHostMalloc((void**)&M.h_info, 64, hipHostMallocDefault));
+    PTEBD_HIP(hipHostMalloc((void**)&M.h_part, 256 * sizeof(double), hipHostMallocDefault));
     PTEBD_HIP(hipMemcpy(a.re, A, sizeof(double) * m * n, hipMemcpyHostToDevice));
     PTEBD_HIP(hipMemcpy(a.im, A + (int64_t)m * n, sizeof(double) * m * n, hipMemcpyHostToDevice));
     PTEBD_HIP(hipMemset(M.ledger, 0, sizeof(double)));
@@ -118,6 +135,41 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     ptebd::set_last_error(e.what());
     ptebd::mps_release(&M);
     if (M.stream) (void)hipStreamDestroy(M.stream);
+    return (tebd_status)e.code;
+  }
+}
+
+extern "C" tebd_status tebd_diag_zgemm_time(int32_t prec, int32_t m, int32_t n, int32_t k, int32_t reps, double* ms) {
+  if (m < 1 || n < 1 || k < 1 || reps < 1 || !ms || prec < 0 || prec > 2) return TEBD_EINVAL;
+  try {
+    Scratch sc;
+    const int64_t na = (int64_t)m * k, nb = (int64_t)k * n, nc = (int64_t)m * n;
+    double* a = sc.alloc(2 * na);
+    double* b = sc.alloc(2 * nb);
+    double* c = sc.alloc(2 * nc);
+    ptebd::fill_zero(a, 2 * na, nullptr);
+    ptebd::fill_zero(b, 2 * nb, nullptr);
+    ptebd::ZGemmArgs g;
+    g.m = m; g.n = n; g.k = k;
+    g.ar = a; g.ai = a + na; g.lda = k;
+    g.br = b; g.bi = b + nb; g.ldb = n;
+    g.cr = c; g.ci = c + nc; g.ldc = n;
+    ptebd::zgemm(g, prec, nullptr);
+    hipEvent_t e0, e1;
+    PTEBD_HIP(hipEventCreate(&e0));
+    PTEBD_HIP(hipEventCreate(&e1));
+    PTEBD_HIP(hipEventRecord(e0, nullptr));
+    for (int i = 0; i < reps; ++i) ptebd::zgemm(g, prec, nullptr);
+    PTEBD_HIP(hipEventRecord(e1, nullptr));
+    PTEBD_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    PTEBD_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return TEBD_OK;
+  } catch (const ptebd::Error& e) {
+    ptebd::set_last_error(e.what());
     return (tebd_status)e.code;
   }
 }

@@ -129,7 +129,166 @@ __global__ __launch_bounds__(256) void close_hop_kernel(const double* br, const 
   }
 }
 
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  // splitmix64 finaliser
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+__global__ void fill_random_kernel(double* p, int64_t n, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t h = mix64(seed ^ mix64((uint64_t)i));
+    p[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void normalize_rows_kernel(double* xr, double* xi, int64_t ldx, int r, int c,
+                                                             double* norms) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= r) return;
+  double* pr = xr + (int64_t)row * ldx;
+  double* pi = xi + (int64_t)row * ldx;
+  double s = 0.0;
+  for (int j = lane; j < c; j += 64) s += pr[j] * pr[j] + pi[j] * pi[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  const double nrm = sqrt(s);
+  if (lane == 0 && norms) norms[row] = nrm;
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int j = lane; j < c; j += 64) {
+    pr[j] *= inv;
+    pi[j] *= inv;
+  }
+}
+
+__global__ __launch_bounds__(256) void inv_sqrt_clamped_kernel(const double* d, int n, double rel, double* out) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, d[i]);
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double floor = rel * sh[0];
+  for (int i = threadIdx.x; i < n; i += 256) out[i] = d[i] > floor ? 1.0 / sqrt(d[i]) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void tail_rest_kernel(const double* hr, int64_t ldh, int n, const double* vals,
+                                                        int p, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += hr[(int64_t)i * ldh + i];
+  for (int i = threadIdx.x; i < p; i += 256) acc -= vals[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = fmax(sh[0], 0.0);
+}
+
+__global__ __launch_bounds__(256) void gershgorin_kernel(const double* ar, const double* ai, int p, double* out) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < p; i += 256) {
+    double rs = 0.0;
+    for (int j = 0; j < p; ++j) rs += hypot(ar[(int64_t)i * p + j], ai[(int64_t)i * p + j]);
+    mx = fmax(mx, rs);
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double c = sh[0] > 0.0 ? sh[0] : 1.0;
+    out[0] = c;
+    out[1] = sqrt(c);
+  }
+}
+
+__global__ void ns_init_kernel(const double* ar, const double* ai, int p, const double* c, double* yr, double* yi,
+                               double* zr, double* zi) {
+  const double inv = 1.0 / c[0];
+  const int64_t n = (int64_t)p * p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    yr[e] = ar[e] * inv;
+    yi[e] = ai[e] * inv;
+    zr[e] = (e / p == e % p) ? 1.0 : 0.0;
+    zi[e] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void ns_three_minus_kernel(double* pr, double* pi, int p, double* dev) {
+  __shared__ double sh[256];
+  const int64_t n = (int64_t)p * p;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool dg = (e / p == e % p);
+    const double tr = (dg ? 1.5 : 0.0) - 0.5 * pr[e];
+    const double ti = -0.5 * pi[e];
+    const double dr = tr - (dg ? 1.0 : 0.0);
+    acc += dr * dr + ti * ti;
+    pr[e] = tr;
+    pi[e] = ti;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dev[blockIdx.x] = sh[0];   // per-block partial, summed in order by the host
+}
+
 }  // namespace
+
+void gershgorin(const double* ar, const double* ai, int p, double* out, hipStream_t s) {
+  gershgorin_kernel<<<1, 256, 0, s>>>(ar, ai, p, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void ns_init(const double* ar, const double* ai, int p, const double* c, double* yr, double* yi, double* zr,
+             double* zi, hipStream_t s) {
+  ns_init_kernel<<<std::min<int64_t>(((int64_t)p * p + 255) / 256, 2048), 256, 0, s>>>(ar, ai, p, c, yr, yi, zr, zi);
+  PTEBD_LAUNCH_CHECK();
+}
+
+int ns_three_minus(double* pr, double* pi, int p, double* dev, hipStream_t s) {
+  const int g = (int)std::min<int64_t>(((int64_t)p * p + 255) / 256, 256);
+  ns_three_minus_kernel<<<g, 256, 0, s>>>(pr, pi, p, dev);
+  PTEBD_LAUNCH_CHECK();
+  return g;
+}
+
+void fill_random(double* p, int64_t n, uint64_t seed, hipStream_t s) {
+  if (n <= 0) return;
+  fill_random_kernel<<<std::min<int64_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, n, seed);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void normalize_rows(double* xr, double* xi, int64_t ldx, int r, int c, double* norms, hipStream_t s) {
+  if (r <= 0) return;
+  normalize_rows_kernel<<<ceil_div(r, 4), 256, 0, s>>>(xr, xi, ldx, r, c, norms);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void inv_sqrt_clamped(const double* d, int n, double rel, double* out, hipStream_t s) {
+  inv_sqrt_clamped_kernel<<<1, 256, 0, s>>>(d, n, rel, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void tail_rest(const double* hr, int64_t ldh, int n, const double* vals, int p, double* out, hipStream_t s) {
+  tail_rest_kernel<<<1, 256, 0, s>>>(hr, ldh, n, vals, p, out);
+  PTEBD_LAUNCH_CHECK();
+}
 
 void scale_rows_copy(const double* xr, const double* xi, int64_t ldx, const double* rs, int rdiv, int rows, int cols,
                      double* yr, double* yi, int64_t ldy, hipStream_t s) {

@@ -71,8 +71,16 @@ size_t Sizes::bytes() const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems;
   d += 2 * (T1 + 2 * psi + X2 + G + W + V1h + 2 * meas_sq + 2 * meas_rect);
-  d += 4 * vec + part + gates + 64;
+  d += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
+  d += 5 * vec + part + gates + 64;
   return (size_t)d * sizeof(double);
+}
+
+int subspace_width(int r, int chi_max) {
+  const int keep = std::min(chi_max, r);
+  const int p = ((keep + std::max(64, keep / 4)) + 15) / 16 * 16;
+  // below ~1.5 p the whole Gram matrix is cheaper to diagonalise directly
+  return (3 * p < 2 * r) ? p : 0;
 }
 
 Sizes plan_sizes(int L, int d, int chi_max) {
@@ -95,6 +103,13 @@ Sizes plan_sizes(int L, int d, int chi_max) {
     s.G = std::max(s.G, std::max(r1 * r1, r2 * r2));
     s.vec = std::max(s.vec, std::max(std::max(r1, r2), std::max(m1, m2)));
     maxr = std::max(maxr, std::max(r1, r2));
+    for (int64_t r : {r1, r2}) {
+      const int64_t p = subspace_width((int)r, chi_max);
+      if (p > 0) {
+        s.sub_p = std::max(s.sub_p, p);
+        s.sub_r = std::max(s.sub_r, r);
+      }
+    }
   }
   s.W = s.G;
   int chi = *std::max_element(c.begin(), c.end());
@@ -138,10 +153,25 @@ void mps_allocate(tebd_mps* M) {
   M->inv_sig = dalloc(M, s.vec);
   M->sq = dalloc(M, s.vec);
   M->perm = static_cast<int*>(dev_alloc(M, sizeof(int) * s.vec));
+  M->flags = static_cast<int*>(dev_alloc(M, sizeof(int) * s.vec));
+  if (s.sub_p > 0 && M->opts.svd == TEBD_SVD_GRAM_EIG) {
+    M->sub_p = (int)s.sub_p;
+    M->sZ = zalloc(M, s.sub_p * s.sub_r);
+    M->sY = zalloc(M, s.sub_p * s.sub_r);
+    M->sZ2 = zalloc(M, s.sub_p * s.sub_r);
+    M->sY2 = zalloc(M, s.sub_p * s.sub_r);
+    M->sH = zalloc(M, s.sub_p * s.sub_p);
+    M->sW = zalloc(M, s.sub_p * s.sub_p);
+    M->nY = zalloc(M, s.sub_p * s.sub_p);
+    M->nZ = zalloc(M, s.sub_p * s.sub_p);
+    M->nY2 = zalloc(M, s.sub_p * s.sub_p);
+    M->nZ2 = zalloc(M, s.sub_p * s.sub_p);
+    M->ns_part = dalloc(M, 256);
+  }
   M->part = dalloc(M, s.part);
   M->part_cap = s.part;
   M->info_i = static_cast<int*>(dev_alloc(M, sizeof(int) * 8));
-  M->info_d = dalloc(M, 8);
+  M->info_d = dalloc(M, 16);
   M->counter = static_cast<unsigned int*>(dev_alloc(M, sizeof(unsigned int) * 4));
   M->meas = dalloc(M, 5 * (int64_t)L);
   M->d_br = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
@@ -150,6 +180,7 @@ void mps_allocate(tebd_mps* M) {
   M->d_chi = static_cast<int*>(dev_alloc(M, sizeof(int) * (L + 1)));
   PTEBD_HIP(hipHostMalloc((void**)&M->h_counter, 64, hipHostMallocDefault));
   PTEBD_HIP(hipHostMalloc((void**)&M->h_info, 64, hipHostMallocDefault));
+  PTEBD_HIP(hipHostMalloc((void**)&M->h_part, 256 * sizeof(double), hipHostMallocDefault));
   PTEBD_HIP(hipMemcpyAsync(M->d_br, M->Br.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
@@ -168,8 +199,10 @@ void mps_release(tebd_mps* M) {
   M->allocs.clear();
   if (M->h_counter) (void)hipHostFree(M->h_counter);
   if (M->h_info) (void)hipHostFree(M->h_info);
+  if (M->h_part) (void)hipHostFree(M->h_part);
   M->h_counter = nullptr;
   M->h_info = nullptr;
+  M->h_part = nullptr;
 }
 
 void upload_product(tebd_mps* M, const int* occ) {
@@ -299,6 +332,179 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
 // Truncated SVD of diag(rs) A.  Writes the kept normalised singular values
 // into lam_out, V^+ rows into (vhr, vhi) with leading dimension n, the norm of
 // the kept values into info_d[2*slot] and returns k.
+int inner_sweeps() {
+  static const int v = std::getenv("PTEBD_INNER_SWEEPS") ? std::atoi(std::getenv("PTEBD_INNER_SWEEPS")) : 2;
+  return v;
+}
+
+// Two-sided block Jacobi on the Hermitian H (n x n) in place, eigenvector rows
+// accumulated into W (set to the identity first).  Returns the sweeps used.
+int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, double* wr, double* wi, int64_t ldw) {
+  hipStream_t s = M->stream;
+  int nb = (n + 15) / 16;
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  const int npairs = nb / 2;
+  if ((int64_t)npairs * 2048 > M->part_cap) throw Error(-1, "Hermitian Jacobi scratch too small");
+  HermArgs a{};
+  a.hr = hr; a.hi = hi; a.ldh = ldh; a.n = n; a.nb = nb;
+  a.wr = wr; a.wi = wi; a.ldw = ldw;
+  a.wcols = 128;
+  a.wchunks = (n + a.wcols - 1) / a.wcols;
+  a.qbuf = M->part;
+  a.flag = M->flags;
+  a.inner_sweeps = inner_sweeps();
+  a.rotated = M->counter;
+  herm_tol(hr, hi, ldh, n, 32.0, M->info_d + 7, s);
+  a.tol_abs = M->info_d + 7;
+  if (wr) set_identity(wr, wi, ldw, n, s);
+  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
+  for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+    PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
+    for (int t = 0; t < nb - 1; ++t) herm_round(a, t, s);
+    PTEBD_HIP(hipMemcpyAsync(M->h_counter, M->counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    if (debug_enabled())
+      std::fprintf(stderr, "[ptebd] herm-jacobi n=%d sweep=%d rotated_pairs=%u\n", n, sweep, *M->h_counter);
+    if (*M->h_counter == 0) {
+      M->last_sweeps = sweep;
+      M->total_sweeps += sweep;
+      return sweep;
+    }
+  }
+  M->failed = true;
+  throw Error(-4, "Hermitian Jacobi did not converge within max_sweeps (n " + std::to_string(n) + ")");
+}
+
+// Symmetric (Loewdin) orthonormalisation of the rows of Z (p x r): rows are
+// normalised, then Z <- (Z Z^+)^{-1/2} Z.  Of all orthonormal bases of the row
+// space this one is closest to Z, so a basis that was already nearly
+// orthonormal (Ritz vectors and their images) keeps its alignment.  The
+// inverse square root of A = Z Z^+ comes from the coupled Newton-Schulz
+// iteration Y <- Y T, X <- T X, T = (3 I - X Y) / 2 started from Y = A / c,
+// X = I, with c >= lambda_max(A) (Gershgorin), so that X -> (A / c)^{-1/2}.
+void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r) {
+  hipStream_t s = M->stream;
+  normalize_rows(Z.re, Z.im, r, p, r, nullptr, s);
+  auto mm = [&](const tebd_mps::Z& A, const tebd_mps::Z& B, tebd_mps::Z& C) {
+    ZGemmArgs g;
+    g.m = p; g.n = p; g.k = p;
+    g.ar = A.re; g.ai = A.im; g.lda = p;
+    g.br = B.re; g.bi = B.im; g.ldb = p;
+    g.cr = C.re; g.ci = C.im; g.ldc = p;
+    zgemm(g, 0, s);
+  };
+  {
+    ZGemmArgs g;
+    g.m = p; g.n = p; g.k = r;
+    g.ar = Z.re; g.ai = Z.im; g.lda = r;
+    g.br = Z.re; g.bi = Z.im; g.ldb = r; g.transB = 1;
+    g.cr = M->sH.re; g.ci = M->sH.im; g.ldc = p;
+    zgemm(g, 0, s);
+  }
+  double* c = M->info_d + 8;   // c, sqrt(c)
+  gershgorin(M->sH.re, M->sH.im, p, c, s);
+  ns_init(M->sH.re, M->sH.im, p, c, M->nY.re, M->nY.im, M->nZ.re, M->nZ.im, s);
+  const double tol2 = 1e-28 * p;
+  int it = 0;
+  for (; it < 40; ++it) {
+    mm(M->nZ, M->nY, M->sW);                       // P = X Y
+    const int g = ns_three_minus(M->sW.re, M->sW.im, p, M->ns_part, s);   // T = (3I - P)/2
+    mm(M->nY, M->sW, M->nY2);                      // Y <- Y T
+    mm(M->sW, M->nZ, M->nZ2);                      // X <- T X
+    std::swap(M->nY, M->nY2);
+    std::swap(M->nZ, M->nZ2);
+    PTEBD_HIP(hipMemcpyAsync(M->h_part, M->ns_part, sizeof(double) * g, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    double dev = 0.0;
+    for (int b = 0; b < g; ++b) dev += M->h_part[b];
+    if (dev <= tol2) break;
+  }
+  if (debug_enabled()) std::fprintf(stderr, "[ptebd] lowdin p=%d newton-schulz iterations=%d\n", p, it + 1);
+  // Z <- A^{-1/2} Z = X Z / sqrt(c)
+  ZGemmArgs q;
+  q.m = p; q.n = r; q.k = p;
+  q.ar = M->nZ.re; q.ai = M->nZ.im; q.lda = p;
+  q.br = Z.re; q.bi = Z.im; q.ldb = r;
+  q.cr = T.re; q.ci = T.im; q.ldc = r;
+  q.alpha_dev = c + 1; q.alpha_recip = 1;
+  zgemm(q, 0, s);
+  std::swap(Z, T);
+}
+
+// Top-p eigenpairs of the Hermitian PSD G (r x r) by subspace iteration with
+// Rayleigh-Ritz.  On return sZ holds the Ritz vectors as rows (conjugated,
+// as W in run_herm_jacobi), M->norms the Ritz values, and info_d[5] the
+// weight of G outside the subspace (trace minus the Ritz values).
+void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w) {
+  hipStream_t s = M->stream;
+  fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
+  fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
+  if (w.kind == 1 && w.src_cols <= p && w.src_rows == r) {
+    conj_transpose_scaled(w.sr, w.si, w.ld, w.rs, w.rdiv, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
+  } else if (w.kind == 2 && w.src_rows <= p && w.src_cols == r) {
+    scale_rows_copy(w.sr, w.si, w.ld, nullptr, 1, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
+  }
+  lowdin(M, M->sZ, M->sZ2, p, r);
+  lowdin(M, M->sZ, M->sZ2, p, r);
+  // trace of G: scale of the rounding noise in the Ritz values
+  tail_rest(gr, r, r, M->norms, 0, M->info_d + 4, s);
+  double trace = 0.0;
+  PTEBD_HIP(hipMemcpyAsync(&trace, M->info_d + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  std::vector<double> prev(keep, 0.0), cur(keep, 0.0);
+  const int max_it = 30;
+  for (int it = 0; it < max_it; ++it) {
+    // Y = Z G (rows: (G z_i)^+), H = Y Z^+
+    ZGemmArgs g;
+    g.m = p; g.n = r; g.k = r;
+    g.ar = M->sZ.re; g.ai = M->sZ.im; g.lda = r;
+    g.br = gr; g.bi = gi; g.ldb = r;
+    g.cr = M->sY.re; g.ci = M->sY.im; g.ldc = r;
+    zgemm(g, 0, s);
+    ZGemmArgs h;
+    h.m = p; h.n = p; h.k = r;
+    h.ar = M->sY.re; h.ai = M->sY.im; h.lda = r;
+    h.br = M->sZ.re; h.bi = M->sZ.im; h.ldb = r; h.transB = 1;
+    h.cr = M->sH.re; h.ci = M->sH.im; h.ldc = p;
+    zgemm(h, 0, s);
+    run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p);
+    herm_diag(M->sH.re, p, p, M->norms, s);
+    // Ritz rotation of the basis and of its image
+    ZGemmArgs q;
+    q.m = p; q.n = r; q.k = p;
+    q.ar = M->sW.re; q.ai = M->sW.im; q.lda = p;
+    q.br = M->sZ.re; q.bi = M->sZ.im; q.ldb = r;
+    q.cr = M->sZ2.re; q.ci = M->sZ2.im; q.ldc = r;
+    zgemm(q, 0, s);
+    std::swap(M->sZ, M->sZ2);
+    q.br = M->sY.re; q.bi = M->sY.im;
+    q.cr = M->sY2.re; q.ci = M->sY2.im;
+    zgemm(q, 0, s);
+    std::swap(M->sY, M->sY2);
+    // convergence of the largest `keep` Ritz values
+    std::vector<double> h_vals(p);
+    PTEBD_HIP(hipMemcpyAsync(h_vals.data(), M->norms, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    std::sort(h_vals.begin(), h_vals.end(), std::greater<double>());
+    double delta = 0.0;
+    for (int i = 0; i < keep; ++i) {
+      cur[i] = h_vals[i];
+      delta = std::max(delta, std::fabs(cur[i] - prev[i]));
+    }
+    if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d delta=%.3e top=%.6e\n", r, p, it,
+                                      delta, h_vals[0]);
+    // a change of a kept Ritz value bounds the weight its vector can still
+    // move; stop at 1e-13 of the largest or at the rounding level of G
+    if (it >= 1 && delta <= 1e-13 * cur[0] + 128 * 1.1102230246251565e-16 * trace) break;
+    prev = cur;
+    // next basis: orthonormalised image of the Ritz vectors
+    std::swap(M->sZ, M->sY);
+    lowdin(M, M->sZ, M->sZ2, p, r);
+  }
+  tail_rest(gr, r, r, M->norms, p, M->info_d + 5, s);
+}
+
 // Relative orthogonality target of the one-sided Jacobi for rows of length c:
 // a few times the rounding error of a length-c dot product.
 double jacobi_tol(int c) { return std::max(2e-15, 2.0 * std::sqrt((double)c) * 1.11e-16); }
@@ -319,7 +525,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       run_jacobi(M, xbuf.re, xbuf.im, n, nullptr, nullptr, 0, m, n, jacobi_tol(n),
                  0.0);
       row_norms(xbuf.re, xbuf.im, n, m, n, M->norms, s);
-      select_truncate(M->norms, m, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
+      select_truncate(M->norms, m, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, nullptr, s);
       PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       const int k = M->h_info[0];
@@ -330,7 +536,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       run_jacobi(M, xbuf.re, xbuf.im, m, M->W.re, M->W.im, n, n, m, jacobi_tol(m),
                  0.0);
       row_norms(xbuf.re, xbuf.im, m, n, m, M->norms, s);
-      select_truncate(M->norms, n, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
+      select_truncate(M->norms, n, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, nullptr, s);
       PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       const int k = M->h_info[0];
@@ -338,9 +544,11 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       return k;
     }
   }
-  // Gram route
+  // Gram route: G = A_s A_s^+ (m <= n) or A_s^+ A_s (m > n), r x r
   const double eps_g = std::max(eps, kGramSigmaFloor);
-  if (m <= n) {
+  const int r = std::min(m, n);
+  const bool left = in.prefer_right ? (m < n) : (m <= n);
+  if (left) {
     ZGemmArgs g;
     g.m = m; g.n = m; g.k = n;
     g.ar = in.ar; g.ai = in.ai; g.lda = in.lda;
@@ -348,24 +556,8 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
     g.cr = M->G.re; g.ci = M->G.im; g.ldc = m;
     g.row_scale = in.rs; g.row_div = in.rdiv;
     g.col_scale = in.rs; g.col_div = in.rdiv;
+    g.herm_out = 1;
     zgemm(g, 0, s);
-    run_jacobi(M, M->G.re, M->G.im, m, M->W.re, M->W.im, m, m, m, jacobi_tol(m),
-               0.0);
-    row_norms(M->G.re, M->G.im, m, m, m, M->norms, s);
-    select_truncate(M->norms, m, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
-    PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    const int k = M->h_info[0];
-    // V^+ = S^-1 W_k diag(rs) A
-    gather_rows(M->W.re, M->W.im, m, M->perm, M->inv_sig, k, m, xbuf.re, xbuf.im, m, kdev, s);
-    ZGemmArgs v;
-    v.m = k; v.n = n; v.k = m;
-    v.ar = xbuf.re; v.ai = xbuf.im; v.lda = m;
-    v.br = in.ar; v.bi = in.ai; v.ldb = in.lda;
-    v.cr = vhr; v.ci = vhi; v.ldc = n;
-    v.k_scale = in.rs; v.k_div = in.rdiv;
-    zgemm(v, 0, s);
-    return k;
   } else {
     const double* ks = nullptr;
     if (in.rs) {
@@ -378,17 +570,48 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
     g.br = in.ar; g.bi = in.ai; g.ldb = in.lda;
     g.cr = M->G.re; g.ci = M->G.im; g.ldc = n;
     g.k_scale = ks; g.k_div = 1;
+    g.herm_out = 1;
     zgemm(g, 0, s);
-    run_jacobi(M, M->G.re, M->G.im, n, M->W.re, M->W.im, n, n, n, jacobi_tol(n),
-               0.0);
-    row_norms(M->G.re, M->G.im, n, n, n, M->norms, s);
-    select_truncate(M->norms, n, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, s);
-    PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    const int k = M->h_info[0];
-    gather_rows(M->W.re, M->W.im, n, M->perm, nullptr, k, n, vhr, vhi, n, kdev, s);
-    return k;
   }
+  // eigenvectors (conjugated, as rows) and eigenvalues of G
+  const double* rows_r;
+  const double* rows_i;
+  int nvals;
+  const double* extra = nullptr;
+  const int p = M->sub_p > 0 ? subspace_width(r, M->chi_max) : 0;
+  if (p > 0 && p <= M->sub_p) {
+    subspace_topk(M, M->G.re, M->G.im, r, p, std::min(M->chi_max, r), in.warm);
+    rows_r = M->sZ.re;
+    rows_i = M->sZ.im;
+    nvals = p;
+    extra = M->info_d + 5;
+  } else {
+    run_herm_jacobi(M, M->G.re, M->G.im, r, r, M->W.re, M->W.im, r);
+    herm_diag(M->G.re, r, r, M->norms, s);
+    rows_r = M->W.re;
+    rows_i = M->W.im;
+    nvals = r;
+  }
+  select_truncate(M->norms, nvals, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger,
+                  extra, s);
+  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  const int k = M->h_info[0];
+  if (left) {
+    // V^+ = S^-1 U_k^+ diag(rs) A
+    gather_rows(rows_r, rows_i, r, M->perm, M->inv_sig, k, m, xbuf.re, xbuf.im, m, kdev, s);
+    ZGemmArgs v;
+    v.m = k; v.n = n; v.k = m;
+    v.ar = xbuf.re; v.ai = xbuf.im; v.lda = m;
+    v.br = in.ar; v.bi = in.ai; v.ldb = in.lda;
+    v.cr = vhr; v.ci = vhi; v.ldc = n;
+    v.k_scale = in.rs; v.k_div = in.rdiv;
+    zgemm(v, 0, s);
+  } else {
+    // eigenvectors of A^+ A are the right singular vectors
+    gather_rows(rows_r, rows_i, r, M->perm, nullptr, k, n, vhr, vhi, n, kdev, s);
+  }
+  return k;
 }
 
 namespace {
@@ -424,6 +647,12 @@ void gate_update(tebd_mps* M, int j, std::pair<double*, double*> G) {
   }
   const int m1 = cl * d, n1 = d * d * cr;
   SvdIn in1{M->psip.re, M->psip.im, n1, m1, n1, M->lam[j], d};
+  // before the gate the left singular space of theta across bond j+1 is
+  // spanned by the columns of Lambda_j B_j
+  in1.warm.kind = 1;
+  in1.warm.sr = M->Br[j]; in1.warm.si = M->Bi[j]; in1.warm.ld = c1;
+  in1.warm.src_rows = m1; in1.warm.src_cols = c1;
+  in1.warm.rs = M->lam[j]; in1.warm.rdiv = d;
   const int k1 = svd_trunc(M, in1, M->lam[j + 1], M->V1h.re, M->V1h.im, 0, M->psi);
   {  // B_j = psi' V1 / |S1|
     ZGemmArgs g;
@@ -436,6 +665,12 @@ void gate_update(tebd_mps* M, int j, std::pair<double*, double*> G) {
   }
   const int m2 = k1 * d, n2 = d * cr;
   SvdIn in2{M->V1h.re, M->V1h.im, n2, m2, n2, M->lam[j + 1], d};
+  // before the gate the right singular space across bond j+2 is the row
+  // space of B_{j+2}
+  in2.prefer_right = true;
+  in2.warm.kind = 2;
+  in2.warm.sr = M->Br[j + 2]; in2.warm.si = M->Bi[j + 2]; in2.warm.ld = n2;
+  in2.warm.src_rows = c2; in2.warm.src_cols = n2;
   const int k2 = svd_trunc(M, in2, M->lam[j + 2], M->Br[j + 2], M->Bi[j + 2], 1, M->X2);
   {  // B_{j+1} = V1^+ V2 / |S2|
     ZGemmArgs g;
@@ -454,6 +689,16 @@ void gate_update(tebd_mps* M, int j, std::pair<double*, double*> G) {
 
 void layer(tebd_mps* M, int group, double tau) {
   for (int j = group; j + 2 < M->L; j += 3) gate_update(M, j, device_gate(M, j, tau));
+}
+
+void canonicalize(tebd_mps* M) {
+  // identity gates swept left to right: each exposes the exact Schmidt
+  // decomposition across its two inner bonds given the left Lambda
+  for (int j = 0; j + 2 < M->L; ++j) gate_update(M, j, device_gate(M, j, 0.0));
+}
+
+void prepare_gates(tebd_mps* M, int group, double tau) {
+  for (int j = group; j + 2 < M->L; j += 3) (void)device_gate(M, j, tau);
 }
 
 void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {

@@ -9,6 +9,7 @@
 #include "common.hpp"
 #include "gates.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 
 struct tebd_mps {
   ptebd::ModelP model{};
@@ -33,6 +34,12 @@ struct tebd_mps {
   // workspace (planar complex buffers: re, im)
   struct Z { double* re = nullptr; double* im = nullptr; };
   Z T1, psi, psip, X2, G, W, V1h;
+  Z sZ, sY, sZ2, sY2, sH, sW;   // subspace iteration: bases (p x r) and p x p blocks
+  Z nY, nZ, nY2, nZ2;           // Newton-Schulz iterates (p x p)
+  double* ns_part = nullptr;    // Newton-Schulz residual partial sums (256)
+  double* h_part = nullptr;     // pinned host mirror of ns_part
+  int sub_p = 0;                // subspace width reserved (0: not reserved)
+  int* flags = nullptr;         // per block pair flags of the Hermitian Jacobi
   Z E, F, F2, F3;
   double* ks = nullptr;
   double* norms = nullptr;
@@ -54,6 +61,9 @@ struct tebd_mps {
 
   bool failed = false;
   int64_t last_sweeps = 0, total_sweeps = 0;
+
+  ptebd::Profiler prof;   // kernel timings while profiling is enabled
+  bool prof_on = false;
 };
 
 namespace ptebd {
@@ -62,18 +72,39 @@ struct Sizes {
   std::vector<int> cap;
   int64_t site_elems = 0, lam_elems = 0;
   int64_t T1 = 0, psi = 0, X2 = 0, G = 0, W = 0, V1h = 0, meas_sq = 0, meas_rect = 0, vec = 0, part = 0;
+  int64_t sub_p = 0, sub_r = 0;   // subspace iteration width and row length
   int64_t gates = 0;
   size_t bytes() const;
 };
 
 Sizes plan_sizes(int L, int d, int chi_max);
+// Width of the subspace used for the top-k eigenpairs of an r x r Gram
+// matrix when keeping at most chi_max values (0: solve the whole matrix).
+int subspace_width(int r, int chi_max);
 void mps_allocate(tebd_mps* M);
 void mps_release(tebd_mps* M);
 void upload_product(tebd_mps* M, const int* occ);
 void upload_state(tebd_mps* M, const int* chi, const double* B, const double* lam);
 void set_model(tebd_mps* M, const ModelP& m);
 void layer(tebd_mps* M, int group, double tau);
+// Sweep of identity gates j = 0..L-3: brings a right-orthonormal state into
+// the canonical form with exact Schmidt values (up to truncation).
+void canonicalize(tebd_mps* M);
+// Build and upload the gates of the given group and time slice (no state change).
+void prepare_gates(tebd_mps* M, int group, double tau);
 void measure(tebd_mps* M, double* n, double* cnn, double* cnnn);
+
+// Starting rows for the subspace iteration of the Gram route: the singular
+// vectors of the state before the gate, on the side the Gram matrix lives on.
+struct WarmStart {
+  int kind = 0;                 // 0 none, 1 rows = conj((diag(rs) S)^T), 2 rows = S
+  const double* sr = nullptr;   // source S (src_rows x src_cols), leading dimension ld
+  const double* si = nullptr;
+  int64_t ld = 0;
+  int src_rows = 0, src_cols = 0;
+  const double* rs = nullptr;
+  int rdiv = 1;
+};
 
 struct SvdIn {
   const double* ar;
@@ -82,6 +113,8 @@ struct SvdIn {
   int m, n;
   const double* rs;   // row scale of the input (Lambda), may be null
   int rdiv;
+  bool prefer_right = false;   // Gram route: use A^+ A when n <= m (not only n < m)
+  WarmStart warm;
 };
 // Truncated SVD of diag(rs) A with the handle's settings (see engine.cpp).
 int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf);

@@ -12,6 +12,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace ptebd {
 
@@ -219,6 +220,10 @@ void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
   if (a.k <= 0) throw Error(-1, "zgemm: k must be positive");
   dim3 grid(ceil_div(a.n, BN), ceil_div(a.m, BM), a.batch);
   if (grid.y > 65535 || grid.z > 65535) throw Error(-1, "zgemm: grid too large");
+  // algorithmic work: a Hermitian Gram product counts as a rank-k update
+  const double flops = a.herm_out ? 4.0 * a.m * a.m * (double)a.k * a.batch
+                                  : 8.0 * a.m * (double)a.n * a.k * a.batch;
+  ProfScope ps(prec == 0 ? K_GEMM_FP64 : K_GEMM_FP32, flops, s);
   switch (prec) {
     case 0: zgemm_kernel<0><<<grid, 256, 0, s>>>(a); break;
     case 1: zgemm_kernel<1><<<grid, 256, 0, s>>>(a); break;

@@ -1,0 +1,366 @@
+// Two-sided block Jacobi eigensolver for a Hermitian matrix H (n x n, FP64).
+//
+// Used on Gram matrices, whose entries carry an absolute error of order
+// u * ||H||: rotations stop once every off-diagonal entry is below
+// tol_abs = c u ||H||_F, the accuracy the Gram matrix can support.  Blocks of
+// 16 rows/columns are paired round-robin; per round:
+//   herm_eig   : each pair's 32 x 32 diagonal block S = H[R, R] is
+//                diagonalised in LDS by cyclic rotations, S = Q D Q^+;
+//   herm_apply : every block pair (P1 >= P2) of the round is transformed,
+//                H[R1, R2] <- Q1^+ H[R1, R2] Q2 (mirrored to H[R2, R1]), and
+//                W[R, :] <- Q^+ W[R, :] accumulates the eigenvectors.
+// At convergence H is diagonal (eigenvalues) and W H0 W^+ = H, so the rows
+// of W are the conjugated eigenvectors.
+#include "kernels.hpp"
+#include "profile.hpp"
+
+namespace ptebd {
+
+namespace {
+
+constexpr int JB = 16;
+constexpr int PR = 32;
+
+__device__ __forceinline__ void round_pair(int nb, int t, int p, int& I, int& J) {
+  auto pos = [&](int i) { return i == 0 ? 0 : 1 + (i - 1 + t) % (nb - 1); };
+  int a = pos(p), b = pos(nb - 1 - p);
+  I = a < b ? a : b;
+  J = a < b ? b : a;
+}
+
+__device__ __forceinline__ int pidx(int I, int J, int k) { return k < JB ? I * JB + k : J * JB + (k - JB); }
+
+__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// row of accumulator element e of a 16x16 FP64 MFMA result held by `lane`
+__device__ __forceinline__ int acc_row(int lane, int e) { return (lane >> 4) + 4 * e; }
+
+// Cyclic Jacobi on the 32 x 32 Hermitian block in LDS (absolute threshold).
+// One step applies 16 disjoint rotations (round-robin pairs) as C <- J^+ C J
+// and Q <- Q J.  For the rotation of pair k = (p, q) the 2 x 2 block of J is
+//   [[cs, sn], [-sn e, cs e]],  e = conj(C_pq) / |C_pq|,
+// stored as cf[k] = (cs, sn, Re e, Im e).  The four entries of C at rows
+// (p_k, q_k) and columns (p_l, q_l) depend only on those same four entries,
+// so thread (k, l) updates its 2 x 2 block of C in place.
+__device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Qr)[PR + 1], double (*Qi)[PR + 1],
+                          double (*cf)[4], double thr, int max_sweeps) {
+  const int tid = threadIdx.x;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    int changed = 0;
+    for (int st = 0; st < PR - 1; ++st) {
+      auto member = [st](int k) { return k == 0 ? 0 : 1 + (k - 1 + st) % (PR - 1); };
+      if (tid < 16) {
+        const int a0 = member(tid), b0 = member(PR - 1 - tid);
+        const int p = min(a0, b0), q = max(a0, b0);
+        const double app = Cr[p][p], aqq = Cr[q][q];
+        const double cre = Cr[p][q], cim = Ci[p][q];
+        const double c = hypot(cre, cim);
+        double cs = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+        if (c > thr) {
+          const double tau = (aqq - app) / (2.0 * c);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          cs = 1.0 / sqrt(1.0 + t * t);
+          sn = t * cs;
+          er = cre / c;
+          ei = -cim / c;
+          changed = 1;
+        }
+        cf[tid][0] = cs; cf[tid][1] = sn; cf[tid][2] = er; cf[tid][3] = ei;
+      }
+      __syncthreads();
+      {
+        // C block (rows of pair k, columns of pair l)
+        const int k = tid >> 4, l = tid & 15;
+        const double ck = cf[k][0], sk = cf[k][1], cl = cf[l][0], sl = cf[l][1];
+        if (sk != 0.0 || sl != 0.0) {
+          const int a0 = member(k), a1 = member(PR - 1 - k), b0 = member(l), b1 = member(PR - 1 - l);
+          const int p = min(a0, a1), q = max(a0, a1), u = min(b0, b1), v = max(b0, b1);
+          // column transform (J on the right) with pair l: col u' = cl col u - sl e_l col v,
+          // col v' = sl col u + cl e_l col v
+          const double elr = cf[l][2], eli = cf[l][3];
+          double r0r[2], r0i[2], r1r[2], r1i[2];  // rows p, q after the column transform: [u', v']
+          {
+            const int rows[2] = {p, q};
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const int rr = rows[t];
+              const double ur = Cr[rr][u], ui = Ci[rr][u], vr = Cr[rr][v], vi = Ci[rr][v];
+              const double wr = elr * vr - eli * vi, wi = elr * vi + eli * vr;   // e_l * C[rr][v]
+              const double nur = cl * ur - sl * wr, nui = cl * ui - sl * wi;
+              const double nvr = sl * ur + cl * wr, nvi = sl * ui + cl * wi;
+              if (t == 0) { r0r[0] = nur; r0i[0] = nui; r0r[1] = nvr; r0i[1] = nvi; }
+              else { r1r[0] = nur; r1i[0] = nui; r1r[1] = nvr; r1i[1] = nvi; }
+            }
+          }
+          // row transform (J^+ on the left) with pair k: row p' = ck row p - sk conj(e_k) row q,
+          // row q' = sk row p + ck conj(e_k) row q
+          const double ekr = cf[k][2], eki = -cf[k][3];   // conj(e_k)
+          const int cols[2] = {u, v};
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const double pr_ = r0r[t], pi_ = r0i[t], qr_ = r1r[t], qi_ = r1i[t];
+            const double wr = ekr * qr_ - eki * qi_, wi = ekr * qi_ + eki * qr_;
+            Cr[p][cols[t]] = ck * pr_ - sk * wr;
+            Ci[p][cols[t]] = ck * pi_ - sk * wi;
+            Cr[q][cols[t]] = sk * pr_ + ck * wr;
+            Ci[q][cols[t]] = sk * pi_ + ck * wi;
+          }
+        }
+      }
+      // Q <- Q J: item (row r, pair l)
+      for (int e = tid; e < PR * 16; e += 256) {
+        const int r = e >> 4, l = e & 15;
+        const double cl = cf[l][0], sl = cf[l][1];
+        if (sl == 0.0) continue;
+        const int b0 = member(l), b1 = member(PR - 1 - l);
+        const int u = min(b0, b1), v = max(b0, b1);
+        const double elr = cf[l][2], eli = cf[l][3];
+        const double ur = Qr[r][u], ui = Qi[r][u], vr = Qr[r][v], vi = Qi[r][v];
+        const double wr = elr * vr - eli * vi, wi = elr * vi + eli * vr;
+        Qr[r][u] = cl * ur - sl * wr;
+        Qi[r][u] = cl * ui - sl * wi;
+        Qr[r][v] = sl * ur + cl * wr;
+        Qi[r][v] = sl * ui + cl * wi;
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(changed)) break;
+  }
+}
+
+// grid: nb/2 work-groups.  Writes Q of each pair (or flag 0 if the pair is
+// already diagonal to the threshold).
+__global__ __launch_bounds__(256) void herm_eig(HermArgs a, int round) {
+  __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
+  __shared__ double cf[16][4];
+  const int tid = threadIdx.x;
+  int I, J;
+  round_pair(a.nb, round, blockIdx.x, I, J);
+  for (int idx = tid; idx < PR * PR; idx += 256) {
+    const int p = idx / PR, q = idx % PR;
+    const int gp = pidx(I, J, p), gq = pidx(I, J, q);
+    const bool ok = gp < a.n && gq < a.n;
+    Cr[p][q] = ok ? a.hr[(int64_t)gp * a.ldh + gq] : 0.0;
+    Ci[p][q] = ok ? a.hi[(int64_t)gp * a.ldh + gq] : 0.0;
+    Qr[p][q] = (p == q) ? 1.0 : 0.0;
+    Qi[p][q] = 0.0;
+  }
+  __syncthreads();
+  const double thr = *a.tol_abs;
+  int need = 0;
+  for (int idx = tid; idx < PR * PR; idx += 256) {
+    const int p = idx / PR, q = idx % PR;
+    if (p < q && hypot(Cr[p][q], Ci[p][q]) > thr) need = 1;
+  }
+  double* qout = a.qbuf + (int64_t)blockIdx.x * 2 * PR * PR;
+  if (!__syncthreads_or(need)) {
+    if (tid == 0) a.flag[blockIdx.x] = 0;
+    return;
+  }
+  if (tid == 0) {
+    a.flag[blockIdx.x] = 1;
+    atomicAdd(a.rotated, 1u);
+  }
+  block_eig(Cr, Ci, Qr, Qi, cf, 0.5 * thr, a.inner_sweeps);
+  for (int idx = tid; idx < PR * PR; idx += 256) {
+    qout[idx] = Qr[idx / PR][idx % PR];
+    qout[PR * PR + idx] = Qi[idx / PR][idx % PR];
+  }
+}
+
+// grid.x = npairs*(npairs+1)/2 block-pair sandwiches, then npairs * wchunks
+// W-row updates.
+__global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
+  __shared__ double Ar[PR][PR + 1], Ai[PR][PR + 1], Tr[PR][PR + 1], Ti[PR][PR + 1];
+  __shared__ double Q1r[PR][PR + 1], Q1i[PR][PR + 1], Q2r[PR][PR + 1], Q2i[PR][PR + 1];
+  const int tid = threadIdx.x;
+  const int npairs = a.nb / 2;
+  const int nsand = npairs * (npairs + 1) / 2;
+  int bid = blockIdx.x;
+  const int round = a.round;
+  if (bid < nsand) {
+    // decode (P1, P2), P1 >= P2
+    int P1 = 0;
+    while ((P1 + 1) * (P1 + 2) / 2 <= bid) ++P1;
+    const int P2 = bid - P1 * (P1 + 1) / 2;
+    const int f1 = a.flag[P1], f2 = a.flag[P2];
+    if (!f1 && !f2) return;
+    int I1, J1, I2, J2;
+    round_pair(a.nb, round, P1, I1, J1);
+    round_pair(a.nb, round, P2, I2, J2);
+    const double* q1 = a.qbuf + (int64_t)P1 * 2 * PR * PR;
+    const double* q2 = a.qbuf + (int64_t)P2 * 2 * PR * PR;
+    for (int idx = tid; idx < PR * PR; idx += 256) {
+      const int p = idx / PR, q = idx % PR;
+      const int gp = pidx(I1, J1, p), gq = pidx(I2, J2, q);
+      const bool ok = gp < a.n && gq < a.n;
+      Ar[p][q] = ok ? a.hr[(int64_t)gp * a.ldh + gq] : 0.0;
+      Ai[p][q] = ok ? a.hi[(int64_t)gp * a.ldh + gq] : 0.0;
+      Q1r[p][q] = f1 ? q1[idx] : (p == q ? 1.0 : 0.0);
+      Q1i[p][q] = f1 ? q1[PR * PR + idx] : 0.0;
+      Q2r[p][q] = f2 ? q2[idx] : (p == q ? 1.0 : 0.0);
+      Q2i[p][q] = f2 ? q2[PR * PR + idx] : 0.0;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int tr = wave >> 1, tc = wave & 1;   // 16 x 16 output tile of this wave
+    // T = Q1^+ A : A operand Q1^+(row, k) = conj(Q1(k, row)), B operand A(k, col)
+    f64x4 accr = f64x4{0, 0, 0, 0}, acci = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int k = 4 * ks + (lane >> 4);
+      const int row = tr * 16 + (lane & 15), col = tc * 16 + (lane & 15);
+      const double xr = Q1r[k][row], xi = -Q1i[k][row];
+      const double yr = Ar[k][col], yi = Ai[k][col];
+      accr = mfma(xr, yr, accr);
+      accr = mfma(-xi, yi, accr);
+      acci = mfma(xr, yi, acci);
+      acci = mfma(xi, yr, acci);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      Tr[tr * 16 + acc_row(lane, e)][tc * 16 + (lane & 15)] = accr[e];
+      Ti[tr * 16 + acc_row(lane, e)][tc * 16 + (lane & 15)] = acci[e];
+    }
+    __syncthreads();
+    // out = T Q2
+    accr = f64x4{0, 0, 0, 0};
+    acci = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int k = 4 * ks + (lane >> 4);
+      const int row = tr * 16 + (lane & 15), col = tc * 16 + (lane & 15);
+      const double xr = Tr[row][k], xi = Ti[row][k];
+      const double yr = Q2r[k][col], yi = Q2i[k][col];
+      accr = mfma(xr, yr, accr);
+      accr = mfma(-xi, yi, accr);
+      acci = mfma(xr, yi, acci);
+      acci = mfma(xi, yr, acci);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int p = tr * 16 + acc_row(lane, e), q = tc * 16 + (lane & 15);
+      const int gp = pidx(I1, J1, p), gq = pidx(I2, J2, q);
+      double sr = accr[e], si = acci[e];
+      if (gp < a.n && gq < a.n) {
+        if (P1 == P2 && p == q) si = 0.0;   // keep the diagonal real
+        a.hr[(int64_t)gp * a.ldh + gq] = sr;
+        a.hi[(int64_t)gp * a.ldh + gq] = si;
+        if (P1 != P2) {
+          a.hr[(int64_t)gq * a.ldh + gp] = sr;
+          a.hi[(int64_t)gq * a.ldh + gp] = -si;
+        }
+      }
+    }
+    return;
+  }
+  // ---- W rows update: W[R, cols] <- Q^+ W[R, cols] on the matrix cores
+  bid -= nsand;
+  const int P = bid / a.wchunks, ch = bid % a.wchunks;
+  if (P >= npairs || !a.flag[P] || !a.wr) return;
+  int I, J;
+  round_pair(a.nb, round, P, I, J);
+  const double* q = a.qbuf + (int64_t)P * 2 * PR * PR;
+  const int lane = tid & 63, wave = tid >> 6;
+  // A operand Q^+(p, k) = conj(Q(k, p)); lane: p = lane%16 (+16 t), k = 4 ks + lane/16
+  double qar[2][8], qai[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int pp = t * 16 + (lane & 15), k = 4 * ks + (lane >> 4);
+      qar[t][ks] = q[k * PR + pp];
+      qai[t][ks] = -q[PR * PR + k * PR + pp];
+    }
+  const int cb = ch * a.wcols, ce = min(a.n, cb + a.wcols);
+  for (int j0 = cb + wave * 16; j0 < ce; j0 += 64) {
+    const int col = j0 + (lane & 15);
+    const bool okc = col < ce;
+    double xr[8], xi[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int row = pidx(I, J, 4 * ks + (lane >> 4));
+      const bool ok = okc && row < a.n;
+      xr[ks] = ok ? a.wr[(int64_t)row * a.ldw + col] : 0.0;
+      xi[ks] = ok ? a.wi[(int64_t)row * a.ldw + col] : 0.0;
+    }
+    f64x4 orr[2], oii[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      orr[t] = f64x4{0, 0, 0, 0};
+      oii[t] = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        orr[t] = mfma(qar[t][ks], xr[ks], orr[t]);
+        orr[t] = mfma(-qai[t][ks], xi[ks], orr[t]);
+        oii[t] = mfma(qar[t][ks], xi[ks], oii[t]);
+        oii[t] = mfma(qai[t][ks], xr[ks], oii[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = pidx(I, J, t * 16 + acc_row(lane, e));
+        if (okc && row < a.n) {
+          a.wr[(int64_t)row * a.ldw + col] = orr[t][e];
+          a.wi[(int64_t)row * a.ldw + col] = oii[t][e];
+        }
+      }
+  }
+}
+
+__global__ __launch_bounds__(256) void fro_tol_kernel(const double* hr, const double* hi, int64_t ldh, int n,
+                                                      double c, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) {
+    const int64_t i = e / n, j = e % n;
+    const double x = hr[i * ldh + j], y = hi[i * ldh + j];
+    acc += x * x + y * y;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = c * 1.1102230246251565e-16 * sqrt(sh[0]);
+}
+
+__global__ void diag_kernel(const double* hr, int64_t ldh, int n, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = hr[(int64_t)i * ldh + i];
+}
+
+}  // namespace
+
+void herm_tol(const double* hr, const double* hi, int64_t ldh, int n, double c, double* out, hipStream_t s) {
+  fro_tol_kernel<<<1, 256, 0, s>>>(hr, hi, ldh, n, c, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void herm_round(HermArgs a, int round, hipStream_t s) {
+  a.round = round;
+  const int npairs = a.nb / 2;
+  {
+    ProfScope ps(K_HERM_EIG, 0.0, s);
+    herm_eig<<<npairs, 256, 0, s>>>(a, round);
+    PTEBD_LAUNCH_CHECK();
+  }
+  const int nsand = npairs * (npairs + 1) / 2;
+  const int nw = a.wr ? npairs * a.wchunks : 0;
+  {
+    ProfScope ps(K_HERM_APPLY, 0.0, s);
+    herm_apply<<<nsand + nw, 256, 0, s>>>(a);
+    PTEBD_LAUNCH_CHECK();
+  }
+}
+
+void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s) {
+  diag_kernel<<<ceil_div(n, 256), 256, 0, s>>>(hr, ldh, n, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+}  // namespace ptebd

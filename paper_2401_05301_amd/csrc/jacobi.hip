@@ -12,6 +12,7 @@
 // At convergence the row norms of X are the singular values (or, when X is a
 // Gram matrix G, its eigenvalues) and W holds the accumulated unitary.
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace ptebd {
 
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const double* xr, const 
 __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, int npow2, int is_gram,
                                                      int chi_max, double w_max, double eps, double* lam_out,
                                                      int* perm, double* inv_sig, int* info_i, double* info_d,
-                                                     double* ledger) {
+                                                     double* ledger, const double* extra_tail) {
   extern __shared__ unsigned char smem[];
   double* key = reinterpret_cast<double*>(smem);
   int* idx = reinterpret_cast<int*>(key + npow2);
@@ -340,7 +341,8 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
     }
   }
   if (threadIdx.x == 0) {
-    double total = 0.0;
+    const double extra = extra_tail ? fmax(extra_tail[0], 0.0) : 0.0;
+    double total = extra;
     for (int i = 0; i < r; ++i) total += key[i] * key[i];
     int k;
     double tail_k = 0.0;
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
       tail_k = 0.0;
     } else {
       // k_w: smallest k with sum_{i>=k} s_i^2 <= w_max * total
-      double acc = 0.0;
+      double acc = extra;
       int kw = r;
       // tails accumulated from the smallest value upwards
       // (walk down while the tail stays within the tolerance)
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
       k = min(min(chi_max, kw), ke);
       if (k < 1) k = 1;
       if (k > r) k = r;
-      tail_k = 0.0;
+      tail_k = extra;
       for (int i = r - 1; i >= k; --i) tail_k += key[i] * key[i];
     }
     double kept = 0.0;
@@ -426,11 +428,17 @@ __global__ void gather_kernel(const double* sr, const double* si, int64_t lds, c
 
 void jacobi_round(const JacobiArgs& a, int round, hipStream_t s) {
   dim3 g1(a.nb / 2, a.nsplit);
-  jac_gram<<<g1, 256, 0, s>>>(a, round);
-  PTEBD_LAUNCH_CHECK();
+  {
+    ProfScope ps(K_JAC_GRAM, 0.0, s);
+    jac_gram<<<g1, 256, 0, s>>>(a, round);
+    PTEBD_LAUNCH_CHECK();
+  }
   dim3 g2(a.nb / 2, a.nuchunks);
-  jac_rotate<<<g2, 256, 0, s>>>(a, round);
-  PTEBD_LAUNCH_CHECK();
+  {
+    ProfScope ps(K_JAC_ROTATE, 0.0, s);
+    jac_rotate<<<g2, 256, 0, s>>>(a, round);
+    PTEBD_LAUNCH_CHECK();
+  }
 }
 
 void negligible_norm2(const double* norms, int r, double* out, hipStream_t s) {
@@ -445,7 +453,7 @@ void row_norms(const double* xr, const double* xi, int64_t ldx, int r, int c, do
 
 void select_truncate(const double* vals, int r, int is_gram, int chi_max, double w_max, double eps,
                      double* lam_out, int* perm, double* inv_sig, int* info_i, double* info_d, double* ledger,
-                     hipStream_t s) {
+                     const double* extra_tail, hipStream_t s) {
   int np2 = 1;
   while (np2 < r) np2 <<= 1;
   const size_t shm = (size_t)np2 * (sizeof(double) + sizeof(int));
@@ -458,7 +466,7 @@ void select_truncate(const double* vals, int r, int is_gram, int chi_max, double
     attr = true;
   }
   select_kernel<<<1, 256, shm, s>>>(vals, r, np2, is_gram, chi_max, w_max, eps, lam_out, perm, inv_sig, info_i,
-                                    info_d, ledger);
+                                    info_d, ledger, extra_tail);
   PTEBD_LAUNCH_CHECK();
 }
 

@@ -26,6 +26,7 @@ struct ZGemmArgs {
   const double* alpha_dev = nullptr; int alpha_recip = 0;
   double alpha = 1.0;
   int beta = 0;
+  int herm_out = 0;   // C = X X^+ (Hermitian): accounted as 4 m^2 k flops
 };
 
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (FP32 accumulate), 2 = split FP32 (three products).
@@ -50,6 +51,35 @@ struct JacobiArgs {
 };
 void jacobi_round(const JacobiArgs& a, int round, hipStream_t s);
 
+// ------------------------------------------------- two-sided Hermitian Jacobi
+struct HermArgs {
+  double* hr; double* hi; int64_t ldh;      // H (n x n), overwritten towards diagonal
+  int n, nb;                                // nb: 16-blocks, even
+  double* wr; double* wi; int64_t ldw;      // eigenvector rows (n x n) or null
+  int wcols, wchunks;                       // column chunking of the W update
+  double* qbuf;                             // [nb/2][2][32*32] pair rotations
+  int* flag;                                // [nb/2] pair rotated this round
+  unsigned int* rotated;                    // pairs rotated this sweep
+  const double* tol_abs;                    // device scalar threshold
+  int round;
+  int inner_sweeps;                         // sweeps of the 32 x 32 pair solve per visit
+};
+// *out = c * u * ||H||_F
+void herm_tol(const double* hr, const double* hi, int64_t ldh, int n, double c, double* out, hipStream_t s);
+void herm_round(HermArgs a, int round, hipStream_t s);
+// out[i] = Re H(i, i)
+void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s);
+
+// Newton-Schulz helpers on p x p planar matrices (leading dimension p).
+// out[0] = max_i sum_j |A(i, j)| (Gershgorin bound), out[1] = sqrt(out[0]).
+void gershgorin(const double* ar, const double* ai, int p, double* out, hipStream_t s);
+// Y = A / *c  and  Z = I.
+void ns_init(const double* ar, const double* ai, int p, const double* c, double* yr, double* yi, double* zr,
+             double* zi, hipStream_t s);
+// T = (3 I - P) / 2 in place; partial sums of ||T - I||_F^2 into dev[0..g),
+// g returned (at most 256).
+int ns_three_minus(double* pr, double* pi, int p, double* dev, hipStream_t s);
+
 // *out = (4 u)^2 sum_i norms[i]^2: squared norm below which a row of a matrix
 // with these row norms is rounding noise (u = 2^-53).
 void negligible_norm2(const double* norms, int r, double* out, hipStream_t s);
@@ -63,9 +93,19 @@ void row_norms(const double* xr, const double* xi, int64_t ldx, int r, int c, do
 // into lam_out[0..k), perm[0..k), inv_sig[0..k) = 1/sigma, and into info:
 // info_i[0] = k; info_d[0] = nrm, info_d[1] = discarded relative weight;
 // *ledger += weight.
+// extra_tail (device scalar, may be null): weight of values not in vals (added
+// to the total and to every tail).
 void select_truncate(const double* vals, int r, int is_gram, int chi_max, double w_max, double eps,
                      double* lam_out, int* perm, double* inv_sig, int* info_i, double* info_d,
-                     double* ledger, hipStream_t s);
+                     double* ledger, const double* extra_tail, hipStream_t s);
+// Deterministic pseudo-random fill in [-1, 1) (counter hash of (seed, index)).
+void fill_random(double* p, int64_t n, uint64_t seed, hipStream_t s);
+// Rows of X scaled to unit 2-norm (zero rows stay zero).
+void normalize_rows(double* xr, double* xi, int64_t ldx, int r, int c, double* norms, hipStream_t s);
+// out[i] = 1 / sqrt(max(d[i], floor)) with floor = rel * max_j d[j] (0 if d[i] <= floor).
+void inv_sqrt_clamped(const double* d, int n, double rel, double* out, hipStream_t s);
+// *out = max(0, trace - sum_i vals[i]), trace = sum of diag of H.
+void tail_rest(const double* hr, int64_t ldh, int n, const double* vals, int p, double* out, hipStream_t s);
 
 // dst row i = src row perm[i] * (scale ? scale[i] : 1), i < k; planar, c columns.
 void gather_rows(const double* sr, const double* si, int64_t lds, const int* perm, const double* scale,

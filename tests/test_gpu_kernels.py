@@ -93,3 +93,21 @@ def test_svd_rank_deficient_and_chi_cap(pt):
     sr = np.linalg.svd(A, compute_uv=False)
     assert len(s2) == 2
     assert abs(w2 - np.sum(sr[2:] ** 2) / np.sum(sr ** 2)) < 1e-13
+
+
+@pytest.mark.parametrize("m,n,chi", [(400, 900, 64), (900, 400, 48), (640, 3000, 128)])
+def test_gram_subspace_topk(pt, m, n, chi):
+    """Gram route with subspace iteration (chi_max well below min(m, n))."""
+    rng = np.random.default_rng(m + n + chi)
+    A, s_true = graded_matrix(rng, m, n, decay=chi / 4.0)
+    note(f"gram subspace m={m} n={n} chi={chi}")
+    s, vh, nrm, w, sweeps = pt.tebd_diag_svd(A, variant=1, chi_max=chi, w_max=1e-14, eps=1e-12)
+    _, s_ref, vh_ref = np.linalg.svd(A, full_matrices=False)
+    k = len(s)
+    assert k == chi
+    assert np.abs(s * nrm - s_ref[:k]).max() < 1e-9 * s_ref[0]
+    tot = np.sum(s_ref ** 2)
+    assert abs(w - np.sum(s_ref[k:] ** 2) / tot) < 1e-12
+    P = vh.conj().T @ vh
+    Pr = vh_ref[:k].conj().T @ vh_ref[:k]
+    assert np.abs(P - Pr).max() < 1e-6

@@ -131,3 +131,30 @@ def test_single_layers_and_random_state(pt):
         assert np.abs(C - oC).max() < tol
         assert np.abs(D - oD).max() < tol
     assert abs(g.discarded_weight() - om.w_total) < 1e-12 + 1e-8 * om.w_total
+
+
+@pytest.mark.parametrize("svd", [0, 1])
+def test_random_state_layers_chi48(pt, svd):
+    """Random right-orthonormal input at chi = 48, d = 5: with the Gram route
+    the top-chi eigenpairs come from subspace iteration (r = 240 > 1.5 p)."""
+    L, d, chi = 12, 5, 48
+    B, lam = random_mps(L, d, chi, seed=7, tau=10.0)
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-12)
+    om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12, svd=svd), B, lam)
+    gates = otebd.GateCache(m)
+    errs = []
+    for group, tau in [(0, 0.005), (1, 0.005), (2, 0.01)]:
+        note(f"chi48 svd={svd} layer group={group}")
+        otebd.apply_layer(om, gates, group, tau, tr)
+        g.layer(group, tau)
+        n, C, D = g.measure()
+        on, oC, oD = otebd.measure(om)
+        errs.append(max(np.abs(n - on).max(), np.abs(C - oC).max(), np.abs(D - oD).max()))
+    note(f"chi48 svd={svd} errors per layer {errs} min_gap {om.min_gap:.2e} w {om.w_total:.2e}")
+    tol = 1e-10 if svd == 0 else 1e-7
+    if om.min_gap < 1e-8:
+        tol = max(tol, 2 * om.w_total)
+    assert max(errs) < tol
+    assert g.bond_dims() == om.bond_dims()
