@@ -73,7 +73,9 @@ def main():
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--svd", choices=["gram", "jacobi"], default="gram")
     ap.add_argument("--prec", choices=["fp64", "fp32", "split"], default="fp64")
-    ap.add_argument("--tau", type=float, default=110.0, help="decay length of the synthetic Schmidt profile")
+    ap.add_argument("--tau", type=float, default=110.0, help="decay length of the imposed Lambda profile")
+    ap.add_argument("--bias", type=float, default=120.0,
+                    help="decay length of the right-index weighting that shapes the canonical Schmidt spectra")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-canonicalize", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -102,7 +104,7 @@ def main():
     svd = {"gram": pt.SVD_GRAM_EIG, "jacobi": pt.SVD_JACOBI}[args.svd]
 
     t0 = time.perf_counter()
-    B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau)
+    B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
     log(f"synthetic input L={L} d={d} chi={chi} generated in {time.perf_counter() - t0:.1f} s")
     model = pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre())
     opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream)
@@ -170,7 +172,7 @@ def main():
         "config": {"workload": "bulk_L64_chi1024", "L": L, "d": d, "chi_max": chi, "U": mdl.U, "J": mdl.J,
                    "Jnnn": mdl.Jnnn, "K": mdl.K, "dt": dt, "svd": args.svd, "theta_gate_prec": args.prec,
                    "gate_updates_per_step": nsteps_gu, "w_max": 1e-12, "eps": 1e-12,
-                   "input": (f"random right-orthonormal MPS (seed {args.seed}), Schmidt profile exp(-k/{args.tau:g}), "
+                   "input": (f"random right-orthonormal MPS (seed {args.seed}, right-index weight exp(-b/{args.bias:g})), "
                              + ("canonicalised by an identity sweep" if not args.no_canonicalize else "as generated"))},
         "roofline": roof,
         "path_roofline": {"unit_flops": F_GU, "achieved_TFLOPs": F_GU * value / 1e12, "peak": PEAK_FP64,

@@ -91,6 +91,9 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* ctx);  /* optional device allocator (e.g. torch caching allocator) */
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
+  int32_t workers;        /* gate workspaces run concurrently within a layer (own stream and host
+                             thread each); 0 = min(4, gates per layer).  Device memory grows by one
+                             gate workspace per worker. */
 } tebd_opts;
 
 typedef struct tebd_mps tebd_mps;

@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("chi_max", ctypes.c_int32), ("trunc_weight", ctypes.c_double), ("trunc_rel", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("svd", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32)]
 
 
 def _load():
@@ -109,12 +109,13 @@ def make_model(L: int, d: int, U: float, J: float = 1.0, Jnnn: float = 0.0, K: f
 
 
 def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int = FP64, svd: int = SVD_JACOBI,
-              max_sweeps: int = 40, stream: Optional[int] = None) -> Opts:
+              max_sweeps: int = 40, stream: Optional[int] = None, workers: int = 0) -> Opts:
     o = Opts()
     _lib.tebd_opts_default(ctypes.byref(o))
     o.chi_max, o.trunc_weight, o.trunc_rel = chi_max, w_max, eps
     o.prec, o.svd, o.max_sweeps = prec, svd, max_sweeps
     o.stream = stream
+    o.workers = workers
     return o
 
 

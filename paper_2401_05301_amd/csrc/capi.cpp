@@ -63,6 +63,7 @@ tebd_status check_opts(const tebd_opts* o, int d) {
   if (!finite(o->trunc_rel) || o->trunc_rel < 0) return fail(TEBD_EINVAL, "trunc_rel must be >= 0");
   if (o->prec < TEBD_FP64 || o->prec > TEBD_FP32_SPLIT) return fail(TEBD_EINVAL, "bad precision");
   if (o->svd < TEBD_SVD_JACOBI || o->svd > TEBD_SVD_GRAM_EIG) return fail(TEBD_EINVAL, "bad svd variant");
+  if (o->workers < 0) return fail(TEBD_EINVAL, "workers must be >= 0");
   if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr))
     return fail(TEBD_EINVAL, "dev_alloc and dev_free must be given together");
   return TEBD_OK;
@@ -272,8 +273,7 @@ tebd_status mps_discarded_weight(const tebd_mps* M, double* w) {
 
 tebd_status mps_sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
   if (!M || !last || !total) return fail(TEBD_EINVAL, "NULL argument");
-  *last = M->last_sweeps;
-  *total = M->total_sweeps;
+  ptebd::sweep_stats(M, last, total);
   return TEBD_OK;
 }
 
@@ -283,7 +283,7 @@ tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t
   if (st) return st;
   st = check_opts(opts, model->d);
   if (st) return st;
-  *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max).bytes();
+  *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max).bytes(ptebd::auto_workers(model->L, opts->workers));
   return TEBD_OK;
 }
 

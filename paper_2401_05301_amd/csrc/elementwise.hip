@@ -164,6 +164,47 @@ __global__ __launch_bounds__(256) void normalize_rows_kernel(double* xr, double*
   }
 }
 
+// Damped power step on Ritz pairs: row i of Y holds (G z_i)^+ and row i of Z
+// holds z_i^+ with Ritz value theta_i.  The residual R_i = Y_i - theta_i Z_i
+// is orthogonal to every z_j, so Y_i <- Z_i + beta_i R_i keeps the rows
+// within a factor (1 + gamma^2) of orthonormal while beta_i = 1 / theta_i (a
+// plain power step, up to scale) wherever the residual is small against the
+// Ritz value.  Rows whose Ritz value is below zero_rel * max theta keep z_i;
+// beta_i never exceeds 1 / (damp_rel * max theta).
+__global__ __launch_bounds__(256) void damped_power_rows_kernel(const double* zr, const double* zi, double* yr,
+                                                                double* yi, int64_t ld, int p, int r,
+                                                                const double* theta, double gamma, double damp_rel,
+                                                                double zero_rel) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= p) return;
+  double tmax = 0.0;
+  for (int j = lane; j < p; j += 64) tmax = fmax(tmax, theta[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+  const double th = theta[row];
+  const double* pz = zr + (int64_t)row * ld;
+  const double* qz = zi + (int64_t)row * ld;
+  double* py = yr + (int64_t)row * ld;
+  double* qy = yi + (int64_t)row * ld;
+  double s = 0.0;
+  for (int j = lane; j < r; j += 64) {
+    const double a = py[j] - th * pz[j];
+    const double b = qy[j] - th * qz[j];
+    s += a * a + b * b;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  const double res = sqrt(s);
+  double beta = 0.0;
+  if (tmax > 0.0 && th > zero_rel * tmax) beta = 1.0 / fmax(fmax(th, res / gamma), damp_rel * tmax);
+  const double keep = 1.0 - beta * th;
+  for (int j = lane; j < r; j += 64) {
+    py[j] = keep * pz[j] + beta * py[j];
+    qy[j] = keep * qz[j] + beta * qy[j];
+  }
+}
+
 __global__ __launch_bounds__(256) void inv_sqrt_clamped_kernel(const double* d, int n, double rel, double* out) {
   __shared__ double sh[256];
   double mx = 0.0;
@@ -249,6 +290,15 @@ __global__ __launch_bounds__(256) void ns_three_minus_kernel(double* pr, double*
 }
 
 }  // namespace
+
+// Adds the per-gate ledger slots to the running total in gate order, so that
+// the sum does not depend on which worker finished first.
+__global__ void accumulate_slots_kernel(const double* slots, int n, double* acc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = 0.0;
+  for (int i = 0; i < n; ++i) t += slots[i];
+  acc[0] += t;
+}
 
 void gershgorin(const double* ar, const double* ai, int p, double* out, hipStream_t s) {
   gershgorin_kernel<<<1, 256, 0, s>>>(ar, ai, p, out);
@@ -341,6 +391,18 @@ void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s) {
 void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d, int cr,
                double* out, hipStream_t s) {
   close_hop_kernel<<<1, 256, 0, s>>>(br, bi, fr, fi, chi, d, cr, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(accumulate_slots_kernel, dim3(1), dim3(64), 0, s, slots, n, acc);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void damped_power_rows(const double* zr, const double* zi, double* yr, double* yi, int64_t ld, int p, int r,
+                       const double* theta, double gamma, double damp_rel, double zero_rel, hipStream_t s) {
+  hipLaunchKernelGGL(damped_power_rows_kernel, dim3(ceil_div(p, 4)), dim3(256), 0, s, zr, zi, yr, yi, ld, p, r, theta,
+                     gamma, damp_rel, zero_rel);
   PTEBD_LAUNCH_CHECK();
 }
 

@@ -16,7 +16,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <string>
+#include <thread>
 
 namespace ptebd {
 
@@ -67,13 +69,20 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 
 }  // namespace
 
-size_t Sizes::bytes() const {
+size_t Sizes::bytes(int workers) const {
   int64_t d = 0;
-  d += 2 * site_elems + lam_elems;
-  d += 2 * (T1 + 2 * psi + X2 + G + W + V1h + 2 * meas_sq + 2 * meas_rect);
-  d += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
-  d += 5 * vec + part + gates + 64;
+  d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
+  int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
+  w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
+  w += 6 * vec + part + 64;
+  d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
+}
+
+int auto_workers(int L, int requested) {
+  const int per_layer = std::max(1, (L - 2 + 2) / 3);
+  const int w = requested > 0 ? requested : 4;
+  return std::max(1, std::min(w, per_layer));
 }
 
 int subspace_width(int r, int chi_max) {
@@ -122,6 +131,49 @@ Sizes plan_sizes(int L, int d, int chi_max) {
   return s;
 }
 
+namespace {
+
+// Gate workspace of one worker W (sizes from plan_sizes).
+void allocate_work(tebd_mps* W, const Sizes& s) {
+  W->T1 = zalloc(W, s.T1);
+  W->psi = zalloc(W, s.psi);
+  W->psip = zalloc(W, s.psi);
+  W->X2 = zalloc(W, s.X2);
+  W->G = zalloc(W, s.G);
+  W->W = zalloc(W, s.W);
+  W->V1h = zalloc(W, s.V1h);
+  W->ks = dalloc(W, s.vec);
+  W->norms = dalloc(W, s.vec);
+  W->inv_sig = dalloc(W, s.vec);
+  W->sq = dalloc(W, s.vec);
+  W->perm = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
+  W->flags = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
+  if (s.sub_p > 0 && W->opts.svd == TEBD_SVD_GRAM_EIG) {
+    W->sub_p = (int)s.sub_p;
+    W->sZ = zalloc(W, s.sub_p * s.sub_r);
+    W->sY = zalloc(W, s.sub_p * s.sub_r);
+    W->sZ2 = zalloc(W, s.sub_p * s.sub_r);
+    W->sY2 = zalloc(W, s.sub_p * s.sub_r);
+    W->sH = zalloc(W, s.sub_p * s.sub_p);
+    W->sW = zalloc(W, s.sub_p * s.sub_p);
+    W->nY = zalloc(W, s.sub_p * s.sub_p);
+    W->nZ = zalloc(W, s.sub_p * s.sub_p);
+    W->nY2 = zalloc(W, s.sub_p * s.sub_p);
+    W->nZ2 = zalloc(W, s.sub_p * s.sub_p);
+    W->ns_part = dalloc(W, 256);
+  }
+  W->part = dalloc(W, s.part);
+  W->part_cap = s.part;
+  W->info_i = static_cast<int*>(dev_alloc(W, sizeof(int) * 8));
+  W->info_d = dalloc(W, 16);
+  W->counter = static_cast<unsigned int*>(dev_alloc(W, sizeof(unsigned int) * 4));
+  PTEBD_HIP(hipHostMalloc((void**)&W->h_counter, 64, hipHostMallocDefault));
+  PTEBD_HIP(hipHostMalloc((void**)&W->h_info, 64, hipHostMallocDefault));
+  PTEBD_HIP(hipHostMalloc((void**)&W->h_part, 256 * sizeof(double), hipHostMallocDefault));
+}
+
+}  // namespace
+
 void mps_allocate(tebd_mps* M) {
   Sizes s = plan_sizes(M->L, M->d, M->chi_max);
   M->cap = s.cap;
@@ -137,58 +189,48 @@ void mps_allocate(tebd_mps* M) {
   M->lam.resize(L + 1);
   for (int b = 0; b <= L; ++b) M->lam[b] = dalloc(M, M->cap[b]);
   M->ledger = dalloc(M, 1);
-  M->T1 = zalloc(M, s.T1);
-  M->psi = zalloc(M, s.psi);
-  M->psip = zalloc(M, s.psi);
-  M->X2 = zalloc(M, s.X2);
-  M->G = zalloc(M, s.G);
-  M->W = zalloc(M, s.W);
-  M->V1h = zalloc(M, s.V1h);
+  M->wslots = dalloc(M, L);
   M->E = zalloc(M, s.meas_sq);
   M->F2 = zalloc(M, s.meas_sq);
   M->F = zalloc(M, s.meas_rect);
   M->F3 = zalloc(M, s.meas_rect);
   M->ks = dalloc(M, s.vec);
-  M->norms = dalloc(M, s.vec);
-  M->inv_sig = dalloc(M, s.vec);
-  M->sq = dalloc(M, s.vec);
-  M->perm = static_cast<int*>(dev_alloc(M, sizeof(int) * s.vec));
-  M->flags = static_cast<int*>(dev_alloc(M, sizeof(int) * s.vec));
-  if (s.sub_p > 0 && M->opts.svd == TEBD_SVD_GRAM_EIG) {
-    M->sub_p = (int)s.sub_p;
-    M->sZ = zalloc(M, s.sub_p * s.sub_r);
-    M->sY = zalloc(M, s.sub_p * s.sub_r);
-    M->sZ2 = zalloc(M, s.sub_p * s.sub_r);
-    M->sY2 = zalloc(M, s.sub_p * s.sub_r);
-    M->sH = zalloc(M, s.sub_p * s.sub_p);
-    M->sW = zalloc(M, s.sub_p * s.sub_p);
-    M->nY = zalloc(M, s.sub_p * s.sub_p);
-    M->nZ = zalloc(M, s.sub_p * s.sub_p);
-    M->nY2 = zalloc(M, s.sub_p * s.sub_p);
-    M->nZ2 = zalloc(M, s.sub_p * s.sub_p);
-    M->ns_part = dalloc(M, 256);
-  }
-  M->part = dalloc(M, s.part);
-  M->part_cap = s.part;
-  M->info_i = static_cast<int*>(dev_alloc(M, sizeof(int) * 8));
-  M->info_d = dalloc(M, 16);
-  M->counter = static_cast<unsigned int*>(dev_alloc(M, sizeof(unsigned int) * 4));
   M->meas = dalloc(M, 5 * (int64_t)L);
   M->d_br = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
   M->d_bi = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
   M->d_lam = static_cast<double**>(dev_alloc(M, sizeof(double*) * (L + 1)));
   M->d_chi = static_cast<int*>(dev_alloc(M, sizeof(int) * (L + 1)));
-  PTEBD_HIP(hipHostMalloc((void**)&M->h_counter, 64, hipHostMallocDefault));
-  PTEBD_HIP(hipHostMalloc((void**)&M->h_info, 64, hipHostMallocDefault));
-  PTEBD_HIP(hipHostMalloc((void**)&M->h_part, 256 * sizeof(double), hipHostMallocDefault));
   PTEBD_HIP(hipMemcpyAsync(M->d_br, M->Br.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemsetAsync(M->ledger, 0, sizeof(double), M->stream));
+  const int nw = auto_workers(L, M->opts.workers);
+  for (int w = 0; w < nw; ++w) {
+    tebd_mps* W = new tebd_mps();
+    M->workers.push_back(W);
+    W->parent = M;
+    W->opts = M->opts;
+    W->L = M->L;
+    W->d = M->d;
+    W->chi_max = M->chi_max;
+    if (w == 0) {
+      W->stream = M->stream;
+    } else {
+      PTEBD_HIP(hipStreamCreateWithFlags(&W->stream, hipStreamNonBlocking));
+      W->own_stream = true;
+    }
+    allocate_work(W, s);
+  }
   PTEBD_HIP(hipStreamSynchronize(M->stream));
 }
 
 void mps_release(tebd_mps* M) {
+  for (tebd_mps* W : M->workers) {
+    mps_release(W);
+    if (W->own_stream) (void)hipStreamDestroy(W->stream);
+    delete W;
+  }
+  M->workers.clear();
   if (M->stream) (void)hipStreamSynchronize(M->stream);
   for (void* p : M->allocs) {
     if (M->opts.dev_free)
@@ -332,6 +374,13 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
 // Truncated SVD of diag(rs) A.  Writes the kept normalised singular values
 // into lam_out, V^+ rows into (vhr, vhi) with leading dimension n, the norm of
 // the kept values into info_d[2*slot] and returns k.
+// Off-diagonal target of the Hermitian Jacobi in units of u ||H||_F (the
+// Gram matrices carry absolute errors of ~sqrt(k) u ||M||^2 themselves).
+double herm_tol_units() {
+  static const double v = std::getenv("PTEBD_HERM_TOL") ? std::atof(std::getenv("PTEBD_HERM_TOL")) : 32.0;
+  return v;
+}
+
 int inner_sweeps() {
   static const int v = std::getenv("PTEBD_INNER_SWEEPS") ? std::atoi(std::getenv("PTEBD_INNER_SWEEPS")) : 2;
   return v;
@@ -355,7 +404,7 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
   a.flag = M->flags;
   a.inner_sweeps = inner_sweeps();
   a.rotated = M->counter;
-  herm_tol(hr, hi, ldh, n, 32.0, M->info_d + 7, s);
+  herm_tol(hr, hi, ldh, n, herm_tol_units(), M->info_d + 7, s);
   a.tol_abs = M->info_d + 7;
   if (wr) set_identity(wr, wi, ldw, n, s);
   const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
@@ -383,15 +432,20 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
 // inverse square root of A = Z Z^+ comes from the coupled Newton-Schulz
 // iteration Y <- Y T, X <- T X, T = (3 I - X Y) / 2 started from Y = A / c,
 // X = I, with c >= lambda_max(A) (Gershgorin), so that X -> (A / c)^{-1/2}.
-void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r) {
+// With in_place the result is copied back into Z's memory (Z may then be a
+// view of leading rows of a larger basis); otherwise Z and T swap.
+void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_place = false) {
   hipStream_t s = M->stream;
   normalize_rows(Z.re, Z.im, r, p, r, nullptr, s);
+  // every product below is a polynomial in the Hermitian A, hence Hermitian:
+  // only the lower-triangular tiles are computed
   auto mm = [&](const tebd_mps::Z& A, const tebd_mps::Z& B, tebd_mps::Z& C) {
     ZGemmArgs g;
     g.m = p; g.n = p; g.k = p;
     g.ar = A.re; g.ai = A.im; g.lda = p;
     g.br = B.re; g.bi = B.im; g.ldb = p;
     g.cr = C.re; g.ci = C.im; g.ldc = p;
+    g.herm_out = 1;
     zgemm(g, 0, s);
   };
   {
@@ -400,6 +454,7 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r) {
     g.ar = Z.re; g.ai = Z.im; g.lda = r;
     g.br = Z.re; g.bi = Z.im; g.ldb = r; g.transB = 1;
     g.cr = M->sH.re; g.ci = M->sH.im; g.ldc = p;
+    g.herm_out = 1;
     zgemm(g, 0, s);
   }
   double* c = M->info_d + 8;   // c, sqrt(c)
@@ -421,6 +476,10 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r) {
     if (dev <= tol2) break;
   }
   if (debug_enabled()) std::fprintf(stderr, "[ptebd] lowdin p=%d newton-schulz iterations=%d\n", p, it + 1);
+  if (it == 40) {
+    M->failed = true;
+    throw Error(-4, "Newton-Schulz orthonormalisation did not converge (basis of width " + std::to_string(p) + ")");
+  }
   // Z <- A^{-1/2} Z = X Z / sqrt(c)
   ZGemmArgs q;
   q.m = p; q.n = r; q.k = p;
@@ -429,7 +488,12 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r) {
   q.cr = T.re; q.ci = T.im; q.ldc = r;
   q.alpha_dev = c + 1; q.alpha_recip = 1;
   zgemm(q, 0, s);
-  std::swap(Z, T);
+  if (in_place) {
+    PTEBD_HIP(hipMemcpyAsync(Z.re, T.re, sizeof(double) * (size_t)p * r, hipMemcpyDeviceToDevice, s));
+    PTEBD_HIP(hipMemcpyAsync(Z.im, T.im, sizeof(double) * (size_t)p * r, hipMemcpyDeviceToDevice, s));
+  } else {
+    std::swap(Z, T);
+  }
 }
 
 // Top-p eigenpairs of the Hermitian PSD G (r x r) by subspace iteration with
@@ -440,19 +504,45 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
   hipStream_t s = M->stream;
   fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
   fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
+  int kw = 0;   // warm rows at the top of the basis
   if (w.kind == 1 && w.src_cols <= p && w.src_rows == r) {
     conj_transpose_scaled(w.sr, w.si, w.ld, w.rs, w.rdiv, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
+    kw = w.src_cols;
   } else if (w.kind == 2 && w.src_rows <= p && w.src_cols == r) {
     scale_rows_copy(w.sr, w.si, w.ld, nullptr, 1, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
+    kw = w.src_rows;
   }
-  lowdin(M, M->sZ, M->sZ2, p, r);
-  lowdin(M, M->sZ, M->sZ2, p, r);
+  if (kw > 0 && kw < p) {
+    // Orthonormalise the warm rows on their own and take the random rows
+    // out of their span, so that the basis keeps the warm rows as they are
+    // (a joint symmetric orthonormalisation would mix them with noise).
+    lowdin(M, M->sZ, M->sZ2, kw, r, true);
+    tebd_mps::Z rnd{M->sZ.re + (size_t)kw * r, M->sZ.im + (size_t)kw * r};
+    ZGemmArgs c;   // C = R Zw^+  ((p - kw) x kw)
+    c.m = p - kw; c.n = kw; c.k = r;
+    c.ar = rnd.re; c.ai = rnd.im; c.lda = r;
+    c.br = M->sZ.re; c.bi = M->sZ.im; c.ldb = r; c.transB = 1;
+    c.cr = M->sH.re; c.ci = M->sH.im; c.ldc = kw;
+    zgemm(c, 0, s);
+    ZGemmArgs u;   // R <- R - C Zw
+    u.m = p - kw; u.n = r; u.k = kw;
+    u.ar = M->sH.re; u.ai = M->sH.im; u.lda = kw;
+    u.br = M->sZ.re; u.bi = M->sZ.im; u.ldb = r;
+    u.cr = rnd.re; u.ci = rnd.im; u.ldc = r;
+    u.alpha = -1.0; u.beta = 1;
+    zgemm(u, 0, s);
+    lowdin(M, M->sZ, M->sZ2, p, r);
+  } else {
+    lowdin(M, M->sZ, M->sZ2, p, r);
+    lowdin(M, M->sZ, M->sZ2, p, r);
+  }
   // trace of G: scale of the rounding noise in the Ritz values
   tail_rest(gr, r, r, M->norms, 0, M->info_d + 4, s);
   double trace = 0.0;
   PTEBD_HIP(hipMemcpyAsync(&trace, M->info_d + 4, sizeof(double), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
-  std::vector<double> prev(keep, 0.0), cur(keep, 0.0);
+  double prev_kept = 0.0;
+  std::vector<double> prev(keep, 0.0);
   const int max_it = 30;
   for (int it = 0; it < max_it; ++it) {
     // Y = Z G (rows: (G z_i)^+), H = Y Z^+
@@ -467,6 +557,7 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     h.ar = M->sY.re; h.ai = M->sY.im; h.lda = r;
     h.br = M->sZ.re; h.bi = M->sZ.im; h.ldb = r; h.transB = 1;
     h.cr = M->sH.re; h.ci = M->sH.im; h.ldc = p;
+    h.herm_out = 1;   // Z G Z^+ is Hermitian
     zgemm(h, 0, s);
     run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p);
     herm_diag(M->sH.re, p, p, M->norms, s);
@@ -487,18 +578,32 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     PTEBD_HIP(hipMemcpyAsync(h_vals.data(), M->norms, sizeof(double) * p, hipMemcpyDeviceToHost, s));
     PTEBD_HIP(hipStreamSynchronize(s));
     std::sort(h_vals.begin(), h_vals.end(), std::greater<double>());
-    double delta = 0.0;
+    double kept = 0.0, delta = 0.0;
     for (int i = 0; i < keep; ++i) {
-      cur[i] = h_vals[i];
-      delta = std::max(delta, std::fabs(cur[i] - prev[i]));
+      kept += h_vals[i];
+      delta = std::max(delta, std::fabs(h_vals[i] - prev[i]));
+      prev[i] = h_vals[i];
     }
-    if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d delta=%.3e top=%.6e\n", r, p, it,
-                                      delta, h_vals[0]);
-    // a change of a kept Ritz value bounds the weight its vector can still
-    // move; stop at 1e-13 of the largest or at the rounding level of G
-    if (it >= 1 && delta <= 1e-13 * cur[0] + 128 * 1.1102230246251565e-16 * trace) break;
-    prev = cur;
-    // next basis: orthonormalised image of the Ritz vectors
+    if (debug_enabled())
+      std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d captured=%.15e gain=%.3e delta=%.3e top=%.6e\n", r, p,
+                   it, kept, kept - prev_kept, delta, h_vals[0]);
+    // The sum of the largest `keep` Ritz values is the weight the kept
+    // subspace captures; it grows monotonically towards the optimum.  Stop
+    // once an iteration gains less than 1e-4 of the weight still outside
+    // (or less than the rounding level of G) and no kept Ritz value moved by
+    // more than 1e-10 of the largest.
+    const double u = 1.1102230246251565e-16;
+    if (it >= 1 && kept - prev_kept <= std::max(1e-4 * (trace - kept), 64 * u * trace) &&
+        delta <= 1e-10 * h_vals[0])
+      break;
+    prev_kept = kept;
+    // next basis: orthonormalised (damped) image of the Ritz vectors.  A
+    // plain image G Z has rows spread over the whole dynamic range of G and
+    // is too ill-conditioned to orthonormalise by Newton-Schulz; scaling
+    // each image by its Ritz value and capping the residual step keeps the
+    // rows near orthonormal.
+    damped_power_rows(M->sZ.re, M->sZ.im, M->sY.re, M->sY.im, r, p, r, M->norms, 1.0, 1e-10,
+                      kGramSigmaFloor * kGramSigmaFloor, s);
     std::swap(M->sZ, M->sY);
     lowdin(M, M->sZ, M->sZ2, p, r);
   }
@@ -616,85 +721,180 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
 
 namespace {
 
-void gate_update(tebd_mps* M, int j, std::pair<double*, double*> G) {
-  hipStream_t s = M->stream;
-  const int d = M->d, d3 = d * d * d;
-  const int cl = M->chi[j], c1 = M->chi[j + 1], c2 = M->chi[j + 2], cr = M->chi[j + 3];
-  const int prec = M->opts.prec;
+// One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
+// stream and settings of worker W.
+void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {
+  hipStream_t s = W->stream;
+  const int d = W->d, d3 = d * d * d;
+  const int cl = S->chi[j], c1 = S->chi[j + 1], c2 = S->chi[j + 2], cr = S->chi[j + 3];
+  const int prec = W->opts.prec;
   {  // T1 = B_j B_{j+1}
     ZGemmArgs g;
     g.m = cl * d; g.n = d * c2; g.k = c1;
-    g.ar = M->Br[j]; g.ai = M->Bi[j]; g.lda = c1;
-    g.br = M->Br[j + 1]; g.bi = M->Bi[j + 1]; g.ldb = (int64_t)d * c2;
-    g.cr = M->T1.re; g.ci = M->T1.im; g.ldc = (int64_t)d * c2;
+    g.ar = S->Br[j]; g.ai = S->Bi[j]; g.lda = c1;
+    g.br = S->Br[j + 1]; g.bi = S->Bi[j + 1]; g.ldb = (int64_t)d * c2;
+    g.cr = W->T1.re; g.ci = W->T1.im; g.ldc = (int64_t)d * c2;
     zgemm(g, prec, s);
   }
   {  // psi = T1 B_{j+2}
     ZGemmArgs g;
     g.m = cl * d * d; g.n = d * cr; g.k = c2;
-    g.ar = M->T1.re; g.ai = M->T1.im; g.lda = c2;
-    g.br = M->Br[j + 2]; g.bi = M->Bi[j + 2]; g.ldb = (int64_t)d * cr;
-    g.cr = M->psi.re; g.ci = M->psi.im; g.ldc = (int64_t)d * cr;
+    g.ar = W->T1.re; g.ai = W->T1.im; g.lda = c2;
+    g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = (int64_t)d * cr;
+    g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)d * cr;
     zgemm(g, prec, s);
   }
   {  // psi'[a] = G psi[a]
     ZGemmArgs g;
     g.m = d3; g.n = cr; g.k = d3; g.batch = cl;
     g.ar = G.first; g.ai = G.second; g.lda = d3; g.sA = 0;
-    g.br = M->psi.re; g.bi = M->psi.im; g.ldb = cr; g.sB = (int64_t)d3 * cr;
-    g.cr = M->psip.re; g.ci = M->psip.im; g.ldc = cr; g.sC = (int64_t)d3 * cr;
+    g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)d3 * cr;
+    g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)d3 * cr;
     zgemm(g, prec, s);
   }
   const int m1 = cl * d, n1 = d * d * cr;
-  SvdIn in1{M->psip.re, M->psip.im, n1, m1, n1, M->lam[j], d};
+  SvdIn in1{W->psip.re, W->psip.im, n1, m1, n1, S->lam[j], d};
   // before the gate the left singular space of theta across bond j+1 is
   // spanned by the columns of Lambda_j B_j
   in1.warm.kind = 1;
-  in1.warm.sr = M->Br[j]; in1.warm.si = M->Bi[j]; in1.warm.ld = c1;
+  in1.warm.sr = S->Br[j]; in1.warm.si = S->Bi[j]; in1.warm.ld = c1;
   in1.warm.src_rows = m1; in1.warm.src_cols = c1;
-  in1.warm.rs = M->lam[j]; in1.warm.rdiv = d;
-  const int k1 = svd_trunc(M, in1, M->lam[j + 1], M->V1h.re, M->V1h.im, 0, M->psi);
+  in1.warm.rs = S->lam[j]; in1.warm.rdiv = d;
+  const int k1 = svd_trunc(W, in1, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi);
   {  // B_j = psi' V1 / |S1|
     ZGemmArgs g;
     g.m = m1; g.n = k1; g.k = n1;
-    g.ar = M->psip.re; g.ai = M->psip.im; g.lda = n1;
-    g.br = M->V1h.re; g.bi = M->V1h.im; g.ldb = n1; g.transB = 1;
-    g.cr = M->Br[j]; g.ci = M->Bi[j]; g.ldc = k1;
-    g.alpha_dev = M->info_d + 0; g.alpha_recip = 1;
+    g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
+    g.br = W->V1h.re; g.bi = W->V1h.im; g.ldb = n1; g.transB = 1;
+    g.cr = S->Br[j]; g.ci = S->Bi[j]; g.ldc = k1;
+    g.alpha_dev = W->info_d + 0; g.alpha_recip = 1;
     zgemm(g, 0, s);
   }
   const int m2 = k1 * d, n2 = d * cr;
-  SvdIn in2{M->V1h.re, M->V1h.im, n2, m2, n2, M->lam[j + 1], d};
+  SvdIn in2{W->V1h.re, W->V1h.im, n2, m2, n2, S->lam[j + 1], d};
   // before the gate the right singular space across bond j+2 is the row
   // space of B_{j+2}
   in2.prefer_right = true;
   in2.warm.kind = 2;
-  in2.warm.sr = M->Br[j + 2]; in2.warm.si = M->Bi[j + 2]; in2.warm.ld = n2;
+  in2.warm.sr = S->Br[j + 2]; in2.warm.si = S->Bi[j + 2]; in2.warm.ld = n2;
   in2.warm.src_rows = c2; in2.warm.src_cols = n2;
-  const int k2 = svd_trunc(M, in2, M->lam[j + 2], M->Br[j + 2], M->Bi[j + 2], 1, M->X2);
+  const int k2 = svd_trunc(W, in2, S->lam[j + 2], S->Br[j + 2], S->Bi[j + 2], 1, W->X2);
   {  // B_{j+1} = V1^+ V2 / |S2|
     ZGemmArgs g;
     g.m = m2; g.n = k2; g.k = n2;
-    g.ar = M->V1h.re; g.ai = M->V1h.im; g.lda = n2;
-    g.br = M->Br[j + 2]; g.bi = M->Bi[j + 2]; g.ldb = n2; g.transB = 1;
-    g.cr = M->Br[j + 1]; g.ci = M->Bi[j + 1]; g.ldc = k2;
-    g.alpha_dev = M->info_d + 2; g.alpha_recip = 1;
+    g.ar = W->V1h.re; g.ai = W->V1h.im; g.lda = n2;
+    g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = n2; g.transB = 1;
+    g.cr = S->Br[j + 1]; g.ci = S->Bi[j + 1]; g.ldc = k2;
+    g.alpha_dev = W->info_d + 2; g.alpha_recip = 1;
     zgemm(g, 0, s);
   }
-  M->chi[j + 1] = k1;
-  M->chi[j + 2] = k2;
+  S->chi[j + 1] = k1;
+  S->chi[j + 2] = k2;
+}
+
+}  // namespace
+
+namespace {
+
+// Adds the per-gate discarded weights of the layer to the ledger, in gate
+// order (independent of how the gates were spread over workers).
+void fold_ledger(tebd_mps* M) { accumulate_slots(M->wslots, M->L, M->ledger, M->stream); }
+
+void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::pair<double*, double*>>& G,
+               bool parallel) {
+  fill_zero(M->wslots, M->L, M->stream);
+  const int nw = parallel ? std::min<int>((int)M->workers.size(), (int)js.size()) : 1;
+  if (nw <= 1) {
+    tebd_mps* W = M->workers[0];
+    for (size_t x = 0; x < js.size(); ++x) {
+      W->ledger = M->wslots + js[x];
+      gate_update(M, W, js[x], G[x]);
+    }
+  } else {
+    // workers start after everything enqueued so far on the handle's stream
+    hipEvent_t start;
+    PTEBD_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    PTEBD_HIP(hipEventRecord(start, M->stream));
+    for (int w = 1; w < nw; ++w) PTEBD_HIP(hipStreamWaitEvent(M->workers[w]->stream, start, 0));
+    std::vector<std::exception_ptr> err(nw);
+    Profiler* prof = active_profiler();
+    auto work = [&](int w) {
+      active_profiler() = prof;
+      try {
+        tebd_mps* W = M->workers[w];
+        for (size_t x = w; x < js.size(); x += nw) {
+          W->ledger = M->wslots + js[x];
+          gate_update(M, W, js[x], G[x]);
+        }
+      } catch (...) {
+        err[w] = std::current_exception();
+      }
+      active_profiler() = nullptr;
+    };
+    std::vector<std::thread> th;
+    for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+    work(0);
+    active_profiler() = prof;
+    for (auto& t : th) t.join();
+    // the handle's stream continues after every worker
+    for (int w = 1; w < nw; ++w) {
+      hipEvent_t done;
+      PTEBD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+      PTEBD_HIP(hipEventRecord(done, M->workers[w]->stream));
+      PTEBD_HIP(hipStreamWaitEvent(M->stream, done, 0));
+      PTEBD_HIP(hipEventDestroy(done));
+    }
+    PTEBD_HIP(hipEventDestroy(start));
+    for (int w = 0; w < nw; ++w)
+      if (err[w]) {
+        for (tebd_mps* W : M->workers) M->failed = M->failed || W->failed;
+        std::rethrow_exception(err[w]);
+      }
+  }
+  fold_ledger(M);
 }
 
 }  // namespace
 
 void layer(tebd_mps* M, int group, double tau) {
-  for (int j = group; j + 2 < M->L; j += 3) gate_update(M, j, device_gate(M, j, tau));
+  std::vector<int> js;
+  std::vector<std::pair<double*, double*>> G;
+  for (int j = group; j + 2 < M->L; j += 3) {
+    js.push_back(j);
+    G.push_back(device_gate(M, j, tau));
+  }
+  try {
+    run_gates(M, js, G, true);
+  } catch (...) {
+    for (tebd_mps* W : M->workers) M->failed = M->failed || W->failed;
+    throw;
+  }
 }
 
 void canonicalize(tebd_mps* M) {
   // identity gates swept left to right: each exposes the exact Schmidt
   // decomposition across its two inner bonds given the left Lambda
-  for (int j = 0; j + 2 < M->L; ++j) gate_update(M, j, device_gate(M, j, 0.0));
+  std::vector<int> js;
+  std::vector<std::pair<double*, double*>> G;
+  for (int j = 0; j + 2 < M->L; ++j) {
+    js.push_back(j);
+    G.push_back(device_gate(M, j, 0.0));
+  }
+  try {
+    run_gates(M, js, G, false);
+  } catch (...) {
+    for (tebd_mps* W : M->workers) M->failed = M->failed || W->failed;
+    throw;
+  }
+}
+
+void sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
+  *last = 0;
+  *total = 0;
+  for (const tebd_mps* W : M->workers) {
+    *last = std::max<int64_t>(*last, W->last_sweeps);
+    *total += W->total_sweeps;
+  }
 }
 
 void prepare_gates(tebd_mps* M, int group, double tau) {

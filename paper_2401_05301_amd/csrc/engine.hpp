@@ -64,6 +64,14 @@ struct tebd_mps {
 
   ptebd::Profiler prof;   // kernel timings while profiling is enabled
   bool prof_on = false;
+
+  // Gate workspaces.  The gates of one layer act on disjoint sites, so they
+  // are spread over workers, each with its own buffers, stream and host
+  // thread; worker 0 runs on the handle's stream.  A worker is a tebd_mps
+  // that holds workspace only (its parent holds the state).
+  std::vector<tebd_mps*> workers;
+  tebd_mps* parent = nullptr;
+  double* wslots = nullptr;   // discarded weight of each gate of the current layer (device, L)
 };
 
 namespace ptebd {
@@ -74,8 +82,12 @@ struct Sizes {
   int64_t T1 = 0, psi = 0, X2 = 0, G = 0, W = 0, V1h = 0, meas_sq = 0, meas_rect = 0, vec = 0, part = 0;
   int64_t sub_p = 0, sub_r = 0;   // subspace iteration width and row length
   int64_t gates = 0;
-  size_t bytes() const;
+  size_t bytes(int workers) const;
 };
+
+// Number of gate workers of a handle: opts.workers if positive, else 4,
+// at most the number of gates in a layer.
+int auto_workers(int L, int requested);
 
 Sizes plan_sizes(int L, int d, int chi_max);
 // Width of the subspace used for the top-k eigenpairs of an r x r Gram
@@ -90,6 +102,8 @@ void layer(tebd_mps* M, int group, double tau);
 // Sweep of identity gates j = 0..L-3: brings a right-orthonormal state into
 // the canonical form with exact Schmidt values (up to truncation).
 void canonicalize(tebd_mps* M);
+// Sweeps of the last SVD (max over workers) and their running total.
+void sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total);
 // Build and upload the gates of the given group and time slice (no state change).
 void prepare_gates(tebd_mps* M, int group, double tau);
 void measure(tebd_mps* M, double* n, double* cnn, double* cnnn);

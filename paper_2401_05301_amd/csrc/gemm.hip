@@ -59,7 +59,17 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t bz = blockIdx.z;
-  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  int tile_r = blockIdx.y, tile_c = blockIdx.x;
+  if (g.herm_out) {
+    // lower-triangular tiles only (tile_c <= tile_r), linearised in blockIdx.x
+    const int t = blockIdx.x;
+    int ty = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((ty + 1) * (ty + 2) / 2 <= t) ++ty;
+    while (ty * (ty + 1) / 2 > t) --ty;
+    tile_r = ty;
+    tile_c = t - ty * (ty + 1) / 2;
+  }
+  const int row0 = tile_r * BM, col0 = tile_c * BN;
   const double* Ar = g.ar + bz * g.sA;
   const double* Ai = g.ai + bz * g.sA;
   const double* Br = g.br + bz * g.sB;
@@ -74,70 +84,89 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
       acci[a][b] = Acc{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < g.k; k0 += BK) {
-    // ---- stage op(A) tile (BM x BK) as As[kk][row]
+  // Global loads of the next K slab go to registers while the current slab is
+  // multiplied out of LDS (register double buffering).
+  double ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+  auto load = [&](int k0) {
     if (!g.transA) {
       const int kk = tid & 15, kg = k0 + kk;
       const double ks = (g.k_scale && kg < g.k) ? g.k_scale[kg / g.k_div] : 1.0;
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
-        const int r = (tid >> 4) + 16 * rep, i = row0 + r;
-        double vr = 0.0, vi = 0.0;
-        if (i < g.m && kg < g.k) {
-          const int64_t o = (int64_t)i * g.lda + kg;
-          vr = Ar[o] * ks;
-          vi = Ai[o] * ks;
-        }
-        put<PREC>(As_r, kk, r, vr);
-        put<PREC>(As_i, kk, r, vi);
+        const int i = row0 + (tid >> 4) + 16 * rep;
+        const bool ok = i < g.m && kg < g.k;
+        const int64_t o = (int64_t)i * g.lda + kg;
+        ra_r[rep] = ok ? Ar[o] * ks : 0.0;
+        ra_i[rep] = ok ? Ai[o] * ks : 0.0;
       }
     } else {
-      const int r = tid & 63, i = row0 + r;
+      const int i = row0 + (tid & 63);
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
-        const int kk = (tid >> 6) + 4 * rep, kg = k0 + kk;
-        double vr = 0.0, vi = 0.0;
-        if (i < g.m && kg < g.k) {
-          const double ks = g.k_scale ? g.k_scale[kg / g.k_div] : 1.0;
-          const int64_t o = (int64_t)kg * g.lda + i;
-          vr = Ar[o] * ks;
-          vi = -Ai[o] * ks;
-        }
-        put<PREC>(As_r, kk, r, vr);
-        put<PREC>(As_i, kk, r, vi);
+        const int kg = k0 + (tid >> 6) + 4 * rep;
+        const bool ok = i < g.m && kg < g.k;
+        const double ks = (ok && g.k_scale) ? g.k_scale[kg / g.k_div] : 1.0;
+        const int64_t o = (int64_t)kg * g.lda + i;
+        ra_r[rep] = ok ? Ar[o] * ks : 0.0;
+        ra_i[rep] = ok ? -Ai[o] * ks : 0.0;
       }
     }
-    // ---- stage op(B) tile (BK x BN) as Bs[kk][col]
     if (!g.transB) {
-      const int c = tid & 63, j = col0 + c;
+      const int j = col0 + (tid & 63);
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
-        const int kk = (tid >> 6) + 4 * rep, kg = k0 + kk;
-        double vr = 0.0, vi = 0.0;
-        if (j < g.n && kg < g.k) {
-          const int64_t o = (int64_t)kg * g.ldb + j;
-          vr = Br[o];
-          vi = Bi[o];
-        }
-        put<PREC>(Bs_r, kk, c, vr);
-        put<PREC>(Bs_i, kk, c, vi);
+        const int kg = k0 + (tid >> 6) + 4 * rep;
+        const bool ok = j < g.n && kg < g.k;
+        const int64_t o = (int64_t)kg * g.ldb + j;
+        rb_r[rep] = ok ? Br[o] : 0.0;
+        rb_i[rep] = ok ? Bi[o] : 0.0;
       }
     } else {
-      const int kk = tid & 15, kg = k0 + kk;
+      const int kg = k0 + (tid & 15);
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
-        const int c = (tid >> 4) + 16 * rep, j = col0 + c;
-        double vr = 0.0, vi = 0.0;
-        if (j < g.n && kg < g.k) {
-          const int64_t o = (int64_t)j * g.ldb + kg;
-          vr = Br[o];
-          vi = -Bi[o];
-        }
-        put<PREC>(Bs_r, kk, c, vr);
-        put<PREC>(Bs_i, kk, c, vi);
+        const int j = col0 + (tid >> 4) + 16 * rep;
+        const bool ok = j < g.n && kg < g.k;
+        const int64_t o = (int64_t)j * g.ldb + kg;
+        rb_r[rep] = ok ? Br[o] : 0.0;
+        rb_i[rep] = ok ? -Bi[o] : 0.0;
       }
     }
+  };
+  auto stage = [&]() {
+    if (!g.transA) {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep) {
+        put<PREC>(As_r, tid & 15, (tid >> 4) + 16 * rep, ra_r[rep]);
+        put<PREC>(As_i, tid & 15, (tid >> 4) + 16 * rep, ra_i[rep]);
+      }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep) {
+        put<PREC>(As_r, (tid >> 6) + 4 * rep, tid & 63, ra_r[rep]);
+        put<PREC>(As_i, (tid >> 6) + 4 * rep, tid & 63, ra_i[rep]);
+      }
+    }
+    if (!g.transB) {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep) {
+        put<PREC>(Bs_r, (tid >> 6) + 4 * rep, tid & 63, rb_r[rep]);
+        put<PREC>(Bs_i, (tid >> 6) + 4 * rep, tid & 63, rb_i[rep]);
+      }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep) {
+        put<PREC>(Bs_r, tid & 15, (tid >> 4) + 16 * rep, rb_r[rep]);
+        put<PREC>(Bs_i, tid & 15, (tid >> 4) + 16 * rep, rb_i[rep]);
+      }
+    }
+  };
+
+  load(0);
+  for (int k0 = 0; k0 < g.k; k0 += BK) {
+    stage();
     __syncthreads();
+    if (k0 + BK < g.k) load(k0 + BK);
 
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
@@ -209,6 +238,11 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
             Cr[o] = vr;
             Ci[o] = vi;
           }
+          if (g.herm_out && tile_c < tile_r) {   // mirror into the upper triangle
+            const int64_t om = (int64_t)j * g.ldc + i;
+            Cr[om] = vr;
+            Ci[om] = -vi;
+          }
         }
       }
 }
@@ -219,6 +253,13 @@ void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
   if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return;
   if (a.k <= 0) throw Error(-1, "zgemm: k must be positive");
   dim3 grid(ceil_div(a.n, BN), ceil_div(a.m, BM), a.batch);
+  if (a.herm_out) {
+    // C = X X^+ is Hermitian: only tiles on or below the diagonal are computed
+    if (a.m != a.n || a.beta || a.col_scale != a.row_scale || a.col_div != a.row_div)
+      throw Error(-1, "zgemm: Hermitian output needs a square, overwritten, symmetrically scaled C");
+    const int T = ceil_div(a.m, BM);
+    grid = dim3(T * (T + 1) / 2, 1, a.batch);
+  }
   if (grid.y > 65535 || grid.z > 65535) throw Error(-1, "zgemm: grid too large");
   // algorithmic work: a Hermitian Gram product counts as a rank-k update
   const double flops = a.herm_out ? 4.0 * a.m * a.m * (double)a.k * a.batch

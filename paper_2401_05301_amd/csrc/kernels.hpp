@@ -102,6 +102,11 @@ void select_truncate(const double* vals, int r, int is_gram, int chi_max, double
 void fill_random(double* p, int64_t n, uint64_t seed, hipStream_t s);
 // Rows of X scaled to unit 2-norm (zero rows stay zero).
 void normalize_rows(double* xr, double* xi, int64_t ldx, int r, int c, double* norms, hipStream_t s);
+// Y_i <- Z_i + beta_i (Y_i - theta_i Z_i) on p rows of length r, with
+// beta_i = 1 / max(theta_i, |Y_i - theta_i Z_i| / gamma, damp_rel * max theta),
+// and beta_i = 0 where theta_i <= zero_rel * max theta.
+void damped_power_rows(const double* zr, const double* zi, double* yr, double* yi, int64_t ld, int p, int r,
+                       const double* theta, double gamma, double damp_rel, double zero_rel, hipStream_t s);
 // out[i] = 1 / sqrt(max(d[i], floor)) with floor = rel * max_j d[j] (0 if d[i] <= floor).
 void inv_sqrt_clamped(const double* d, int n, double rel, double* out, hipStream_t s);
 // *out = max(0, trace - sum_i vals[i]), trace = sum of diag of H.
@@ -130,5 +135,7 @@ void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s);
 void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d,
                int cr, double* out, hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
+// *acc += sum_{i<n} slots[i], summed in index order by one thread.
+void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s);
 
 }  // namespace ptebd

@@ -8,6 +8,7 @@ Profiler*& active_profiler() {
 }
 
 hipEvent_t Profiler::get() {
+  std::lock_guard<std::mutex> lk(mu);
   if (!pool.empty()) {
     hipEvent_t e = pool.back();
     pool.pop_back();
@@ -41,7 +42,10 @@ ProfScope::ProfScope(int cls_, double flops_, hipStream_t s_) : p(active_profile
 ProfScope::~ProfScope() {
   if (p && a) {
     hipEvent_t b = p->get();
-    if (hipEventRecord(b, s) == hipSuccess) p->recs.push_back({cls, flops, a, b});
+    if (hipEventRecord(b, s) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(p->mu);
+      p->recs.push_back({cls, flops, a, b});
+    }
   }
 }
 

@@ -1,6 +1,7 @@
 // Per-launch timing of the library's kernels with HIP events (opt-in).
 #pragma once
 
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -18,6 +19,7 @@ struct Profiler {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  std::mutex mu;   // launchers of several worker threads report here
   hipEvent_t get();
   void clear();
   ~Profiler();

@@ -111,3 +111,29 @@ def test_gram_subspace_topk(pt, m, n, chi):
     P = vh.conj().T @ vh
     Pr = vh_ref[:k].conj().T @ vh_ref[:k]
     assert np.abs(P - Pr).max() < 1e-6
+
+
+@pytest.mark.parametrize("m,n,rank,chi", [(700, 900, 150, 128), (900, 700, 1, 64), (1100, 2600, 300, 256)])
+def test_gram_subspace_rank_deficient(pt, m, n, rank, chi):
+    """Subspace route on a Gram matrix whose rank lies below the subspace
+    width (as for an identity gate on a state of exact bond dimension), with
+    a steep spectrum inside the rank."""
+    rng = np.random.default_rng(m + n + rank)
+    U, _ = np.linalg.qr(rand_c(rng, m, rank))
+    V, _ = np.linalg.qr(rand_c(rng, n, rank))
+    s_true = np.exp(-np.arange(rank) / (rank / 12.0))
+    A = (U * s_true) @ V.conj().T
+    note(f"gram subspace rank-deficient m={m} n={n} rank={rank} chi={chi}")
+    s, vh, nrm, w, sweeps = pt.tebd_diag_svd(A, variant=1, chi_max=chi, w_max=1e-14, eps=1e-12)
+    k = len(s)
+    sv = np.sort(s_true)[::-1]
+    assert k == min(chi, rank) or (k < min(chi, rank) and sv[k] <= 1e-6 * sv[0])
+    assert np.abs(s * nrm - sv[:k]).max() < 1e-9 * sv[0]
+    # the Gram route resolves a singular vector to ~u / (relative gap * s_i^2):
+    # near-orthonormal rows, exact to rounding once weighted by the values
+    E = vh @ vh.conj().T - np.eye(k)
+    assert np.abs(E).max() < 1e-4
+    sk = sv[:k]
+    assert np.abs(sk[:, None] * E * sk[None, :]).max() < 1e-12
+    # the kept rows lie in the row space of A
+    assert np.linalg.norm(vh - (vh @ V) @ V.conj().T) < 1e-6 * np.sqrt(k)

@@ -158,3 +158,24 @@ def test_random_state_layers_chi48(pt, svd):
         tol = max(tol, 2 * om.w_total)
     assert max(errs) < tol
     assert g.bond_dims() == om.bond_dims()
+
+
+def test_layer_workers_give_identical_results(pt):
+    """Gates of a layer spread over four concurrent workers give bit-identical
+    observables, Schmidt values and ledger to one worker."""
+    L, d, chi = 14, 4, 24
+    B, lam = random_mps(L, d, chi, seed=3, tau=6.0)
+    m = Model(L=L, d=d, U=3.0, J=1.0, Jnnn=0.1, K=0.02)
+    res = []
+    for workers in (1, 4):
+        note(f"workers={workers}")
+        g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12, svd=1, workers=workers), B, lam)
+        g.step(0.02)
+        g.step(0.02)
+        n, C, D = g.measure()
+        res.append((n, C, D, [g.lam(b) for b in range(L + 1)], g.discarded_weight()))
+        g.close()
+    a, b = res
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert all(np.array_equal(x, y) for x, y in zip(a[3], b[3]))
+    assert a[4] == b[4]

@@ -92,16 +92,19 @@ def bulk_bond_dims(L: int, d: int, chi: int) -> List[int]:
 
 
 def random_mps(L: int, d: int, chi: int, seed: int = 0, tau: float = 30.0,
-               bonds: List[int] | None = None) -> Tuple[List[np.ndarray], List[np.ndarray]]:
+               bonds: List[int] | None = None, bias: float | None = None
+               ) -> Tuple[List[np.ndarray], List[np.ndarray]]:
     """Random MPS in (B, Lambda) form with right-orthonormal B tensors.
 
     B_i has shape (chi_i, d, chi_{i+1}); its (chi_i) x (d chi_{i+1}) matrix
     has orthonormal rows (drawn as the conjugate transpose of the Q factor
-    of a complex Gaussian).  Lambda_b is a decaying profile
-    s_k ~ exp(-k / tau) normalised to unit 2-norm; Lambda_0 = Lambda_L = [1].
-    The profile is imposed, not derived, so the state is right-canonical
-    but not left-canonical: a throughput input of the right shapes and of a
-    graded spectrum, fed identically to both implementations.
+    of a complex Gaussian).  With ``bias`` the Gaussian's column for right
+    bond index b is weighted by exp(-b / bias), so that the row space leans
+    on the first right indices and the Schmidt spectra of the state decay
+    (roughly as exp(-k / bias)) instead of being flat.  Lambda_b is a decaying
+    profile s_k ~ exp(-k / tau) normalised to unit 2-norm; Lambda_0 =
+    Lambda_L = [1].  The profile is imposed, not derived, so the state is
+    right-canonical but not left-canonical until it is canonicalised.
     """
     rng = np.random.default_rng(seed)
     if bonds is None:
@@ -110,6 +113,8 @@ def random_mps(L: int, d: int, chi: int, seed: int = 0, tau: float = 30.0,
     for i in range(L):
         cl, cr = bonds[i], bonds[i + 1]
         g = rng.standard_normal((d * cr, cl)) + 1j * rng.standard_normal((d * cr, cl))
+        if bias is not None:
+            g *= np.tile(np.exp(-np.arange(cr) / bias), d)[:, None]
         q, _ = np.linalg.qr(g)
         B.append(np.ascontiguousarray(q.conj().T.reshape(cl, d, cr)))
     lam = []
