@@ -74,12 +74,13 @@ def main():
     ap.add_argument("--svd", choices=["gram", "jacobi"], default="gram")
     ap.add_argument("--prec", choices=["fp64", "fp32", "split"], default="fp64")
     ap.add_argument("--tau", type=float, default=110.0, help="decay length of the imposed Lambda profile")
-    ap.add_argument("--bias", type=float, default=120.0,
+    ap.add_argument("--bias", type=float, default=150.0,
                     help="decay length of the right-index weighting that shapes the canonical Schmidt spectra")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-canonicalize", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-chi", type=int, default=512)
+    ap.add_argument("--workers", type=int, default=0, help="concurrent gate workers per layer (0: library default)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,7 +108,7 @@ def main():
     B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
     log(f"synthetic input L={L} d={d} chi={chi} generated in {time.perf_counter() - t0:.1f} s")
     model = pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre())
-    opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream)
+    opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream, workers=args.workers)
     keep = pt.torch_allocator(opts, stream=stream)
     g = pt.MPS.from_tensors(model, opts, B, lam)
     g._keep = keep

@@ -101,6 +101,7 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
       M.nY2 = z((int64_t)sp * sp);
       M.nZ2 = z((int64_t)sp * sp);
       M.ns_part = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * 256));
+      M.ratio_bits = static_cast<unsigned long long*>(ptebd::dev_alloc(&M, sizeof(unsigned long long)));
     }
     const int64_t nbk = (r + 15) / 16 + 2;
     M.part_cap = (nbk / 2 + 1) * 16 * 1536;
@@ -113,6 +114,7 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     PTEBD_HIP(hipHostMalloc((void**)&M.h_counter, 64, hipHostMallocDefault));
     PTEBD_HIP(hipHostMalloc((void**)&M.h_info, 64, hipHostMallocDefault));
     PTEBD_HIP(hipHostMalloc((void**)&M.h_part, 256 * sizeof(double), hipHostMallocDefault));
+    PTEBD_HIP(hipHostMalloc((void**)&M.h_ratio, sizeof(unsigned long long), hipHostMallocDefault));
     PTEBD_HIP(hipMemcpy(a.re, A, sizeof(double) * m * n, hipMemcpyHostToDevice));
     PTEBD_HIP(hipMemcpy(a.im, A + (int64_t)m * n, sizeof(double) * m * n, hipMemcpyHostToDevice));
     PTEBD_HIP(hipMemset(M.ledger, 0, sizeof(double)));
@@ -147,8 +149,8 @@ extern "C" tebd_status tebd_diag_zgemm_time(int32_t prec, int32_t m, int32_t n, 
     double* a = sc.alloc(2 * na);
     double* b = sc.alloc(2 * nb);
     double* c = sc.alloc(2 * nc);
-    ptebd::fill_zero(a, 2 * na, nullptr);
-    ptebd::fill_zero(b, 2 * nb, nullptr);
+    ptebd::fill_random(a, 2 * na, 0x1234ull, nullptr);
+    ptebd::fill_random(b, 2 * nb, 0x5678ull, nullptr);
     ptebd::ZGemmArgs g;
     g.m = m; g.n = n; g.k = k;
     g.ar = a; g.ai = a + na; g.lda = k;

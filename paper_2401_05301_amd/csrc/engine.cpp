@@ -26,6 +26,9 @@ namespace {
 
 constexpr int kNsplitMax = 16;
 constexpr double kGramSigmaFloor = 1e-6;   // Gram route: singular values below this (relative) are noise
+constexpr double kDampRel = 1e-10;         // subspace iteration: power-step scale floor (relative to the top value)
+constexpr double kDiagCoupling = 0.05;     // subspace iteration: largest relative coupling treated as diagonal
+constexpr int kPartialSweeps = 2;          // subspace iteration: Jacobi sweeps of an intermediate rotation
 
 int64_t ipow_cap(int d, int e, int cap) {
   int64_t v = 1;
@@ -161,6 +164,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
     W->nY2 = zalloc(W, s.sub_p * s.sub_p);
     W->nZ2 = zalloc(W, s.sub_p * s.sub_p);
     W->ns_part = dalloc(W, 256);
+    W->ratio_bits = static_cast<unsigned long long*>(dev_alloc(W, sizeof(unsigned long long)));
   }
   W->part = dalloc(W, s.part);
   W->part_cap = s.part;
@@ -170,6 +174,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   PTEBD_HIP(hipHostMalloc((void**)&W->h_counter, 64, hipHostMallocDefault));
   PTEBD_HIP(hipHostMalloc((void**)&W->h_info, 64, hipHostMallocDefault));
   PTEBD_HIP(hipHostMalloc((void**)&W->h_part, 256 * sizeof(double), hipHostMallocDefault));
+  PTEBD_HIP(hipHostMalloc((void**)&W->h_ratio, sizeof(unsigned long long), hipHostMallocDefault));
 }
 
 }  // namespace
@@ -242,6 +247,8 @@ void mps_release(tebd_mps* M) {
   if (M->h_counter) (void)hipHostFree(M->h_counter);
   if (M->h_info) (void)hipHostFree(M->h_info);
   if (M->h_part) (void)hipHostFree(M->h_part);
+  if (M->h_ratio) (void)hipHostFree(M->h_ratio);
+  M->h_ratio = nullptr;
   M->h_counter = nullptr;
   M->h_info = nullptr;
   M->h_part = nullptr;
@@ -374,10 +381,13 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
 // Truncated SVD of diag(rs) A.  Writes the kept normalised singular values
 // into lam_out, V^+ rows into (vhr, vhi) with leading dimension n, the norm of
 // the kept values into info_d[2*slot] and returns k.
-// Off-diagonal target of the Hermitian Jacobi in units of u ||H||_F (the
-// Gram matrices carry absolute errors of ~sqrt(k) u ||M||^2 themselves).
+// Off-diagonal target of the Hermitian Jacobi in units of u trace(H).  The
+// entries of a Gram matrix M M^+ carry absolute errors of order
+// u sqrt(k) |m_i| |m_j| themselves; an unresolved off-diagonal entry delta
+// leaves the Schmidt basis off diagonal by delta, an error of that size in
+// the local observables.
 double herm_tol_units() {
-  static const double v = std::getenv("PTEBD_HERM_TOL") ? std::atof(std::getenv("PTEBD_HERM_TOL")) : 32.0;
+  static const double v = std::getenv("PTEBD_HERM_TOL") ? std::atof(std::getenv("PTEBD_HERM_TOL")) : 64.0;
   return v;
 }
 
@@ -388,7 +398,10 @@ int inner_sweeps() {
 
 // Two-sided block Jacobi on the Hermitian H (n x n) in place, eigenvector rows
 // accumulated into W (set to the identity first).  Returns the sweeps used.
-int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, double* wr, double* wi, int64_t ldw) {
+// With sweep_cap > 0 at most that many sweeps run and an unconverged H is
+// returned as it stands (partial diagonalisation), without an error.
+int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, double* wr, double* wi, int64_t ldw,
+                    int sweep_cap = 0) {
   hipStream_t s = M->stream;
   int nb = (n + 15) / 16;
   if (nb < 2) nb = 2;
@@ -404,10 +417,10 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
   a.flag = M->flags;
   a.inner_sweeps = inner_sweeps();
   a.rotated = M->counter;
-  herm_tol(hr, hi, ldh, n, herm_tol_units(), M->info_d + 7, s);
+  herm_tol(hr, ldh, n, herm_tol_units(), M->info_d + 7, s);
   a.tol_abs = M->info_d + 7;
   if (wr) set_identity(wr, wi, ldw, n, s);
-  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
+  const int max_sweeps = sweep_cap > 0 ? sweep_cap : (M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40);
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
     PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
     for (int t = 0; t < nb - 1; ++t) herm_round(a, t, s);
@@ -421,6 +434,7 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
       return sweep;
     }
   }
+  if (sweep_cap > 0) return sweep_cap;
   M->failed = true;
   throw Error(-4, "Hermitian Jacobi did not converge within max_sweeps (n " + std::to_string(n) + ")");
 }
@@ -496,6 +510,17 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
   }
 }
 
+// H = Y Z^+ (p x p) for the basis rows Z and their images Y = Z G.
+void rayleigh(tebd_mps* M, int p, int r) {
+  ZGemmArgs h;
+  h.m = p; h.n = p; h.k = r;
+  h.ar = M->sY.re; h.ai = M->sY.im; h.lda = r;
+  h.br = M->sZ.re; h.bi = M->sZ.im; h.ldb = r; h.transB = 1;
+  h.cr = M->sH.re; h.ci = M->sH.im; h.ldc = p;
+  h.herm_out = 1;   // Z G Z^+ is Hermitian
+  zgemm(h, 0, M->stream);
+}
+
 // Top-p eigenpairs of the Hermitian PSD G (r x r) by subspace iteration with
 // Rayleigh-Ritz.  On return sZ holds the Ritz vectors as rows (conjugated,
 // as W in run_herm_jacobi), M->norms the Ritz values, and info_d[5] the
@@ -531,7 +556,7 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     u.cr = rnd.re; u.ci = rnd.im; u.ldc = r;
     u.alpha = -1.0; u.beta = 1;
     zgemm(u, 0, s);
-    lowdin(M, M->sZ, M->sZ2, p, r);
+    lowdin(M, rnd, M->sZ2, p - kw, r, true);
   } else {
     lowdin(M, M->sZ, M->sZ2, p, r);
     lowdin(M, M->sZ, M->sZ2, p, r);
@@ -544,37 +569,50 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
   double prev_kept = 0.0;
   std::vector<double> prev(keep, 0.0);
   const int max_it = 30;
-  for (int it = 0; it < max_it; ++it) {
-    // Y = Z G (rows: (G z_i)^+), H = Y Z^+
+  auto image = [&]() {   // Y = Z G (rows: (G z_i)^+), H = Y Z^+
     ZGemmArgs g;
     g.m = p; g.n = r; g.k = r;
     g.ar = M->sZ.re; g.ai = M->sZ.im; g.lda = r;
     g.br = gr; g.bi = gi; g.ldb = r;
     g.cr = M->sY.re; g.ci = M->sY.im; g.ldc = r;
     zgemm(g, 0, s);
-    ZGemmArgs h;
-    h.m = p; h.n = p; h.k = r;
-    h.ar = M->sY.re; h.ai = M->sY.im; h.lda = r;
-    h.br = M->sZ.re; h.bi = M->sZ.im; h.ldb = r; h.transB = 1;
-    h.cr = M->sH.re; h.ci = M->sH.im; h.ldc = p;
-    h.herm_out = 1;   // Z G Z^+ is Hermitian
-    zgemm(h, 0, s);
-    run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p);
+    rayleigh(M, p, r);
+  };
+  // rows [r0, r0 + n) of Z (and Y) <- Q rows [r0, r0 + n), Q (n x n, leading dimension n)
+  auto rotate = [&](const tebd_mps::Z& Q, int r0, int n, bool also_y) {
+    for (int t = 0; t < (also_y ? 2 : 1); ++t) {
+      tebd_mps::Z& X = t == 0 ? M->sZ : M->sY;
+      tebd_mps::Z& T = t == 0 ? M->sZ2 : M->sY2;
+      ZGemmArgs q;
+      q.m = n; q.n = r; q.k = n;
+      q.ar = Q.re; q.ai = Q.im; q.lda = n;
+      q.br = X.re + (size_t)r0 * r; q.bi = X.im + (size_t)r0 * r; q.ldb = r;
+      q.cr = T.re + (size_t)r0 * r; q.ci = T.im + (size_t)r0 * r; q.ldc = r;
+      zgemm(q, 0, s);
+      if (r0 == 0 && n == p) {
+        std::swap(X, T);
+      } else {
+        PTEBD_HIP(hipMemcpyAsync(X.re + (size_t)r0 * r, T.re + (size_t)r0 * r, sizeof(double) * (size_t)n * r,
+                                 hipMemcpyDeviceToDevice, s));
+        PTEBD_HIP(hipMemcpyAsync(X.im + (size_t)r0 * r, T.im + (size_t)r0 * r, sizeof(double) * (size_t)n * r,
+                                 hipMemcpyDeviceToDevice, s));
+      }
+    }
+  };
+  const double u = 1.1102230246251565e-16;
+  std::vector<double> h_vals(p);
+  for (int it = 0; it < max_it; ++it) {
+    image();
+    if (it == 0 && kw > 0 && kw < p) {
+      // The random rows carry no structure: diagonalise their own block
+      // first, so that H is nearly diagonal as a whole.
+      const int nr = p - kw;
+      run_herm_jacobi(M, M->sH.re + (size_t)kw * p + kw, M->sH.im + (size_t)kw * p + kw, p, nr, M->sW.re,
+                      M->sW.im, nr);
+      rotate(M->sW, kw, nr, true);
+      rayleigh(M, p, r);
+    }
     herm_diag(M->sH.re, p, p, M->norms, s);
-    // Ritz rotation of the basis and of its image
-    ZGemmArgs q;
-    q.m = p; q.n = r; q.k = p;
-    q.ar = M->sW.re; q.ai = M->sW.im; q.lda = p;
-    q.br = M->sZ.re; q.bi = M->sZ.im; q.ldb = r;
-    q.cr = M->sZ2.re; q.ci = M->sZ2.im; q.ldc = r;
-    zgemm(q, 0, s);
-    std::swap(M->sZ, M->sZ2);
-    q.br = M->sY.re; q.bi = M->sY.im;
-    q.cr = M->sY2.re; q.ci = M->sY2.im;
-    zgemm(q, 0, s);
-    std::swap(M->sY, M->sY2);
-    // convergence of the largest `keep` Ritz values
-    std::vector<double> h_vals(p);
     PTEBD_HIP(hipMemcpyAsync(h_vals.data(), M->norms, sizeof(double) * p, hipMemcpyDeviceToHost, s));
     PTEBD_HIP(hipStreamSynchronize(s));
     std::sort(h_vals.begin(), h_vals.end(), std::greater<double>());
@@ -584,25 +622,60 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       delta = std::max(delta, std::fabs(h_vals[i] - prev[i]));
       prev[i] = h_vals[i];
     }
-    if (debug_enabled())
-      std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d captured=%.15e gain=%.3e delta=%.3e top=%.6e\n", r, p,
-                   it, kept, kept - prev_kept, delta, h_vals[0]);
-    // The sum of the largest `keep` Ritz values is the weight the kept
-    // subspace captures; it grows monotonically towards the optimum.  Stop
-    // once an iteration gains less than 1e-4 of the weight still outside
-    // (or less than the rounding level of G) and no kept Ritz value moved by
-    // more than 1e-10 of the largest.
-    const double u = 1.1102230246251565e-16;
-    if (it >= 1 && kept - prev_kept <= std::max(1e-4 * (trace - kept), 64 * u * trace) &&
-        delta <= 1e-10 * h_vals[0])
-      break;
+    // The sum of the largest `keep` Rayleigh quotients is the weight the
+    // kept subspace captures; it grows monotonically towards the optimum.
+    // Stop once an iteration gains less than 1e-4 of the weight still
+    // outside (or less than the rounding level of G) and no kept value moved
+    // by more than 1e-10 of the largest.
+    const double gain = kept - prev_kept;
+    const bool done = (it >= 1 && gain <= std::max(1e-4 * (trace - kept), 64 * u * trace) &&
+                       delta <= 1e-10 * h_vals[0]) ||
+                      it == max_it - 1;
     prev_kept = kept;
-    // next basis: orthonormalised (damped) image of the Ritz vectors.  A
-    // plain image G Z has rows spread over the whole dynamic range of G and
-    // is too ill-conditioned to orthonormalise by Newton-Schulz; scaling
-    // each image by its Ritz value and capping the residual step keeps the
-    // rows near orthonormal.
-    damped_power_rows(M->sZ.re, M->sZ.im, M->sY.re, M->sY.im, r, p, r, M->norms, 1.0, 1e-10,
+    if (done) {
+      // final Rayleigh-Ritz: exact eigenvectors of H
+      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p);
+      herm_diag(M->sH.re, p, p, M->norms, s);
+      rotate(M->sW, 0, p, false);
+      if (debug_enabled())
+        std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d captured=%.15e delta=%.3e top=%.6e final\n", r, p,
+                     it, kept, delta, h_vals[0]);
+      break;
+    }
+    // Next basis.  The exact power step spans the rows of Z + H^-1 R with
+    // the block residual R = Y - H Z (orthogonal to every basis row).  When
+    // the couplings of H are small against its diagonal (relative to
+    // sqrt(H_ii H_jj), with the damping floor), diag(H) stands in for H.
+    // Otherwise a few Jacobi sweeps first rotate the basis towards the Ritz
+    // vectors; they need not converge, since the residual is taken against
+    // the rotated H as it stands.
+    herm_tol(M->sH.re, p, p, herm_tol_units(), M->info_d + 7, s);
+    const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, kDampRel * h_vals[0], M->ratio_bits,
+                                       M->h_ratio, s);
+    const bool jac = !(ratio <= kDiagCoupling);
+    if (jac) {
+      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, kPartialSweeps);
+      herm_diag(M->sH.re, p, p, M->norms, s);
+      rotate(M->sW, 0, p, true);
+    }
+    {  // Y <- Y - (H - diag(H)) Z: row i becomes theta_i z_i + residual
+      zero_diag(M->sH.re, M->sH.im, p, p, s);
+      ZGemmArgs q;
+      q.m = p; q.n = r; q.k = p;
+      q.ar = M->sH.re; q.ai = M->sH.im; q.lda = p;
+      q.br = M->sZ.re; q.bi = M->sZ.im; q.ldb = r;
+      q.cr = M->sY.re; q.ci = M->sY.im; q.ldc = r;
+      q.alpha = -1.0; q.beta = 1;
+      zgemm(q, 0, s);
+    }
+    if (debug_enabled())
+      std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d captured=%.15e gain=%.3e delta=%.3e top=%.6e %s %.2e\n",
+                   r, p, it, kept, gain, delta, h_vals[0], jac ? "jacobi" : "residual", ratio);
+    // Damped power step: a plain image G Z has rows spread over the whole
+    // dynamic range of G and is too ill-conditioned to orthonormalise by
+    // Newton-Schulz; scaling each image by its Ritz value and capping the
+    // residual step keeps the rows near orthonormal.
+    damped_power_rows(M->sZ.re, M->sZ.im, M->sY.re, M->sY.im, r, p, r, M->norms, 1.0, kDampRel,
                       kGramSigmaFloor * kGramSigmaFloor, s);
     std::swap(M->sZ, M->sY);
     lowdin(M, M->sZ, M->sZ2, p, r);

@@ -38,6 +38,8 @@ struct tebd_mps {
   Z nY, nZ, nY2, nZ2;           // Newton-Schulz iterates (p x p)
   double* ns_part = nullptr;    // Newton-Schulz residual partial sums (256)
   double* h_part = nullptr;     // pinned host mirror of ns_part
+  unsigned long long* ratio_bits = nullptr;   // perturbative Rayleigh-Ritz: max coupling / gap (bits of a double)
+  unsigned long long* h_ratio = nullptr;      // pinned host mirror
   int sub_p = 0;                // subspace width reserved (0: not reserved)
   int* flags = nullptr;         // per block pair flags of the Hermitian Jacobi
   Z E, F, F2, F3;

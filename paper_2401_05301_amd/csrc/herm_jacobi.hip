@@ -2,7 +2,7 @@
 //
 // Used on Gram matrices, whose entries carry an absolute error of order
 // u * ||H||: rotations stop once every off-diagonal entry is below
-// tol_abs = c u ||H||_F, the accuracy the Gram matrix can support.  Blocks of
+// tol_abs = c u trace(H), the accuracy the Gram matrix can support.  Blocks of
 // 16 rows/columns are paired round-robin; per round:
 //   herm_eig   : each pair's 32 x 32 diagonal block S = H[R, R] is
 //                diagonalised in LDS by cyclic rotations, S = Q D Q^+;
@@ -11,6 +11,9 @@
 //                W[R, :] <- Q^+ W[R, :] accumulates the eigenvectors.
 // At convergence H is diagonal (eigenvalues) and W H0 W^+ = H, so the rows
 // of W are the conjugated eigenvectors.
+#include <algorithm>
+#include <cstring>
+
 #include "kernels.hpp"
 #include "profile.hpp"
 
@@ -311,22 +314,55 @@ __global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void fro_tol_kernel(const double* hr, const double* hi, int64_t ldh, int n,
-                                                      double c, double* out) {
+// Absolute off-diagonal target c u sum_i |H_ii|: for the positive
+// semi-definite Gram matrices this is c units of rounding of their trace,
+// the scale of the absolute error their entries carry.
+__global__ __launch_bounds__(256) void trace_tol_kernel(const double* hr, int64_t ldh, int n, double c, double* out) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) {
-    const int64_t i = e / n, j = e % n;
-    const double x = hr[i * ldh + j], y = hi[i * ldh + j];
-    acc += x * x + y * y;
-  }
+  for (int i = threadIdx.x; i < n; i += 256) acc += fabs(hr[(int64_t)i * ldh + i]);
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = c * 1.1102230246251565e-16 * sqrt(sh[0]);
+  if (threadIdx.x == 0) out[0] = c * 1.1102230246251565e-16 * sh[0];
+}
+
+// Largest relative coupling |H_ij| / sqrt(max(H_ii, f) max(H_jj, f)) over
+// the off-diagonal entries with |H_ij| > tol, for a Hermitian positive
+// semi-definite H and a floor f > 0.  Far below 1, the diagonal of H stands
+// in for H itself in H^-1 (with the floor).  The value goes to *ratio_bits as
+// the bit pattern of a non-negative double, so that an integer maximum
+// orders it.
+__global__ __launch_bounds__(256) void offdiag_ratio_kernel(const double* hr, const double* hi, int64_t ldh, int p,
+                                                            const double* tol, double f,
+                                                            unsigned long long* ratio_bits) {
+  const double t = *tol;
+  double worst = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)p * p;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p), j = (int)(e % p);
+    if (i >= j) continue;
+    const double mag = hypot(hr[(int64_t)i * ldh + j], hi[(int64_t)i * ldh + j]);
+    if (mag > t) {
+      const double di = fmax(hr[(int64_t)i * ldh + i], f), dj = fmax(hr[(int64_t)j * ldh + j], f);
+      worst = fmax(worst, mag / sqrt(di * dj));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off));
+  if ((threadIdx.x & 63) == 0 && worst > 0.0) atomicMax(ratio_bits, (unsigned long long)__double_as_longlong(worst));
+}
+
+// H_ii = 0 for i < p.
+__global__ void zero_diag_kernel(double* hr, double* hi, int64_t ldh, int p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p) {
+    hr[(int64_t)i * ldh + i] = 0.0;
+    hi[(int64_t)i * ldh + i] = 0.0;
+  }
 }
 
 __global__ void diag_kernel(const double* hr, int64_t ldh, int n, double* out) {
@@ -336,8 +372,8 @@ __global__ void diag_kernel(const double* hr, int64_t ldh, int n, double* out) {
 
 }  // namespace
 
-void herm_tol(const double* hr, const double* hi, int64_t ldh, int n, double c, double* out, hipStream_t s) {
-  fro_tol_kernel<<<1, 256, 0, s>>>(hr, hi, ldh, n, c, out);
+void herm_tol(const double* hr, int64_t ldh, int n, double c, double* out, hipStream_t s) {
+  trace_tol_kernel<<<1, 256, 0, s>>>(hr, ldh, n, c, out);
   PTEBD_LAUNCH_CHECK();
 }
 
@@ -360,6 +396,25 @@ void herm_round(HermArgs a, int round, hipStream_t s) {
 
 void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s) {
   diag_kernel<<<ceil_div(n, 256), 256, 0, s>>>(hr, ldh, n, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double floor,
+                     unsigned long long* ratio_bits, unsigned long long* h_ratio, hipStream_t s) {
+  PTEBD_HIP(hipMemsetAsync(ratio_bits, 0, sizeof(unsigned long long), s));
+  const int64_t n = (int64_t)p * p;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  offdiag_ratio_kernel<<<grid, 256, 0, s>>>(hr, hi, ldh, p, tol, floor, ratio_bits);
+  PTEBD_LAUNCH_CHECK();
+  PTEBD_HIP(hipMemcpyAsync(h_ratio, ratio_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  double v;
+  std::memcpy(&v, h_ratio, sizeof(double));
+  return v;
+}
+
+void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s) {
+  zero_diag_kernel<<<ceil_div(p, 256), 256, 0, s>>>(hr, hi, ldh, p);
   PTEBD_LAUNCH_CHECK();
 }
 

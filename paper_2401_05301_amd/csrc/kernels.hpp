@@ -64,8 +64,15 @@ struct HermArgs {
   int round;
   int inner_sweeps;                         // sweeps of the 32 x 32 pair solve per visit
 };
-// *out = c * u * ||H||_F
-void herm_tol(const double* hr, const double* hi, int64_t ldh, int n, double c, double* out, hipStream_t s);
+// Largest |H_ij| / sqrt(max(H_ii, floor) max(H_jj, floor)) over the
+// off-diagonal entries above *tol of a Hermitian PSD H (synchronises; 0 when
+// none is above tol).
+double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double floor,
+                     unsigned long long* ratio_bits, unsigned long long* h_ratio, hipStream_t s);
+// H_ii = 0, i < p.
+void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s);
+// *out = c * u * sum_i |H_ii|
+void herm_tol(const double* hr, int64_t ldh, int n, double c, double* out, hipStream_t s);
 void herm_round(HermArgs a, int round, hipStream_t s);
 // out[i] = Re H(i, i)
 void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s);
