@@ -21,10 +21,12 @@ extern "C" {
  * op(A) is A (stored m x k, leading dimension k) when transA == 0, or the
  * conjugate transpose of A stored k x m (leading dimension m) when transA == 1;
  * op(B) likewise (stored k x n, or n x k).  k_scale[k], row_scale[m],
- * col_scale[n] may be NULL.  prec is a tebd_precision. */
+ * col_scale[n] may be NULL.  prec is a tebd_precision.  herm != 0 declares
+ * the product Hermitian (m == n, op(B) = op(A)^+, row_scale == col_scale):
+ * only the lower tiles are computed and mirrored, as for Gram matrices. */
 tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
                             const double* A, const double* B, const double* k_scale, const double* row_scale,
-                            const double* col_scale, double* C);
+                            const double* col_scale, int32_t herm, double* C);
 
 /* Truncated SVD of A (m x n) with the library's Jacobi engine and the
  * truncation rule of ptebd.h.  variant is a tebd_svd.  Outputs: *k kept

@@ -338,7 +338,7 @@ class MPS:
 def _load_diag():
     P = ctypes.POINTER
     _lib.tebd_diag_zgemm.restype = ctypes.c_int
-    _lib.tebd_diag_zgemm.argtypes = [ctypes.c_int32] * 6 + [P(ctypes.c_double)] * 6
+    _lib.tebd_diag_zgemm.argtypes = [ctypes.c_int32] * 6 + [P(ctypes.c_double)] * 5 + [ctypes.c_int32, P(ctypes.c_double)]
     _lib.tebd_diag_svd.restype = ctypes.c_int
     _lib.tebd_diag_svd.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double),
                                    ctypes.c_int32, ctypes.c_double, ctypes.c_double, P(ctypes.c_int32),
@@ -373,16 +373,17 @@ def _opt(a):
 
 
 def tebd_diag_zgemm(A: np.ndarray, B: np.ndarray, transA: int = 0, transB: int = 0, prec: int = FP64,
-                    k_scale=None, row_scale=None, col_scale=None) -> np.ndarray:
+                    k_scale=None, row_scale=None, col_scale=None, herm: bool = False) -> np.ndarray:
     """op(A) diag(k_scale) op(B) scaled by row/col vectors, computed on the GPU.
-    A and B are given in their stored shapes."""
+    A and B are given in their stored shapes.  herm declares the product
+    Hermitian (lower tiles computed and mirrored)."""
     m, k = (A.shape if not transA else A.shape[::-1])
     n = B.shape[1] if not transB else B.shape[0]
     pa, pb = _planar(A), _planar(B)
     keep = [None if x is None else np.ascontiguousarray(x, dtype=np.float64) for x in (k_scale, row_scale, col_scale)]
     c = np.zeros(2 * m * n)
     _check(_lib.tebd_diag_zgemm(prec, m, n, k, transA, transB, _dptr(pa), _dptr(pb),
-                                *[None if x is None else _dptr(x) for x in keep], _dptr(c)))
+                                *[None if x is None else _dptr(x) for x in keep], int(bool(herm)), _dptr(c)))
     return (c[:m * n] + 1j * c[m * n:]).reshape(m, n)
 
 

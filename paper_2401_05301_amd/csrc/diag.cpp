@@ -31,7 +31,8 @@ struct Scratch {
 
 extern "C" tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
                                        const double* A, const double* B, const double* k_scale,
-                                       const double* row_scale, const double* col_scale, double* C) {
+                                       const double* row_scale, const double* col_scale, int32_t herm,
+                                       double* C) {
   if (m < 1 || n < 1 || k < 1 || !A || !B || !C || prec < 0 || prec > 2) return TEBD_EINVAL;
   try {
     Scratch sc;
@@ -46,7 +47,8 @@ extern "C" tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32
     g.cr = c; g.ci = c + nc; g.ldc = n;
     if (k_scale) g.k_scale = sc.upload(k_scale, k);
     if (row_scale) g.row_scale = sc.upload(row_scale, m);
-    if (col_scale) g.col_scale = sc.upload(col_scale, n);
+    if (col_scale) g.col_scale = (herm && row_scale) ? g.row_scale : sc.upload(col_scale, n);
+    g.herm_out = herm ? 1 : 0;
     ptebd::zgemm(g, prec, nullptr);
     PTEBD_HIP(hipDeviceSynchronize());
     PTEBD_HIP(hipMemcpy(C, c, sizeof(double) * 2 * nc, hipMemcpyDeviceToHost));
@@ -102,6 +104,7 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
       M.nZ2 = z((int64_t)sp * sp);
       M.ns_part = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * 256));
       M.ratio_bits = static_cast<unsigned long long*>(ptebd::dev_alloc(&M, sizeof(unsigned long long)));
+      M.pwork = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * (5 * (size_t)sp + 8)));
     }
     const int64_t nbk = (r + 15) / 16 + 2;
     M.part_cap = (nbk / 2 + 1) * 16 * 1536;

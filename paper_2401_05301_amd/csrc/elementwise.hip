@@ -234,14 +234,67 @@ __global__ __launch_bounds__(256) void tail_rest_kernel(const double* hr, int64_
   if (threadIdx.x == 0) out[0] = fmax(sh[0], 0.0);
 }
 
-__global__ __launch_bounds__(256) void gershgorin_kernel(const double* ar, const double* ai, int p, double* out) {
+// Row sums of |A_ij| of a p x p complex matrix, one wave per row.
+__global__ __launch_bounds__(256) void row_abs_sums_kernel(const double* ar, const double* ai, int p, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= p) return;
+  double acc = 0.0;
+  for (int j = lane; j < p; j += 64) acc += hypot(ar[(int64_t)row * p + j], ai[(int64_t)row * p + j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) out[row] = acc;
+}
+
+// y = A v for a p x p complex A and complex v (planar, v at v[0..p), v[p..2p)), one wave per row.
+__global__ __launch_bounds__(256) void matvec_kernel(const double* ar, const double* ai, int p, const double* v,
+                                                     double* y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= p) return;
+  double sr = 0.0, si = 0.0;
+  for (int j = lane; j < p; j += 64) {
+    const double a = ar[(int64_t)row * p + j], b = ai[(int64_t)row * p + j];
+    const double x = v[j], z = v[p + j];
+    sr += a * x - b * z;
+    si += a * z + b * x;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off);
+    si += __shfl_xor(si, off);
+  }
+  if (lane == 0) {
+    y[row] = sr;
+    y[p + row] = si;
+  }
+}
+
+// v = y / |y|, *lam = |y| (one work-group).
+__global__ __launch_bounds__(256) void normalize_vec_kernel(const double* y, int p, double* v, double* lam) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < 2 * p; i += 256) acc += y[i] * y[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double nrm = sqrt(sh[0]);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int i = threadIdx.x; i < 2 * p; i += 256) v[i] = y[i] * inv;
+  if (threadIdx.x == 0) lam[0] = nrm;
+}
+
+// Scale for the Newton-Schulz iteration of a Hermitian positive definite A:
+// c = min(Gershgorin bound, safety * power-iteration estimate), never below
+// the estimate; out = (c, sqrt(c)).
+__global__ __launch_bounds__(256) void ns_scale_kernel(const double* rowsums, int p, const double* lam_est,
+                                                       double safety, double* out) {
   __shared__ double sh[256];
   double mx = 0.0;
-  for (int i = threadIdx.x; i < p; i += 256) {
-    double rs = 0.0;
-    for (int j = 0; j < p; ++j) rs += hypot(ar[(int64_t)i * p + j], ai[(int64_t)i * p + j]);
-    mx = fmax(mx, rs);
-  }
+  for (int i = threadIdx.x; i < p; i += 256) mx = fmax(mx, rowsums[i]);
   sh[threadIdx.x] = mx;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -249,7 +302,9 @@ __global__ __launch_bounds__(256) void gershgorin_kernel(const double* ar, const
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double c = sh[0] > 0.0 ? sh[0] : 1.0;
+    double c = sh[0];
+    if (lam_est && safety > 0.0 && lam_est[0] > 0.0) c = fmin(c, safety * lam_est[0]);
+    if (!(c > 0.0)) c = 1.0;
     out[0] = c;
     out[1] = sqrt(c);
   }
@@ -300,8 +355,25 @@ __global__ void accumulate_slots_kernel(const double* slots, int n, double* acc)
   acc[0] += t;
 }
 
-void gershgorin(const double* ar, const double* ai, int p, double* out, hipStream_t s) {
-  gershgorin_kernel<<<1, 256, 0, s>>>(ar, ai, p, out);
+void ns_scale(const double* ar, const double* ai, int p, double* work, int power_its, double safety, double* out,
+              hipStream_t s) {
+  // work: row sums [p], v [2p], y [2p], lambda [1]
+  double* rows = work;
+  double* v = work + p;
+  double* y = work + 3 * p;
+  double* lam = work + 5 * p;
+  hipLaunchKernelGGL(row_abs_sums_kernel, dim3(ceil_div(p, 4)), dim3(256), 0, s, ar, ai, p, rows);
+  PTEBD_LAUNCH_CHECK();
+  if (power_its > 0) {
+    fill_random(v, 2 * (int64_t)p, 0x9e3779b97f4a7c15ull, s);
+    for (int it = 0; it < power_its; ++it) {
+      hipLaunchKernelGGL(matvec_kernel, dim3(ceil_div(p, 4)), dim3(256), 0, s, ar, ai, p, v, y);
+      PTEBD_LAUNCH_CHECK();
+      hipLaunchKernelGGL(normalize_vec_kernel, dim3(1), dim3(256), 0, s, y, p, v, lam);
+      PTEBD_LAUNCH_CHECK();
+    }
+  }
+  hipLaunchKernelGGL(ns_scale_kernel, dim3(1), dim3(256), 0, s, rows, p, power_its > 0 ? lam : nullptr, safety, out);
   PTEBD_LAUNCH_CHECK();
 }
 

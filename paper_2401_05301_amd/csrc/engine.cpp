@@ -28,7 +28,6 @@ constexpr int kNsplitMax = 16;
 constexpr double kGramSigmaFloor = 1e-6;   // Gram route: singular values below this (relative) are noise
 constexpr double kDampRel = 1e-10;         // subspace iteration: power-step scale floor (relative to the top value)
 constexpr double kDiagCoupling = 0.05;     // subspace iteration: largest relative coupling treated as diagonal
-constexpr int kPartialSweeps = 2;          // subspace iteration: Jacobi sweeps of an intermediate rotation
 
 int64_t ipow_cap(int d, int e, int cap) {
   int64_t v = 1;
@@ -77,7 +76,7 @@ size_t Sizes::bytes(int workers) const {
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
   int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
   w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
-  w += 6 * vec + part + 64;
+  w += 6 * vec + part + 64 + 5 * sub_p + 8;
   d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
 }
@@ -165,6 +164,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
     W->nZ2 = zalloc(W, s.sub_p * s.sub_p);
     W->ns_part = dalloc(W, 256);
     W->ratio_bits = static_cast<unsigned long long*>(dev_alloc(W, sizeof(unsigned long long)));
+    W->pwork = dalloc(W, 5 * s.sub_p + 8);
   }
   W->part = dalloc(W, s.part);
   W->part_cap = s.part;
@@ -391,8 +391,14 @@ double herm_tol_units() {
   return v;
 }
 
+// Jacobi sweeps of an intermediate rotation of the subspace iteration.
+int partial_sweeps() {
+  static const int v = std::getenv("PTEBD_PARTIAL_SWEEPS") ? std::atoi(std::getenv("PTEBD_PARTIAL_SWEEPS")) : 4;
+  return v;
+}
+
 int inner_sweeps() {
-  static const int v = std::getenv("PTEBD_INNER_SWEEPS") ? std::atoi(std::getenv("PTEBD_INNER_SWEEPS")) : 2;
+  static const int v = std::getenv("PTEBD_INNER_SWEEPS") ? std::atoi(std::getenv("PTEBD_INNER_SWEEPS")) : 1;
   return v;
 }
 
@@ -421,6 +427,7 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
   a.tol_abs = M->info_d + 7;
   if (wr) set_identity(wr, wi, ldw, n, s);
   const int max_sweeps = sweep_cap > 0 ? sweep_cap : (M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40);
+  if (debug_enabled()) std::fprintf(stderr, "[ptebd] herm-jacobi start n=%d cap=%d\n", n, sweep_cap);
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
     PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
     for (int t = 0; t < nb - 1; ++t) herm_round(a, t, s);
@@ -472,10 +479,16 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
     zgemm(g, 0, s);
   }
   double* c = M->info_d + 8;   // c, sqrt(c)
-  gershgorin(M->sH.re, M->sH.im, p, c, s);
+  // The scale c must exceed lambda_max(A) (the iteration converges for
+  // eigenvalues of A / c in (0, 3)); the closer it is, the fewer iterations.
+  // A power-iteration estimate times 1.3 is used, capped by the Gershgorin
+  // bound; a diverging run restarts from the Gershgorin bound alone.
+  bool safe = false;
+  ns_scale(M->sH.re, M->sH.im, p, M->pwork, 12, 1.3, c, s);
   ns_init(M->sH.re, M->sH.im, p, c, M->nY.re, M->nY.im, M->nZ.re, M->nZ.im, s);
   const double tol2 = 1e-28 * p;
   int it = 0;
+  double prev_dev = 0.0;
   for (; it < 40; ++it) {
     mm(M->nZ, M->nY, M->sW);                       // P = X Y
     const int g = ns_three_minus(M->sW.re, M->sW.im, p, M->ns_part, s);   // T = (3I - P)/2
@@ -488,8 +501,20 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
     double dev = 0.0;
     for (int b = 0; b < g; ++b) dev += M->h_part[b];
     if (dev <= tol2) break;
+    if (!safe && (!(dev < 1e300) || (it >= 3 && dev > 4.0 * prev_dev))) {
+      safe = true;
+      ns_scale(M->sH.re, M->sH.im, p, M->pwork, 0, 0.0, c, s);
+      ns_init(M->sH.re, M->sH.im, p, c, M->nY.re, M->nY.im, M->nZ.re, M->nZ.im, s);
+      dev = 0.0;
+    }
+    prev_dev = dev;
   }
-  if (debug_enabled()) std::fprintf(stderr, "[ptebd] lowdin p=%d newton-schulz iterations=%d\n", p, it + 1);
+  if (debug_enabled()) {
+    double hc = 0.0;
+    PTEBD_HIP(hipMemcpyAsync(&hc, c, sizeof(double), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    std::fprintf(stderr, "[ptebd] lowdin p=%d newton-schulz iterations=%d c=%.3f\n", p, it + 1, hc);
+  }
   if (it == 40) {
     M->failed = true;
     throw Error(-4, "Newton-Schulz orthonormalisation did not converge (basis of width " + std::to_string(p) + ")");
@@ -654,7 +679,7 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
                                        M->h_ratio, s);
     const bool jac = !(ratio <= kDiagCoupling);
     if (jac) {
-      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, kPartialSweeps);
+      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, partial_sweeps());
       herm_diag(M->sH.re, p, p, M->norms, s);
       rotate(M->sW, 0, p, true);
     }

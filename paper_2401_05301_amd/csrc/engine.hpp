@@ -40,6 +40,7 @@ struct tebd_mps {
   double* h_part = nullptr;     // pinned host mirror of ns_part
   unsigned long long* ratio_bits = nullptr;   // perturbative Rayleigh-Ritz: max coupling / gap (bits of a double)
   unsigned long long* h_ratio = nullptr;      // pinned host mirror
+  double* pwork = nullptr;      // Newton-Schulz scale: row sums and power-iteration vectors (5p + 1)
   int sub_p = 0;                // subspace width reserved (0: not reserved)
   int* flags = nullptr;         // per block pair flags of the Hermitian Jacobi
   Z E, F, F2, F3;

@@ -1,7 +1,8 @@
 // Complex planar GEMM on the gfx950 matrix cores.
 //
-// One work-group of 256 threads (four wave64) computes a 64 x 64 tile of C;
-// each wave owns a 32 x 32 quadrant as 2 x 2 MFMA tiles of 16 x 16.  The
+// A work-group computes a 64 x 64 tile of C with four waves or (FP64, large
+// C) a 128 x 128 tile with eight; each wave owns a block of MFMA tiles of
+// 16 x 16.  The
 // complex product is four real products (Cr += Ar Br - Ai Bi,
 // Ci += Ar Bi + Ai Br), so both rounding errors stay symmetric.  K is walked
 // in slabs of 16 staged through LDS.  Precisions:
@@ -18,7 +19,7 @@ namespace ptebd {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+constexpr int PAD = 1;
 
 __device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -34,8 +35,8 @@ struct Traits {
   static constexpr int NPART = PREC == 2 ? 2 : 1;  // hi (and lo) planes
 };
 
-template <int PREC>
-__device__ __forceinline__ void put(typename Traits<PREC>::T (*s)[BK][BM + PAD], int kk, int r, double v) {
+template <int PREC, int KB, int LD>
+__device__ __forceinline__ void put(typename Traits<PREC>::T (*s)[KB][LD], int kk, int r, double v) {
   if constexpr (PREC == 0) {
     s[0][kk][r] = v;
   } else if constexpr (PREC == 1) {
@@ -47,17 +48,23 @@ __device__ __forceinline__ void put(typename Traits<PREC>::T (*s)[BK][BM + PAD],
   }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
+// Tile BM x BN per work-group of WM x WN waves; each wave owns a
+// (BM/WM) x (BN/WN) block as TM x TN MFMA tiles of 16 x 16.  K advances in
+// slabs of BK.
+template <int PREC, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(ZGemmArgs g) {
   using Tr = Traits<PREC>;
   using T = typename Tr::T;
   using Acc = typename Tr::Acc;
   constexpr int NP = Tr::NPART;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
+  constexpr int RA = BM * BK / NT, RB = BN * BK / NT;   // loads per thread per slab
   __shared__ T As_r[NP][BK][BM + PAD], As_i[NP][BK][BM + PAD];
   __shared__ T Bs_r[NP][BK][BN + PAD], Bs_i[NP][BK][BN + PAD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int64_t bz = blockIdx.z;
   int tile_r = blockIdx.y, tile_c = blockIdx.x;
   if (g.herm_out) {
@@ -75,90 +82,68 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
   const double* Br = g.br + bz * g.sB;
   const double* Bi = g.bi + bz * g.sB;
 
-  Acc accr[2][2], acci[2][2];
+  Acc accr[TM][TN], acci[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < TN; ++b) {
       accr[a][b] = Acc{0, 0, 0, 0};
       acci[a][b] = Acc{0, 0, 0, 0};
     }
 
   // Global loads of the next K slab go to registers while the current slab is
-  // multiplied out of LDS (register double buffering).
-  double ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+  // multiplied out of LDS (register double buffering).  Element e = tid + NT
+  // rep of a slab: k fastest when the operand is contiguous in k, else the
+  // row (column) index fastest, so that neighbouring lanes read neighbouring
+  // addresses.
+  // Every load is unconditional, from an index clamped into the matrix, so
+  // that all of a slab's loads are in flight together; elements outside
+  // the matrix are zeroed (and k-scaled) when staged.
+  double ra_r[RA], ra_i[RA], rb_r[RB], rb_i[RB], rks[RA];
+  int slab_k0 = 0;
   auto load = [&](int k0) {
-    if (!g.transA) {
-      const int kk = tid & 15, kg = k0 + kk;
-      const double ks = (g.k_scale && kg < g.k) ? g.k_scale[kg / g.k_div] : 1.0;
+    slab_k0 = k0;
 #pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        const int i = row0 + (tid >> 4) + 16 * rep;
-        const bool ok = i < g.m && kg < g.k;
-        const int64_t o = (int64_t)i * g.lda + kg;
-        ra_r[rep] = ok ? Ar[o] * ks : 0.0;
-        ra_i[rep] = ok ? Ai[o] * ks : 0.0;
-      }
-    } else {
-      const int i = row0 + (tid & 63);
-#pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        const int kg = k0 + (tid >> 6) + 4 * rep;
-        const bool ok = i < g.m && kg < g.k;
-        const double ks = (ok && g.k_scale) ? g.k_scale[kg / g.k_div] : 1.0;
-        const int64_t o = (int64_t)kg * g.lda + i;
-        ra_r[rep] = ok ? Ar[o] * ks : 0.0;
-        ra_i[rep] = ok ? -Ai[o] * ks : 0.0;
-      }
+    for (int rep = 0; rep < RA; ++rep) {
+      const int e = tid + NT * rep;
+      const int kk = g.transA ? e / BM : e % BK;
+      const int i = min(row0 + (g.transA ? e % BM : e / BK), g.m - 1);
+      const int kg = min(k0 + kk, g.k - 1);
+      const int64_t o = g.transA ? (int64_t)kg * g.lda + i : (int64_t)i * g.lda + kg;
+      ra_r[rep] = Ar[o];
+      ra_i[rep] = Ai[o];
+      rks[rep] = g.k_scale ? g.k_scale[kg / g.k_div] : 1.0;
     }
-    if (!g.transB) {
-      const int j = col0 + (tid & 63);
 #pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        const int kg = k0 + (tid >> 6) + 4 * rep;
-        const bool ok = j < g.n && kg < g.k;
-        const int64_t o = (int64_t)kg * g.ldb + j;
-        rb_r[rep] = ok ? Br[o] : 0.0;
-        rb_i[rep] = ok ? Bi[o] : 0.0;
-      }
-    } else {
-      const int kg = k0 + (tid & 15);
-#pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        const int j = col0 + (tid >> 4) + 16 * rep;
-        const bool ok = j < g.n && kg < g.k;
-        const int64_t o = (int64_t)j * g.ldb + kg;
-        rb_r[rep] = ok ? Br[o] : 0.0;
-        rb_i[rep] = ok ? -Bi[o] : 0.0;
-      }
+    for (int rep = 0; rep < RB; ++rep) {
+      const int e = tid + NT * rep;
+      const int kk = g.transB ? e % BK : e / BN;
+      const int j = min(col0 + (g.transB ? e / BK : e % BN), g.n - 1);
+      const int kg = min(k0 + kk, g.k - 1);
+      const int64_t o = g.transB ? (int64_t)j * g.ldb + kg : (int64_t)kg * g.ldb + j;
+      rb_r[rep] = Br[o];
+      rb_i[rep] = Bi[o];
     }
   };
   auto stage = [&]() {
-    if (!g.transA) {
 #pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        put<PREC>(As_r, tid & 15, (tid >> 4) + 16 * rep, ra_r[rep]);
-        put<PREC>(As_i, tid & 15, (tid >> 4) + 16 * rep, ra_i[rep]);
-      }
-    } else {
-#pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        put<PREC>(As_r, (tid >> 6) + 4 * rep, tid & 63, ra_r[rep]);
-        put<PREC>(As_i, (tid >> 6) + 4 * rep, tid & 63, ra_i[rep]);
-      }
+    for (int rep = 0; rep < RA; ++rep) {
+      const int e = tid + NT * rep;
+      const int kk = g.transA ? e / BM : e % BK;
+      const int i = g.transA ? e % BM : e / BK;
+      const bool ok = row0 + i < g.m && slab_k0 + kk < g.k;
+      const double sc = ok ? rks[rep] : 0.0;
+      put<PREC, BK, BM + PAD>(As_r, kk, i, ra_r[rep] * sc);
+      put<PREC, BK, BM + PAD>(As_i, kk, i, (g.transA ? -ra_i[rep] : ra_i[rep]) * sc);
     }
-    if (!g.transB) {
 #pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        put<PREC>(Bs_r, (tid >> 6) + 4 * rep, tid & 63, rb_r[rep]);
-        put<PREC>(Bs_i, (tid >> 6) + 4 * rep, tid & 63, rb_i[rep]);
-      }
-    } else {
-#pragma unroll
-      for (int rep = 0; rep < 4; ++rep) {
-        put<PREC>(Bs_r, tid & 15, (tid >> 4) + 16 * rep, rb_r[rep]);
-        put<PREC>(Bs_i, tid & 15, (tid >> 4) + 16 * rep, rb_i[rep]);
-      }
+    for (int rep = 0; rep < RB; ++rep) {
+      const int e = tid + NT * rep;
+      const int kk = g.transB ? e % BK : e / BN;
+      const int j = g.transB ? e / BK : e % BN;
+      const bool ok = col0 + j < g.n && slab_k0 + kk < g.k;
+      put<PREC, BK, BN + PAD>(Bs_r, kk, j, ok ? rb_r[rep] : 0.0);
+      put<PREC, BK, BN + PAD>(Bs_i, kk, j, ok ? (g.transB ? -rb_i[rep] : rb_i[rep]) : 0.0);
     }
   };
 
@@ -171,20 +156,24 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      T ar[NP][2], ai[NP][2], br[NP][2], bi[NP][2];
+      T ar[NP][TM], ai[NP][TM], br[NP][TN], bi[NP][TN];
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+      for (int p = 0; p < NP; ++p) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          ar[p][t] = As_r[p][kr][wm * 32 + t * 16 + (lane & 15)];
-          ai[p][t] = As_i[p][kr][wm * 32 + t * 16 + (lane & 15)];
-          br[p][t] = Bs_r[p][kr][wn * 32 + t * 16 + (lane & 15)];
-          bi[p][t] = Bs_i[p][kr][wn * 32 + t * 16 + (lane & 15)];
+        for (int t = 0; t < TM; ++t) {
+          ar[p][t] = As_r[p][kr][wm * (BM / WM) + t * 16 + (lane & 15)];
+          ai[p][t] = As_i[p][kr][wm * (BM / WM) + t * 16 + (lane & 15)];
         }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int t = 0; t < TN; ++t) {
+          br[p][t] = Bs_r[p][kr][wn * (BN / WN) + t * 16 + (lane & 15)];
+          bi[p][t] = Bs_i[p][kr][wn * (BN / WN) + t * 16 + (lane & 15)];
+        }
+      }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
           if constexpr (PREC != 2) {
             accr[a][b] = mfma(ar[0][a], br[0][b], accr[a][b]);
             accr[a][b] = mfma(-ai[0][a], bi[0][b], accr[a][b]);
@@ -218,13 +207,13 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
   double* Cr = g.cr + bz * g.sC;
   double* Ci = g.ci + bz * g.sC;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int i = row0 + wm * 32 + a * 16 + (PREC == 0 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e);
-        const int j = col0 + wn * 32 + b * 16 + (lane & 15);
+        const int i = row0 + wm * (BM / WM) + a * 16 + (PREC == 0 ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e);
+        const int j = col0 + wn * (BN / WN) + b * 16 + (lane & 15);
         if (i < g.m && j < g.n) {
           double s = alpha;
           if (g.row_scale) s *= g.row_scale[i / g.row_div];
@@ -247,28 +236,59 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemmArgs g) {
       }
 }
 
+template <int PREC, int BM, int BN, int BK, int WM, int WN>
+void launch(const ZGemmArgs& a, hipStream_t s) {
+  dim3 grid(ceil_div(a.n, BN), ceil_div(a.m, BM), a.batch);
+  if (a.herm_out) {
+    const int T = ceil_div(a.m, BM);
+    grid = dim3(T * (T + 1) / 2, 1, a.batch);
+  }
+  if (grid.y > 65535 || grid.z > 65535) throw Error(-1, "zgemm: grid too large");
+  zgemm_kernel<PREC, BM, BN, BK, WM, WN><<<grid, 64 * WM * WN, 0, s>>>(a);
+}
+
+// 128 x 128 launches run one work-group per CU at a time (256 CUs): use them
+// for at least one full wave and a last wave at least half full.
+bool wide_tiles_pay(int64_t t) {
+  if (t < 256) return false;
+  const int64_t rest = t % 256;
+  return t >= 1024 || rest == 0 || rest >= 128;
+}
+
+// Number of work-groups a launch with BM x BN tiles would have.
+int64_t tiles(const ZGemmArgs& a, int bm, int bn) {
+  if (a.herm_out) {
+    const int64_t T = ceil_div(a.m, bm);
+    return T * (T + 1) / 2 * a.batch;
+  }
+  return (int64_t)ceil_div(a.m, bm) * ceil_div(a.n, bn) * a.batch;
+}
+
 }  // namespace
 
 void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
   if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return;
   if (a.k <= 0) throw Error(-1, "zgemm: k must be positive");
-  dim3 grid(ceil_div(a.n, BN), ceil_div(a.m, BM), a.batch);
   if (a.herm_out) {
     // C = X X^+ is Hermitian: only tiles on or below the diagonal are computed
     if (a.m != a.n || a.beta || a.col_scale != a.row_scale || a.col_div != a.row_div)
       throw Error(-1, "zgemm: Hermitian output needs a square, overwritten, symmetrically scaled C");
-    const int T = ceil_div(a.m, BM);
-    grid = dim3(T * (T + 1) / 2, 1, a.batch);
   }
-  if (grid.y > 65535 || grid.z > 65535) throw Error(-1, "zgemm: grid too large");
   // algorithmic work: a Hermitian Gram product counts as a rank-k update
   const double flops = a.herm_out ? 4.0 * a.m * a.m * (double)a.k * a.batch
                                   : 8.0 * a.m * (double)a.n * a.k * a.batch;
   ProfScope ps(prec == 0 ? K_GEMM_FP64 : K_GEMM_FP32, flops, s);
   switch (prec) {
-    case 0: zgemm_kernel<0><<<grid, 256, 0, s>>>(a); break;
-    case 1: zgemm_kernel<1><<<grid, 256, 0, s>>>(a); break;
-    case 2: zgemm_kernel<2><<<grid, 256, 0, s>>>(a); break;
+    case 0:
+      // 128 x 128 tiles halve the operand traffic per flop; they pay off
+      // when the launch fills the chip with them without a thin last wave
+      if (wide_tiles_pay(tiles(a, 128, 128)))
+        launch<0, 128, 128, 16, 4, 2>(a, s);
+      else
+        launch<0, 64, 64, 16, 2, 2>(a, s);
+      break;
+    case 1: launch<1, 64, 64, 16, 2, 2>(a, s); break;
+    case 2: launch<2, 64, 64, 16, 2, 2>(a, s); break;
     default: throw Error(-1, "zgemm: bad precision");
   }
   PTEBD_LAUNCH_CHECK();

@@ -46,6 +46,7 @@ __device__ __forceinline__ int acc_row(int lane, int e) { return (lane >> 4) + 4
 // stored as cf[k] = (cs, sn, Re e, Im e).  The four entries of C at rows
 // (p_k, q_k) and columns (p_l, q_l) depend only on those same four entries,
 // so thread (k, l) updates its 2 x 2 block of C in place.
+template <int NT>
 __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Qr)[PR + 1], double (*Qi)[PR + 1],
                           double (*cf)[4], double thr, int max_sweeps) {
   const int tid = threadIdx.x;
@@ -72,9 +73,9 @@ __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Q
         cf[tid][0] = cs; cf[tid][1] = sn; cf[tid][2] = er; cf[tid][3] = ei;
       }
       __syncthreads();
-      {
+      for (int kl = tid; kl < 256; kl += NT) {
         // C block (rows of pair k, columns of pair l)
-        const int k = tid >> 4, l = tid & 15;
+        const int k = kl >> 4, l = kl & 15;
         const double ck = cf[k][0], sk = cf[k][1], cl = cf[l][0], sl = cf[l][1];
         if (sk != 0.0 || sl != 0.0) {
           const int a0 = member(k), a1 = member(PR - 1 - k), b0 = member(l), b1 = member(PR - 1 - l);
@@ -112,7 +113,7 @@ __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Q
         }
       }
       // Q <- Q J: item (row r, pair l)
-      for (int e = tid; e < PR * 16; e += 256) {
+      for (int e = tid; e < PR * 16; e += NT) {
         const int r = e >> 4, l = e & 15;
         const double cl = cf[l][0], sl = cf[l][1];
         if (sl == 0.0) continue;
@@ -132,15 +133,19 @@ __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Q
   }
 }
 
+// Threads per pair solve.  Each step of the solve updates all of the 32 x 32
+// block; spreading that over four waves beats a single wave without barriers.
+constexpr int kEigThreads = 256;
+
 // grid: nb/2 work-groups.  Writes Q of each pair (or flag 0 if the pair is
 // already diagonal to the threshold).
-__global__ __launch_bounds__(256) void herm_eig(HermArgs a, int round) {
+__global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
   __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
   __shared__ double cf[16][4];
   const int tid = threadIdx.x;
   int I, J;
   round_pair(a.nb, round, blockIdx.x, I, J);
-  for (int idx = tid; idx < PR * PR; idx += 256) {
+  for (int idx = tid; idx < PR * PR; idx += kEigThreads) {
     const int p = idx / PR, q = idx % PR;
     const int gp = pidx(I, J, p), gq = pidx(I, J, q);
     const bool ok = gp < a.n && gq < a.n;
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(256) void herm_eig(HermArgs a, int round) {
   __syncthreads();
   const double thr = *a.tol_abs;
   int need = 0;
-  for (int idx = tid; idx < PR * PR; idx += 256) {
+  for (int idx = tid; idx < PR * PR; idx += kEigThreads) {
     const int p = idx / PR, q = idx % PR;
     if (p < q && hypot(Cr[p][q], Ci[p][q]) > thr) need = 1;
   }
@@ -165,8 +170,8 @@ __global__ __launch_bounds__(256) void herm_eig(HermArgs a, int round) {
     a.flag[blockIdx.x] = 1;
     atomicAdd(a.rotated, 1u);
   }
-  block_eig(Cr, Ci, Qr, Qi, cf, 0.5 * thr, a.inner_sweeps);
-  for (int idx = tid; idx < PR * PR; idx += 256) {
+  block_eig<kEigThreads>(Cr, Ci, Qr, Qi, cf, 0.5 * thr, a.inner_sweeps);
+  for (int idx = tid; idx < PR * PR; idx += kEigThreads) {
     qout[idx] = Qr[idx / PR][idx % PR];
     qout[PR * PR + idx] = Qi[idx / PR][idx % PR];
   }
@@ -382,7 +387,7 @@ void herm_round(HermArgs a, int round, hipStream_t s) {
   const int npairs = a.nb / 2;
   {
     ProfScope ps(K_HERM_EIG, 0.0, s);
-    herm_eig<<<npairs, 256, 0, s>>>(a, round);
+    herm_eig<<<npairs, kEigThreads, 0, s>>>(a, round);
     PTEBD_LAUNCH_CHECK();
   }
   const int nsand = npairs * (npairs + 1) / 2;

@@ -78,8 +78,12 @@ void herm_round(HermArgs a, int round, hipStream_t s);
 void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s);
 
 // Newton-Schulz helpers on p x p planar matrices (leading dimension p).
-// out[0] = max_i sum_j |A(i, j)| (Gershgorin bound), out[1] = sqrt(out[0]).
-void gershgorin(const double* ar, const double* ai, int p, double* out, hipStream_t s);
+// Scale c >= lambda_max(A) for the Newton-Schulz iteration of a Hermitian
+// positive definite A (p x p): c = min(Gershgorin bound, safety * estimate)
+// with the estimate from power_its power iterations (0: Gershgorin only);
+// out[0] = c, out[1] = sqrt(c).  work holds 5p + 1 doubles.
+void ns_scale(const double* ar, const double* ai, int p, double* work, int power_its, double safety, double* out,
+              hipStream_t s);
 // Y = A / *c  and  Z = I.
 void ns_init(const double* ar, const double* ai, int p, const double* c, double* yr, double* yi, double* zr,
              double* zi, hipStream_t s);

@@ -25,6 +25,37 @@ def test_zgemm_fp64(pt, m, n, k, ta, tb):
     assert np.abs(C - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * np.sqrt(k)
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_zgemm_fp64_large_tiles(pt, ta, tb):
+    """Shapes large enough for the 128 x 128 tiles, with ragged edges."""
+    m, n, k = 2100, 2070, 37
+    rng = np.random.default_rng(99 + 2 * ta + tb)
+    A = rand_c(rng, *((m, k) if not ta else (k, m)))
+    B = rand_c(rng, *((k, n) if not tb else (n, k)))
+    ks, rs, cs = rng.random(k), rng.random(m), rng.random(n)
+    note(f"zgemm fp64 large m={m} n={n} k={k} ta={ta} tb={tb}")
+    C = pt.tebd_diag_zgemm(A, B, ta, tb, k_scale=ks, row_scale=rs, col_scale=cs)
+    opA = A if not ta else A.conj().T
+    opB = B if not tb else B.conj().T
+    ref = rs[:, None] * ((opA * ks[None, :]) @ opB) * cs[None, :]
+    assert np.abs(C - ref).max() <= 1e-13 * np.abs(ref).max() * np.sqrt(k)
+
+
+@pytest.mark.parametrize("m,k,ta", [(70, 19, 0), (130, 40, 1), (2100, 33, 0), (2100, 33, 1)])
+def test_zgemm_hermitian_output(pt, m, k, ta):
+    """Gram products computed on the lower tiles and mirrored."""
+    rng = np.random.default_rng(m + k + ta)
+    X = rand_c(rng, *((m, k) if not ta else (k, m)))
+    rs = rng.random(m) + 0.5
+    note(f"zgemm herm m={m} k={k} ta={ta}")
+    # op(A) = X (or X^+ when stored transposed), op(B) = op(A)^+
+    C = pt.tebd_diag_zgemm(X, X, ta, 1 - ta, row_scale=rs, col_scale=rs, herm=True)
+    opA = X if not ta else X.conj().T
+    ref = rs[:, None] * (opA @ opA.conj().T) * rs[None, :]
+    assert np.abs(C - ref).max() <= 1e-13 * np.abs(ref).max() * np.sqrt(k)
+    assert np.abs(C - C.conj().T).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_zgemm_scalings(pt):
     rng = np.random.default_rng(3)
     m, n, k = 45, 67, 29
