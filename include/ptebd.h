@@ -127,8 +127,11 @@ tebd_status tebd_layer(tebd_mps* mps, int32_t group, double tau);
 /* One second-order Trotter step: layers (0, dt/2) (1, dt/2) (2, dt) (1, dt/2) (0, dt/2). */
 tebd_status tebd_step(tebd_mps* mps, double dt);
 
-/* One Trotter step for n independent handles, batched together on the device.
- * dt[n] per handle.  Handles must be distinct. */
+/* One Trotter step for n independent handles, run concurrently: one host
+ * thread per handle issues its step on the handle's own stream(s), so that
+ * their kernels overlap on the device.  dt[n] per handle.  Handles must be
+ * distinct and must not have been created on a shared stream.  Each handle
+ * gets exactly the result of tebd_step alone. */
 tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt);
 
 /* Local observables after the last step, FP64, synchronising the handle's stream:
@@ -185,6 +188,49 @@ tebd_status mps_profile(tebd_mps* mps, int32_t enable);
  * device milliseconds, number of launches and algorithmic flops (complex
  * GEMM 8 m n k, Hermitian Gram products 4 m^2 k; 0 for the Jacobi kernels). */
 tebd_status mps_profile_read(tebd_mps* mps, int32_t kclass, double* ms, int64_t* launches, double* flops);
+
+/* ------------------------------------------------------------------ serving
+ * A stream of quench requests (CDW start, Sec. II B; Eq. (1) couplings of
+ * their own; horizon = steps * dt) served concurrently.  Requests are
+ * admitted first come, first served once their arrival time has passed, a
+ * slot is free (max_active) and their footprint (mps_footprint) fits in what
+ * the running requests leave of hbm_budget.  Each admitted request runs on
+ * its own handle, stream and host thread until its horizon, so requests that
+ * arrive while others run overlap with them on the device; each gets exactly
+ * the result it would get alone. */
+typedef struct {
+  tebd_model model;
+  int32_t chi_max;
+  double dt;
+  int32_t steps;            /* second-order Trotter steps to the horizon */
+  double arrival;           /* seconds after the start of tebd_serve */
+  int32_t first_occupied;   /* CDW parity, as in mps_init_cdw */
+} tebd_request;
+
+typedef struct {
+  int32_t max_active;         /* concurrent requests; <= 0 selects 8 */
+  double hbm_budget;          /* device bytes the admitted requests may reserve; <= 0: 85% of the free memory */
+  int32_t prec, svd;          /* tebd_precision, tebd_svd for every request */
+  double trunc_weight, trunc_rel;
+  int32_t workers_per_request;  /* gate workers of each request's handle; <= 0 selects 1 */
+  int32_t measure_every;      /* measure_local every this many steps as well (0: only at the horizon) */
+} tebd_serve_opts;
+
+typedef struct {
+  double arrival, admitted, finished;   /* seconds after the start of tebd_serve */
+  double discarded_weight;             /* FP64 ledger at the horizon */
+  int64_t gate_updates;                /* three-site gate updates performed */
+  int32_t status;                      /* tebd_status of this request */
+} tebd_serve_result;
+
+/* Serves req[n]; fills res[n] and, for request i in order, the observables
+ * at its horizon (as measure_local) at offsets sum_{k<i} L_k in n_out,
+ * sum_{k<i} 2(L_k-1) in c_nn and sum_{k<i} 2(L_k-2) in c_nnn (any output may
+ * be NULL).  Returns after every request has finished; EINVAL/ENOMEM before
+ * anything runs if a request is invalid or larger than the budget alone,
+ * else the first failing request's status (the others still run). */
+tebd_status tebd_serve(const tebd_request* req, int32_t n, const tebd_serve_opts* opts, tebd_serve_result* res,
+                       double* n_out, double* c_nn, double* c_nnn);
 
 /* Block until all work enqueued on the handle has finished. */
 tebd_status mps_sync(tebd_mps* mps);

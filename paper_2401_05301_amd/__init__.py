@@ -25,7 +25,7 @@ EXPORTS = [
     "tebd_opts_default", "mps_init_cdw", "mps_init_product", "mps_init_state", "tebd_layer", "tebd_step",
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
-    "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize",
+    "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve",
 ]
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "herm_eig": 2, "herm_apply": 3, "jac_gram": 4, "jac_rotate": 5}
 
@@ -50,6 +50,22 @@ class Opts(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("svd", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("model", Model), ("chi_max", ctypes.c_int32), ("dt", ctypes.c_double), ("steps", ctypes.c_int32),
+                ("arrival", ctypes.c_double), ("first_occupied", ctypes.c_int32)]
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("hbm_budget", ctypes.c_double), ("prec", ctypes.c_int32),
+                ("svd", ctypes.c_int32), ("trunc_weight", ctypes.c_double), ("trunc_rel", ctypes.c_double),
+                ("workers_per_request", ctypes.c_int32), ("measure_every", ctypes.c_int32)]
+
+
+class ServeResult(ctypes.Structure):
+    _fields_ = [("arrival", ctypes.c_double), ("admitted", ctypes.c_double), ("finished", ctypes.c_double),
+                ("discarded_weight", ctypes.c_double), ("gate_updates", ctypes.c_int64), ("status", ctypes.c_int32)]
 
 
 def _load():
@@ -82,6 +98,8 @@ def _load():
         "mps_canonicalize": (st, [H]),
         "mps_profile": (st, [H, ctypes.c_int32]),
         "mps_profile_read": (st, [H, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_double)]),
+        "tebd_serve": (st, [P(Request), ctypes.c_int32, P(ServeOpts), P(ServeResult), P(ctypes.c_double),
+                            P(ctypes.c_double), P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -262,6 +280,41 @@ def mps_sync(h):
 
 def mps_free(h):
     _check(_lib.mps_free(h))
+
+
+def tebd_serve(requests, max_active: int = 8, hbm_budget: float = 0.0, prec: int = FP64, svd: int = SVD_JACOBI,
+               w_max: float = 1e-12, eps: float = 1e-12, workers_per_request: int = 1, measure_every: int = 0):
+    """Serve quench requests concurrently (see tebd_serve in ptebd.h).
+
+    ``requests`` are dicts with keys model (a Model), chi_max, dt, steps,
+    arrival (s) and optionally first_occupied.  Returns one dict per request
+    with arrival/admitted/finished times, discarded weight, gate updates,
+    status and the observables n, c_nn, c_nnn at the horizon."""
+    n = len(requests)
+    req = (Request * n)()
+    for i, r in enumerate(requests):
+        req[i] = Request(r["model"], int(r["chi_max"]), float(r["dt"]), int(r["steps"]), float(r["arrival"]),
+                         int(r.get("first_occupied", 1)))
+    so = ServeOpts(max_active, hbm_budget, prec, svd, w_max, eps, workers_per_request, measure_every)
+    res = (ServeResult * n)()
+    Ls = [r["model"].L for r in requests]
+    nn = np.zeros(sum(Ls))
+    cn = np.zeros(sum(2 * (L - 1) for L in Ls))
+    dn = np.zeros(sum(2 * (L - 2) for L in Ls))
+    st = _lib.tebd_serve(req, n, ctypes.byref(so), res, _dptr(nn), _dptr(cn), _dptr(dn))
+    out = []
+    o_n = o_c = o_d = 0
+    for i, L in enumerate(Ls):
+        c = cn[o_c:o_c + 2 * (L - 1)]
+        d = dn[o_d:o_d + 2 * (L - 2)]
+        out.append(dict(arrival=res[i].arrival, admitted=res[i].admitted, finished=res[i].finished,
+                        discarded_weight=res[i].discarded_weight, gate_updates=res[i].gate_updates,
+                        status=res[i].status, n=nn[o_n:o_n + L].copy(), c_nn=c[0::2] + 1j * c[1::2],
+                        c_nnn=d[0::2] + 1j * d[1::2]))
+        o_n, o_c, o_d = o_n + L, o_c + 2 * (L - 1), o_d + 2 * (L - 2)
+    if st not in (TEBD_OK,) and all(r["status"] == TEBD_OK for r in out):
+        _check(st)
+    return out
 
 
 class MPS:

@@ -2,6 +2,8 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -207,10 +209,21 @@ tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt) {
     for (int k = 0; k < i; ++k)
       if (mps[k] == mps[i]) return fail(TEBD_EINVAL, "handles must be distinct");
   }
-  for (int i = 0; i < n; ++i) {
-    tebd_status st = tebd_step(mps[i], dt[i]);
-    if (st) return st;
-  }
+  if (n == 1) return tebd_step(mps[0], dt[0]);
+  // Each handle runs its own stream(s); one host thread per handle issues its
+  // step, so that the handles' kernels overlap on the device.
+  std::vector<tebd_status> status(n, TEBD_OK);
+  std::vector<std::string> message(n);
+  std::vector<std::thread> threads;
+  threads.reserve(n);
+  for (int i = 0; i < n; ++i)
+    threads.emplace_back([&, i] {
+      status[i] = tebd_step(mps[i], dt[i]);
+      if (status[i]) message[i] = g_err;
+    });
+  for (auto& t : threads) t.join();
+  for (int i = 0; i < n; ++i)
+    if (status[i]) return fail(status[i], "handle " + std::to_string(i) + ": " + message[i]);
   return TEBD_OK;
 }
 

@@ -428,18 +428,31 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
   if (wr) set_identity(wr, wi, ldw, n, s);
   const int max_sweeps = sweep_cap > 0 ? sweep_cap : (M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40);
   if (debug_enabled()) std::fprintf(stderr, "[ptebd] herm-jacobi start n=%d cap=%d\n", n, sweep_cap);
+  // Convergence is checked before every sweep by counting the off-diagonal
+  // entries above the target, so no sweep runs only to find nothing to do.
+  auto converged = [&]() {
+    const unsigned above = count_above(hr, hi, ldh, n, a.tol_abs, M->counter + 1, M->h_counter + 1, s);
+    return above == 0;
+  };
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+    if (converged()) {
+      M->last_sweeps = sweep - 1;
+      M->total_sweeps += sweep - 1;
+      return sweep - 1;
+    }
     PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
     for (int t = 0; t < nb - 1; ++t) herm_round(a, t, s);
-    PTEBD_HIP(hipMemcpyAsync(M->h_counter, M->counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    if (debug_enabled())
+    if (debug_enabled()) {
+      PTEBD_HIP(hipMemcpyAsync(M->h_counter, M->counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipStreamSynchronize(s));
       std::fprintf(stderr, "[ptebd] herm-jacobi n=%d sweep=%d rotated_pairs=%u\n", n, sweep, *M->h_counter);
-    if (*M->h_counter == 0) {
-      M->last_sweeps = sweep;
-      M->total_sweeps += sweep;
-      return sweep;
     }
+  }
+  if (sweep_cap > 0) return sweep_cap;
+  if (converged()) {
+    M->last_sweeps = max_sweeps;
+    M->total_sweeps += max_sweeps;
+    return max_sweeps;
   }
   if (sweep_cap > 0) return sweep_cap;
   M->failed = true;

@@ -279,7 +279,7 @@ void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
                                   : 8.0 * a.m * (double)a.n * a.k * a.batch;
   ProfScope ps(prec == 0 ? K_GEMM_FP64 : K_GEMM_FP32, flops, s);
   switch (prec) {
-    case 0:
+    case 0: {
       // 128 x 128 tiles halve the operand traffic per flop; they pay off
       // when the launch fills the chip with them without a thin last wave
       if (wide_tiles_pay(tiles(a, 128, 128)))
@@ -287,6 +287,7 @@ void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
       else
         launch<0, 64, 64, 16, 2, 2>(a, s);
       break;
+    }
     case 1: launch<1, 64, 64, 16, 2, 2>(a, s); break;
     case 2: launch<2, 64, 64, 16, 2, 2>(a, s); break;
     default: throw Error(-1, "zgemm: bad precision");

@@ -42,90 +42,89 @@ __device__ __forceinline__ int acc_row(int lane, int e) { return (lane >> 4) + 4
 // Cyclic Jacobi on the 32 x 32 Hermitian block in LDS (absolute threshold).
 // One step applies 16 disjoint rotations (round-robin pairs) as C <- J^+ C J
 // and Q <- Q J.  For the rotation of pair k = (p, q) the 2 x 2 block of J is
-//   [[cs, sn], [-sn e, cs e]],  e = conj(C_pq) / |C_pq|,
-// stored as cf[k] = (cs, sn, Re e, Im e).  The four entries of C at rows
-// (p_k, q_k) and columns (p_l, q_l) depend only on those same four entries,
-// so thread (k, l) updates its 2 x 2 block of C in place.
-template <int NT>
+//   [[cs, sn], [-sn e, cs e]],  e = conj(C_pq) / |C_pq|.
+// The four entries of C at rows (p_k, q_k) and columns (p_l, q_l) depend
+// only on those same four entries, so thread (k, l) of 256 updates its 2 x 2
+// block of C in place, and the rows k and k + 16 of Q for pair l.  Every
+// thread derives the rotations of its pairs k and l itself from the entries
+// before the step (the same arithmetic on the same inputs in every thread),
+// which saves a round trip through LDS and a barrier's worth of idle lanes.
+struct Rot {
+  double cs, sn, er, ei;
+};
+
+__device__ __forceinline__ Rot make_rot(double app, double aqq, double cre, double cim, double thr) {
+  Rot r{1.0, 0.0, 1.0, 0.0};
+  const double c = sqrt(cre * cre + cim * cim);
+  if (c > thr) {
+    const double tau = (aqq - app) / (2.0 * c);
+    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    r.cs = 1.0 / sqrt(1.0 + t * t);
+    r.sn = t * r.cs;
+    r.er = cre / c;
+    r.ei = -cim / c;
+  }
+  return r;
+}
+
 __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Qr)[PR + 1], double (*Qi)[PR + 1],
-                          double (*cf)[4], double thr, int max_sweeps) {
+                          double thr, int max_sweeps) {
   const int tid = threadIdx.x;
+  const int k = tid >> 4, l = tid & 15;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     int changed = 0;
     for (int st = 0; st < PR - 1; ++st) {
-      auto member = [st](int k) { return k == 0 ? 0 : 1 + (k - 1 + st) % (PR - 1); };
-      if (tid < 16) {
-        const int a0 = member(tid), b0 = member(PR - 1 - tid);
-        const int p = min(a0, b0), q = max(a0, b0);
-        const double app = Cr[p][p], aqq = Cr[q][q];
-        const double cre = Cr[p][q], cim = Ci[p][q];
-        const double c = hypot(cre, cim);
-        double cs = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
-        if (c > thr) {
-          const double tau = (aqq - app) / (2.0 * c);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          cs = 1.0 / sqrt(1.0 + t * t);
-          sn = t * cs;
-          er = cre / c;
-          ei = -cim / c;
-          changed = 1;
-        }
-        cf[tid][0] = cs; cf[tid][1] = sn; cf[tid][2] = er; cf[tid][3] = ei;
-      }
+      auto member = [st](int m) {
+        if (m == 0) return 0;
+        int x = m - 1 + st;
+        x -= (x >= PR - 1) ? PR - 1 : 0;
+        return 1 + x;
+      };
+      const int ka = member(k), kb = member(PR - 1 - k), la = member(l), lb = member(PR - 1 - l);
+      const int p = min(ka, kb), q = max(ka, kb), u = min(la, lb), v = max(la, lb);
+      const Rot rk = make_rot(Cr[p][p], Cr[q][q], Cr[p][q], Ci[p][q], thr);
+      const Rot rl = make_rot(Cr[u][u], Cr[v][v], Cr[u][v], Ci[u][v], thr);
+      changed |= (rk.sn != 0.0);
       __syncthreads();
-      for (int kl = tid; kl < 256; kl += NT) {
-        // C block (rows of pair k, columns of pair l)
-        const int k = kl >> 4, l = kl & 15;
-        const double ck = cf[k][0], sk = cf[k][1], cl = cf[l][0], sl = cf[l][1];
-        if (sk != 0.0 || sl != 0.0) {
-          const int a0 = member(k), a1 = member(PR - 1 - k), b0 = member(l), b1 = member(PR - 1 - l);
-          const int p = min(a0, a1), q = max(a0, a1), u = min(b0, b1), v = max(b0, b1);
-          // column transform (J on the right) with pair l: col u' = cl col u - sl e_l col v,
-          // col v' = sl col u + cl e_l col v
-          const double elr = cf[l][2], eli = cf[l][3];
-          double r0r[2], r0i[2], r1r[2], r1i[2];  // rows p, q after the column transform: [u', v']
-          {
-            const int rows[2] = {p, q};
+      if (rk.sn != 0.0 || rl.sn != 0.0) {
+        // column transform (J on the right) with pair l: col u' = cl col u - sl e_l col v,
+        // col v' = sl col u + cl e_l col v; then row transform (J^+ on the left) with pair k:
+        // row p' = ck row p - sk conj(e_k) row q, row q' = sk row p + ck conj(e_k) row q
+        double r0r[2], r0i[2], r1r[2], r1i[2];
+        const int rows[2] = {p, q};
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-              const int rr = rows[t];
-              const double ur = Cr[rr][u], ui = Ci[rr][u], vr = Cr[rr][v], vi = Ci[rr][v];
-              const double wr = elr * vr - eli * vi, wi = elr * vi + eli * vr;   // e_l * C[rr][v]
-              const double nur = cl * ur - sl * wr, nui = cl * ui - sl * wi;
-              const double nvr = sl * ur + cl * wr, nvi = sl * ui + cl * wi;
-              if (t == 0) { r0r[0] = nur; r0i[0] = nui; r0r[1] = nvr; r0i[1] = nvi; }
-              else { r1r[0] = nur; r1i[0] = nui; r1r[1] = nvr; r1i[1] = nvi; }
-            }
-          }
-          // row transform (J^+ on the left) with pair k: row p' = ck row p - sk conj(e_k) row q,
-          // row q' = sk row p + ck conj(e_k) row q
-          const double ekr = cf[k][2], eki = -cf[k][3];   // conj(e_k)
-          const int cols[2] = {u, v};
+        for (int t = 0; t < 2; ++t) {
+          const int rr = rows[t];
+          const double ur = Cr[rr][u], ui = Ci[rr][u], vr = Cr[rr][v], vi = Ci[rr][v];
+          const double wr = rl.er * vr - rl.ei * vi, wi = rl.er * vi + rl.ei * vr;
+          const double nur = rl.cs * ur - rl.sn * wr, nui = rl.cs * ui - rl.sn * wi;
+          const double nvr = rl.sn * ur + rl.cs * wr, nvi = rl.sn * ui + rl.cs * wi;
+          if (t == 0) { r0r[0] = nur; r0i[0] = nui; r0r[1] = nvr; r0i[1] = nvi; }
+          else { r1r[0] = nur; r1i[0] = nui; r1r[1] = nvr; r1i[1] = nvi; }
+        }
+        const double ekr = rk.er, eki = -rk.ei;   // conj(e_k)
+        const int cols[2] = {u, v};
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const double pr_ = r0r[t], pi_ = r0i[t], qr_ = r1r[t], qi_ = r1i[t];
-            const double wr = ekr * qr_ - eki * qi_, wi = ekr * qi_ + eki * qr_;
-            Cr[p][cols[t]] = ck * pr_ - sk * wr;
-            Ci[p][cols[t]] = ck * pi_ - sk * wi;
-            Cr[q][cols[t]] = sk * pr_ + ck * wr;
-            Ci[q][cols[t]] = sk * pi_ + ck * wi;
-          }
+        for (int t = 0; t < 2; ++t) {
+          const double pr_ = r0r[t], pi_ = r0i[t], qr_ = r1r[t], qi_ = r1i[t];
+          const double wr = ekr * qr_ - eki * qi_, wi = ekr * qi_ + eki * qr_;
+          Cr[p][cols[t]] = rk.cs * pr_ - rk.sn * wr;
+          Ci[p][cols[t]] = rk.cs * pi_ - rk.sn * wi;
+          Cr[q][cols[t]] = rk.sn * pr_ + rk.cs * wr;
+          Ci[q][cols[t]] = rk.sn * pi_ + rk.cs * wi;
         }
       }
-      // Q <- Q J: item (row r, pair l)
-      for (int e = tid; e < PR * 16; e += NT) {
-        const int r = e >> 4, l = e & 15;
-        const double cl = cf[l][0], sl = cf[l][1];
-        if (sl == 0.0) continue;
-        const int b0 = member(l), b1 = member(PR - 1 - l);
-        const int u = min(b0, b1), v = max(b0, b1);
-        const double elr = cf[l][2], eli = cf[l][3];
-        const double ur = Qr[r][u], ui = Qi[r][u], vr = Qr[r][v], vi = Qi[r][v];
-        const double wr = elr * vr - eli * vi, wi = elr * vi + eli * vr;
-        Qr[r][u] = cl * ur - sl * wr;
-        Qi[r][u] = cl * ui - sl * wi;
-        Qr[r][v] = sl * ur + cl * wr;
-        Qi[r][v] = sl * ui + cl * wi;
+      if (rl.sn != 0.0) {   // Q <- Q J on rows k and k + 16, pair l
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = k + 16 * h;
+          const double ur = Qr[r][u], ui = Qi[r][u], vr = Qr[r][v], vi = Qi[r][v];
+          const double wr = rl.er * vr - rl.ei * vi, wi = rl.er * vi + rl.ei * vr;
+          Qr[r][u] = rl.cs * ur - rl.sn * wr;
+          Qi[r][u] = rl.cs * ui - rl.sn * wi;
+          Qr[r][v] = rl.sn * ur + rl.cs * wr;
+          Qi[r][v] = rl.sn * ui + rl.cs * wi;
+        }
       }
       __syncthreads();
     }
@@ -133,15 +132,13 @@ __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Q
   }
 }
 
-// Threads per pair solve.  Each step of the solve updates all of the 32 x 32
-// block; spreading that over four waves beats a single wave without barriers.
+// Threads per pair solve: one per (pair, pair) 2 x 2 block of the 32 x 32 block.
 constexpr int kEigThreads = 256;
 
 // grid: nb/2 work-groups.  Writes Q of each pair (or flag 0 if the pair is
 // already diagonal to the threshold).
 __global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
   __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
-  __shared__ double cf[16][4];
   const int tid = threadIdx.x;
   int I, J;
   round_pair(a.nb, round, blockIdx.x, I, J);
@@ -170,7 +167,7 @@ __global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
     a.flag[blockIdx.x] = 1;
     atomicAdd(a.rotated, 1u);
   }
-  block_eig<kEigThreads>(Cr, Ci, Qr, Qi, cf, 0.5 * thr, a.inner_sweeps);
+  block_eig(Cr, Ci, Qr, Qi, 0.5 * thr, a.inner_sweeps);
   for (int idx = tid; idx < PR * PR; idx += kEigThreads) {
     qout[idx] = Qr[idx / PR][idx % PR];
     qout[PR * PR + idx] = Qi[idx / PR][idx % PR];
@@ -361,6 +358,21 @@ __global__ __launch_bounds__(256) void offdiag_ratio_kernel(const double* hr, co
   if ((threadIdx.x & 63) == 0 && worst > 0.0) atomicMax(ratio_bits, (unsigned long long)__double_as_longlong(worst));
 }
 
+// Number of off-diagonal entries i < j with |H_ij| > tol (one atomic per wave).
+__global__ __launch_bounds__(256) void count_above_kernel(const double* hr, const double* hi, int64_t ldh, int n,
+                                                          const double* tol, unsigned int* count) {
+  const double t = *tol;
+  unsigned int c = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (i < j && hypot(hr[(int64_t)i * ldh + j], hi[(int64_t)i * ldh + j]) > t) ++c;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0 && c > 0) atomicAdd(count, c);
+}
+
 // H_ii = 0 for i < p.
 __global__ void zero_diag_kernel(double* hr, double* hi, int64_t ldh, int p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -421,6 +433,18 @@ double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, con
 void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s) {
   zero_diag_kernel<<<ceil_div(p, 256), 256, 0, s>>>(hr, hi, ldh, p);
   PTEBD_LAUNCH_CHECK();
+}
+
+unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n, const double* tol,
+                         unsigned int* count, unsigned int* h_count, hipStream_t s) {
+  PTEBD_HIP(hipMemsetAsync(count, 0, sizeof(unsigned int), s));
+  const int64_t total = (int64_t)n * n;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 2048);
+  count_above_kernel<<<grid, 256, 0, s>>>(hr, hi, ldh, n, tol, count);
+  PTEBD_LAUNCH_CHECK();
+  PTEBD_HIP(hipMemcpyAsync(h_count, count, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  return *h_count;
 }
 
 }  // namespace ptebd

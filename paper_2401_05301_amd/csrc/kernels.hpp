@@ -69,6 +69,9 @@ struct HermArgs {
 // none is above tol).
 double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double floor,
                      unsigned long long* ratio_bits, unsigned long long* h_ratio, hipStream_t s);
+// Number of entries i < j of H (n x n) with |H_ij| > *tol (synchronises).
+unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n, const double* tol,
+                         unsigned int* count, unsigned int* h_count, hipStream_t s);
 // H_ii = 0, i < p.
 void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s);
 // *out = c * u * sum_i |H_ii|

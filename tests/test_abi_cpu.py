@@ -66,3 +66,21 @@ def test_footprint_scales_with_chi():
     assert 0 < small < big
     # chi = 1024, d = 5, L = 64: state ~5.4 GB plus a few GB of gate workspace
     assert 8e9 < big < 40e9
+
+
+def test_serve_validation_without_gpu():
+    import paper_2401_05301_amd as pt
+    m = pt.make_model(L=8, d=3, U=1.0)
+    bad = [dict(model=m, chi_max=8, dt=0.01, steps=-1, arrival=0.0)]
+    with pytest.raises(pt.TebdError) as e:
+        pt.tebd_serve(bad, hbm_budget=1e9)
+    assert e.value.status == pt.TEBD_EINVAL
+    bad = [dict(model=pt.make_model(L=2, d=3, U=1.0), chi_max=8, dt=0.01, steps=1, arrival=0.0)]
+    with pytest.raises(pt.TebdError) as e:
+        pt.tebd_serve(bad, hbm_budget=1e9)
+    assert e.value.status == pt.TEBD_EINVAL
+    # a request larger than the whole budget is refused before anything runs
+    big = [dict(model=m, chi_max=8, dt=0.01, steps=1, arrival=0.0)]
+    with pytest.raises(pt.TebdError) as e:
+        pt.tebd_serve(big, hbm_budget=1024.0)
+    assert e.value.status == pt.TEBD_ENOMEM
