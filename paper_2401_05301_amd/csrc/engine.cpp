@@ -89,7 +89,9 @@ int auto_workers(int L, int requested) {
 
 int subspace_width(int r, int chi_max) {
   const int keep = std::min(chi_max, r);
-  const int p = ((keep + std::max(64, keep / 4)) + 15) / 16 * 16;
+  // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 8)
+  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 8;
+  const int p = ((keep + std::max(64, keep / den)) + 15) / 16 * 16;
   // below ~1.5 p the whole Gram matrix is cheaper to diagonalise directly
   return (3 * p < 2 * r) ? p : 0;
 }
@@ -406,8 +408,12 @@ int inner_sweeps() {
 // accumulated into W (set to the identity first).  Returns the sweeps used.
 // With sweep_cap > 0 at most that many sweeps run and an unconverged H is
 // returned as it stands (partial diagonalisation), without an error.
+// The off-diagonal target is c u trace(H); with a trace_of block given
+// (the whole matrix, of which H is a diagonal block) the target is taken
+// against its trace instead, so that a block of rounding noise is not
+// chased below the rounding level of the whole.
 int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, double* wr, double* wi, int64_t ldw,
-                    int sweep_cap = 0) {
+                    int sweep_cap = 0, const double* trace_of = nullptr, int trace_n = 0) {
   hipStream_t s = M->stream;
   int nb = (n + 15) / 16;
   if (nb < 2) nb = 2;
@@ -423,7 +429,10 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
   a.flag = M->flags;
   a.inner_sweeps = inner_sweeps();
   a.rotated = M->counter;
-  herm_tol(hr, ldh, n, herm_tol_units(), M->info_d + 7, s);
+  if (trace_of)
+    herm_tol(trace_of, ldh, trace_n, herm_tol_units(), M->info_d + 7, s);
+  else
+    herm_tol(hr, ldh, n, herm_tol_units(), M->info_d + 7, s);
   a.tol_abs = M->info_d + 7;
   if (wr) set_identity(wr, wi, ldw, n, s);
   const int max_sweeps = sweep_cap > 0 ? sweep_cap : (M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40);
@@ -646,7 +655,7 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       // first, so that H is nearly diagonal as a whole.
       const int nr = p - kw;
       run_herm_jacobi(M, M->sH.re + (size_t)kw * p + kw, M->sH.im + (size_t)kw * p + kw, p, nr, M->sW.re,
-                      M->sW.im, nr);
+                      M->sW.im, nr, 0, M->sH.re, p);
       rotate(M->sW, kw, nr, true);
       rayleigh(M, p, r);
     }

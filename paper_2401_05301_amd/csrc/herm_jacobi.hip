@@ -329,7 +329,9 @@ __global__ __launch_bounds__(256) void trace_tol_kernel(const double* hr, int64_
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = c * 1.1102230246251565e-16 * sh[0];
+  // floored at a tiny normal number: an exactly zero matrix needs no rotation,
+  // and a target of zero would chase underflowing rounding residue
+  if (threadIdx.x == 0) out[0] = fmax(c * 1.1102230246251565e-16 * sh[0], 1e-280);
 }
 
 // Largest relative coupling |H_ij| / sqrt(max(H_ii, f) max(H_jj, f)) over
