@@ -64,6 +64,50 @@ def cpu_baseline(chi: int, L_ref: int, steps_scale: float):
                        f"to the chi=1024 unit")}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the FP64 GEMM from the committed rocprofv3
+    counter summary, or None when it is missing or the kernel source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "zgemm_traffic_bulk_L64_chi1024.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2401_05301_amd.traffic import gemm_source_hash
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("gemm_source_sha256") != gemm_source_hash():
+        return None
+    return t["traffic_bytes_per_launch"]
+
+
+def serving_sample(pt, n: int, scale: float):
+    """Quench requests of the serving workload (Poisson arrivals, L in
+    {16..64}, U in [2, 10], K in [0, 0.01], J_NNN = 0.1, dt = 0.01), with the
+    small bond caps {16, 32, 64} and each horizon scaled by `scale`, served
+    concurrently by the library; p50/p99 time from arrival to horizon."""
+    import numpy as np
+    from workloads import serving_requests
+    rate = 2.0
+    reqs = []
+    for r in serving_requests(n=n, seed=5, rate=rate, small=True):
+        m = r["model"]
+        steps = max(1, int(round(r["horizon"] / r["dt"] * scale)))
+        reqs.append(dict(model=pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), chi_max=r["chi_max"],
+                         dt=r["dt"], steps=steps, arrival=r["arrival"]))
+    t0 = time.perf_counter()
+    res = pt.tebd_serve(reqs, max_active=8, svd=pt.SVD_GRAM_EIG)
+    wall = time.perf_counter() - t0
+    if any(x["status"] != 0 for x in res):
+        raise RuntimeError("a served request failed: " + str([x["status"] for x in res]))
+    lat = np.array([x["finished"] - x["arrival"] for x in res])
+    span = max(x["finished"] for x in res) - min(x["arrival"] for x in res)
+    gu = sum(x["gate_updates"] for x in res)
+    return {"requests": n, "arrival_rate_per_s": rate, "max_active": 8, "chi_max_set": [16, 32, 64],
+            "horizon_scale": scale, "steps_total": sum(r["steps"] for r in reqs),
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "gate_updates_per_s": gu / span, "wall_s": wall,
+            "note": "time-to-horizon = finish - arrival; Gram route; each request on its own handle and stream"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,7 +125,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-chi", type=int, default=512)
     ap.add_argument("--workers", type=int, default=0, help="concurrent gate workers per layer (0: library default)")
+    ap.add_argument("--serve", type=int, default=16, help="requests in the serving sample (0: skip it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the reference for the HBM counters) and exit")
+    ap.add_argument("--serve-scale", type=float, default=0.1,
+                    help="fraction of each request's horizon served in the sample")
     args = ap.parse_args()
+
+    if args.copy_calibration > 0:
+        import torch
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": nbytes, "dispatches": 5}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -157,6 +217,8 @@ def main():
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
             "launches": gemm_n, "avg_launch_ms": gemm_ms / max(gemm_n, 1),
             "flops_per_launch": gemm_fl / max(gemm_n, 1)}
+    if prec == pt.FP64 and L == 64 and chi == 1024 and args.svd == "gram":
+        roof["traffic"] = measured_traffic()
     out = {
         "metric": METRIC,
         "value": value,
@@ -185,6 +247,9 @@ def main():
         "max_bond": max(chis),
     }
     g.close()
+    if args.serve > 0:
+        log(f"serving sample: {args.serve} requests")
+        out["serving"] = serving_sample(pt, args.serve, args.serve_scale)
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on one chi={args.cpu_chi} gate update")
         out["cpu_baseline"] = cpu_baseline(args.cpu_chi, L, 1.0)
