@@ -104,13 +104,17 @@ __global__ void hop_kscale_kernel(const double* lam, int cl, int d, double* ks) 
   ks[rp] = s >= 1 ? lam[a] * lam[a] * sqrt((double)s) : 0.0;
 }
 
-// sum_{y, t>=1, c} sqrt(t) conj(B(y, t-1, c)) F(y, t, c)
-__global__ __launch_bounds__(256) void close_hop_kernel(const double* br, const double* bi, const double* fr,
-                                                        const double* fi, int chi, int d, int cr, double* out) {
+// sum_{y, t>=1, c} sqrt(t) conj(B(y, t-1, c)) F(y, t, c), in two passes:
+// each of kHopBlocks work-groups sums a fixed slice into part[2 b], then
+// one work-group adds the partial sums in block order (deterministic).
+constexpr int kHopBlocks = 256;
+
+__global__ __launch_bounds__(256) void close_hop_part_kernel(const double* br, const double* bi, const double* fr,
+                                                             const double* fi, int chi, int d, int cr, double* part) {
   __shared__ double sh[4];
   const int64_t tot = (int64_t)chi * (d - 1) * cr;
   double accr = 0.0, acci = 0.0;
-  for (int64_t e = threadIdx.x; e < tot; e += 256) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)kHopBlocks * 256) {
     const int y = (int)(e / ((int64_t)(d - 1) * cr));
     const int t = 1 + (int)((e / cr) % (d - 1));
     const int c = (int)(e % cr);
@@ -123,6 +127,16 @@ __global__ __launch_bounds__(256) void close_hop_kernel(const double* br, const 
   }
   const double sr = block_sum(accr, sh);
   const double si = block_sum(acci, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr;
+    part[2 * blockIdx.x + 1] = si;
+  }
+}
+
+__global__ __launch_bounds__(256) void close_hop_sum_kernel(const double* part, double* out) {
+  __shared__ double sh[4];
+  const double sr = block_sum(threadIdx.x < kHopBlocks ? part[2 * threadIdx.x] : 0.0, sh);
+  const double si = block_sum(threadIdx.x < kHopBlocks ? part[2 * threadIdx.x + 1] : 0.0, sh);
   if (threadIdx.x == 0) {
     out[0] = sr;
     out[1] = si;
@@ -461,8 +475,10 @@ void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s) {
 }
 
 void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d, int cr,
-               double* out, hipStream_t s) {
-  close_hop_kernel<<<1, 256, 0, s>>>(br, bi, fr, fi, chi, d, cr, out);
+               double* out, double* part, hipStream_t s) {
+  close_hop_part_kernel<<<kHopBlocks, 256, 0, s>>>(br, bi, fr, fi, chi, d, cr, part);
+  PTEBD_LAUNCH_CHECK();
+  close_hop_sum_kernel<<<1, 256, 0, s>>>(part, out);
   PTEBD_LAUNCH_CHECK();
 }
 

@@ -203,6 +203,7 @@ void mps_allocate(tebd_mps* M) {
   M->F3 = zalloc(M, s.meas_rect);
   M->ks = dalloc(M, s.vec);
   M->meas = dalloc(M, 5 * (int64_t)L);
+  M->hop_part = dalloc(M, 512);
   M->d_br = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
   M->d_bi = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
   M->d_lam = static_cast<double**>(dev_alloc(M, sizeof(double*) * (L + 1)));
@@ -1050,7 +1051,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
       g.cr = M->F.re; g.ci = M->F.im; g.ldc = (int64_t)d * cr2;
       zgemm(g, 0, s);
     }
-    close_hop(M->Br[i + 1], M->Bi[i + 1], M->F.re, M->F.im, cr, d, cr2, dc + 2 * i, s);
+    close_hop(M->Br[i + 1], M->Bi[i + 1], M->F.re, M->F.im, cr, d, cr2, dc + 2 * i, M->hop_part, s);
     if (i + 2 < L) {
       const int cr3 = M->chi[i + 3];
       {  // F2 = B_{i+1}^+ F   (rows (y, s) contracted)
@@ -1069,7 +1070,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
         g.cr = M->F3.re; g.ci = M->F3.im; g.ldc = (int64_t)d * cr3;
         zgemm(g, 0, s);
       }
-      close_hop(M->Br[i + 2], M->Bi[i + 2], M->F3.re, M->F3.im, cr2, d, cr3, dd + 2 * i, s);
+      close_hop(M->Br[i + 2], M->Bi[i + 2], M->F3.re, M->F3.im, cr2, d, cr3, dd + 2 * i, M->hop_part, s);
     }
   }
   std::vector<double> h(5 * (size_t)L);

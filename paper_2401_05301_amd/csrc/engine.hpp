@@ -55,6 +55,7 @@ struct tebd_mps {
   double* info_d = nullptr;    // [8]: nrm1, w1, nrm2, w2, ...
   unsigned int* counter = nullptr;
   double* meas = nullptr;      // n[L], C[2(L-1)], D[2(L-2)]
+  double* hop_part = nullptr;  // partial sums of the correlator closes (512)
   unsigned int* h_counter = nullptr;  // pinned host mirrors
   int* h_info = nullptr;
 

@@ -146,8 +146,9 @@ void site_densities(const double* const* br, const double* const* bi, const doub
                     const int* chil, const int* chir, int L, int d, double* n_out, hipStream_t s);
 void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s);
 // out[0] += sum_{y, t>=1, c} sqrt(t) conj(B(y, t-1, c)) F(y, t, c) (complex; out[0]=re, out[1]=im)
+// part: 512 doubles of scratch.
 void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d,
-               int cr, double* out, hipStream_t s);
+               int cr, double* out, double* part, hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
 // *acc += sum_{i<n} slots[i], summed in index order by one thread.
 void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s);
