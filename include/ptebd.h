@@ -139,6 +139,17 @@ tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt);
  * of <b+_i b_{i+2}>.  Any output pointer may be NULL to skip that observable. */
 tebd_status measure_local(tebd_mps* mps, double* n, double* c_nn, double* c_nnn);
 
+/* Quasi-local observables of the experiment (Sec. II B; the quasi-local
+ * densities, correlation, tunnel oscillation and visibility equations),
+ * from the local n_j and C_j = <b+_j b_{j+1}> of measure_local, with the
+ * lattice index j = i - centre counted from the site `centre` (0-based; the
+ * centre counts as even).  out[8] = N = sum_j n_j, n_odd, n_even, Re C_even,
+ * Im C_even, A, phi, nu, where n_odd/even = sum over odd/even j of n_j / N,
+ * C_even = sum_{j even} C_j / N (bond j, j+1), A e^{i phi} = n_even - n_odd
+ * - 2 i Im C_even (A >= 0, phi in (-pi, pi]) and nu = (1/N) sum over every
+ * bond of (C_j + C_j^*).  Synchronises.  ESTATE if N is not positive. */
+tebd_status measure_quasi_local(tebd_mps* mps, int32_t centre, double* out);
+
 /* Quench: replace the Hamiltonian parameters (same L and d), keep the state. */
 tebd_status mps_set_model(tebd_mps* mps, const tebd_model* model);
 

@@ -201,6 +201,30 @@ def measure(mps: MPS):
     return n, C, D
 
 
+def quasi_local(n: np.ndarray, C: np.ndarray, centre: int):
+    """Quasi-local observables of Sec. II B from the local n_j and
+    C_j = <b_j^+ b_{j+1}>, with the lattice index j counted from the centre
+    site (j = i - centre, so the centre is even):
+
+      N        = sum_j n_j                       (conserved particle number)
+      n_odd    = sum_{j odd} n_j / N,  n_even = sum_{j even} n_j / N
+      C_even   = sum_{j even} C_j / N            (C_j on the bond j, j+1)
+      A e^{i phi} = n_even - n_odd - 2 i Im(C_even)   (tunnel oscillation)
+      nu       = (1/N) sum_j (C_j + C_j^*)       (visibility, over every bond)
+
+    Returns a dict with those values (A >= 0, phi in (-pi, pi])."""
+    L = len(n)
+    j = np.arange(L) - centre
+    N = float(np.sum(n))
+    n_odd = float(np.sum(n[j % 2 != 0])) / N
+    n_even = float(np.sum(n[j % 2 == 0])) / N
+    jb = np.arange(L - 1) - centre
+    C_even = complex(np.sum(C[jb % 2 == 0])) / N
+    z = n_even - n_odd - 2j * C_even.imag
+    nu = float(np.sum(C + np.conj(C)).real) / N
+    return dict(N=N, n_odd=n_odd, n_even=n_even, C_even=C_even, A=abs(z), phi=float(np.angle(z)), nu=nu)
+
+
 def to_vector(mps: MPS) -> np.ndarray:
     """Dense state vector Lambda_0 B_0 ... B_{L-1} (small L only); site 0 slowest."""
     psi = mps.lam[0][None, :]                      # (1, chi_0)

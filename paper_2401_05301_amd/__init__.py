@@ -25,7 +25,7 @@ EXPORTS = [
     "tebd_opts_default", "mps_init_cdw", "mps_init_product", "mps_init_state", "tebd_layer", "tebd_step",
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
-    "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve",
+    "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve", "measure_quasi_local",
 ]
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "herm_eig": 2, "herm_apply": 3, "jac_gram": 4, "jac_rotate": 5}
 
@@ -100,6 +100,7 @@ def _load():
         "mps_profile_read": (st, [H, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_double)]),
         "tebd_serve": (st, [P(Request), ctypes.c_int32, P(ServeOpts), P(ServeResult), P(ctypes.c_double),
                             P(ctypes.c_double), P(ctypes.c_double)]),
+        "measure_quasi_local": (st, [H, ctypes.c_int32, P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -210,6 +211,14 @@ def measure_local(h, L: int):
     C = c[0:2 * (L - 1):2] + 1j * c[1:2 * (L - 1):2]
     D = dd[0:2 * (L - 2):2] + 1j * dd[1:2 * (L - 2):2]
     return n, C, D
+
+
+def measure_quasi_local(h, centre: int):
+    """Quasi-local observables (see ptebd.h) as a dict."""
+    out = np.zeros(8)
+    _check(_lib.measure_quasi_local(h, int(centre), _dptr(out)))
+    return dict(N=out[0], n_odd=out[1], n_even=out[2], C_even=complex(out[3], out[4]), A=out[5], phi=out[6],
+                nu=out[7])
 
 
 def mps_set_model(h, model: Model):
@@ -343,6 +352,13 @@ class MPS:
 
     def measure(self):
         return measure_local(self.h, self.L)
+
+    def quasi_local(self, centre: int):
+        return measure_quasi_local(self.h, centre)
+
+    @classmethod
+    def product(cls, model: Model, opts: Opts, occ):
+        return cls(mps_init_product(model, opts, occ), model)
 
     def bond_dims(self):
         return mps_bond_dims(self.h, self.L)

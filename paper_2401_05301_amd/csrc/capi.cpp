@@ -234,6 +234,47 @@ tebd_status measure_local(tebd_mps* M, double* n, double* c_nn, double* c_nnn) {
   return guard([&] { ptebd::measure(M, n, c_nn, c_nnn); });
 }
 
+tebd_status measure_quasi_local(tebd_mps* M, int32_t centre, double* out) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  if (!out) return fail(TEBD_EINVAL, "out is NULL");
+  if (centre < 0 || centre >= M->L) return fail(TEBD_EINVAL, "centre must be a site index");
+  ProfBind pb(M);
+  return guard([&] {
+    const int L = M->L;
+    std::vector<double> n(L), c(2 * (L - 1));
+    ptebd::measure(M, n.data(), c.data(), nullptr);
+    // j = i - centre; the centre site is even
+    double N = 0.0, nodd = 0.0, neven = 0.0, cr = 0.0, ci = 0.0, re_all = 0.0;
+    for (int i = 0; i < L; ++i) {
+      N += n[i];
+      if (((i - centre) & 1) == 0) neven += n[i];
+      else nodd += n[i];
+    }
+    for (int i = 0; i + 1 < L; ++i) {
+      re_all += c[2 * i];
+      if (((i - centre) & 1) == 0) {
+        cr += c[2 * i];
+        ci += c[2 * i + 1];
+      }
+    }
+    if (!(N > 0.0)) throw ptebd::Error(TEBD_ESTATE, "quasi-local observables need a state with particles");
+    nodd /= N;
+    neven /= N;
+    cr /= N;
+    ci /= N;
+    const double zr = neven - nodd, zi = -2.0 * ci;   // A e^{i phi} = n_even - n_odd - 2 i Im C_even
+    out[0] = N;
+    out[1] = nodd;
+    out[2] = neven;
+    out[3] = cr;
+    out[4] = ci;
+    out[5] = std::hypot(zr, zi);
+    out[6] = std::atan2(zi, zr);
+    out[7] = 2.0 * re_all / N;                          // nu = (1/N) sum_j (C_j + C_j^*)
+  });
+}
+
 tebd_status mps_set_model(tebd_mps* M, const tebd_model* model) {
   tebd_status st = usable(M);
   if (st) return st;

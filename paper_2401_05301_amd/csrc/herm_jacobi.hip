@@ -53,16 +53,20 @@ struct Rot {
   double cs, sn, er, ei;
 };
 
+// cs^2 + sn^2 = 1 and |e| = 1 hold to rounding whatever the accuracy of t,
+// since cs and e come from reciprocal square roots of the very quantities
+// they normalise; t only sets the angle.
 __device__ __forceinline__ Rot make_rot(double app, double aqq, double cre, double cim, double thr) {
   Rot r{1.0, 0.0, 1.0, 0.0};
-  const double c = sqrt(cre * cre + cim * cim);
-  if (c > thr) {
-    const double tau = (aqq - app) / (2.0 * c);
+  const double c2 = cre * cre + cim * cim;
+  if (c2 > thr * thr) {
+    const double rc = rsqrt(c2);   // 1 / |C_pq|
+    const double tau = 0.5 * (aqq - app) * rc;
     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    r.cs = 1.0 / sqrt(1.0 + t * t);
+    r.cs = rsqrt(1.0 + t * t);
     r.sn = t * r.cs;
-    r.er = cre / c;
-    r.ei = -cim / c;
+    r.er = cre * rc;
+    r.ei = -cim * rc;
   }
   return r;
 }
@@ -142,12 +146,22 @@ __global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
   const int tid = threadIdx.x;
   int I, J;
   round_pair(a.nb, round, blockIdx.x, I, J);
-  for (int idx = tid; idx < PR * PR; idx += kEigThreads) {
+  double vc[PR * PR / kEigThreads][2];
+#pragma unroll
+  for (int u = 0; u < PR * PR / kEigThreads; ++u) {
+    const int idx = tid + kEigThreads * u;
     const int p = idx / PR, q = idx % PR;
-    const int gp = pidx(I, J, p), gq = pidx(I, J, q);
-    const bool ok = gp < a.n && gq < a.n;
-    Cr[p][q] = ok ? a.hr[(int64_t)gp * a.ldh + gq] : 0.0;
-    Ci[p][q] = ok ? a.hi[(int64_t)gp * a.ldh + gq] : 0.0;
+    const int gp = min(pidx(I, J, p), a.n - 1), gq = min(pidx(I, J, q), a.n - 1);
+    vc[u][0] = a.hr[(int64_t)gp * a.ldh + gq];
+    vc[u][1] = a.hi[(int64_t)gp * a.ldh + gq];
+  }
+#pragma unroll
+  for (int u = 0; u < PR * PR / kEigThreads; ++u) {
+    const int idx = tid + kEigThreads * u;
+    const int p = idx / PR, q = idx % PR;
+    const bool ok = pidx(I, J, p) < a.n && pidx(I, J, q) < a.n;
+    Cr[p][q] = ok ? vc[u][0] : 0.0;
+    Ci[p][q] = ok ? vc[u][1] : 0.0;
     Qr[p][q] = (p == q) ? 1.0 : 0.0;
     Qi[p][q] = 0.0;
   }
@@ -196,16 +210,33 @@ __global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
     round_pair(a.nb, round, P2, I2, J2);
     const double* q1 = a.qbuf + (int64_t)P1 * 2 * PR * PR;
     const double* q2 = a.qbuf + (int64_t)P2 * 2 * PR * PR;
-    for (int idx = tid; idx < PR * PR; idx += 256) {
+    // Unconditional loads (indices clamped into the matrix; an unflagged
+    // pair's slot holds stale but valid data), selected afterwards, so that
+    // all of them are in flight together.
+    double va[4][6];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + 256 * u;
       const int p = idx / PR, q = idx % PR;
-      const int gp = pidx(I1, J1, p), gq = pidx(I2, J2, q);
-      const bool ok = gp < a.n && gq < a.n;
-      Ar[p][q] = ok ? a.hr[(int64_t)gp * a.ldh + gq] : 0.0;
-      Ai[p][q] = ok ? a.hi[(int64_t)gp * a.ldh + gq] : 0.0;
-      Q1r[p][q] = f1 ? q1[idx] : (p == q ? 1.0 : 0.0);
-      Q1i[p][q] = f1 ? q1[PR * PR + idx] : 0.0;
-      Q2r[p][q] = f2 ? q2[idx] : (p == q ? 1.0 : 0.0);
-      Q2i[p][q] = f2 ? q2[PR * PR + idx] : 0.0;
+      const int gp = min(pidx(I1, J1, p), a.n - 1), gq = min(pidx(I2, J2, q), a.n - 1);
+      va[u][0] = a.hr[(int64_t)gp * a.ldh + gq];
+      va[u][1] = a.hi[(int64_t)gp * a.ldh + gq];
+      va[u][2] = q1[idx];
+      va[u][3] = q1[PR * PR + idx];
+      va[u][4] = q2[idx];
+      va[u][5] = q2[PR * PR + idx];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + 256 * u;
+      const int p = idx / PR, q = idx % PR;
+      const bool ok = pidx(I1, J1, p) < a.n && pidx(I2, J2, q) < a.n;
+      Ar[p][q] = ok ? va[u][0] : 0.0;
+      Ai[p][q] = ok ? va[u][1] : 0.0;
+      Q1r[p][q] = f1 ? va[u][2] : (p == q ? 1.0 : 0.0);
+      Q1i[p][q] = f1 ? va[u][3] : 0.0;
+      Q2r[p][q] = f2 ? va[u][4] : (p == q ? 1.0 : 0.0);
+      Q2i[p][q] = f2 ? va[u][5] : 0.0;
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -285,10 +316,16 @@ __global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
     double xr[8], xi[8];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
-      const int row = pidx(I, J, 4 * ks + (lane >> 4));
-      const bool ok = okc && row < a.n;
-      xr[ks] = ok ? a.wr[(int64_t)row * a.ldw + col] : 0.0;
-      xi[ks] = ok ? a.wi[(int64_t)row * a.ldw + col] : 0.0;
+      const int row = min(pidx(I, J, 4 * ks + (lane >> 4)), a.n - 1);
+      const int64_t o = (int64_t)row * a.ldw + min(col, ce - 1);
+      xr[ks] = a.wr[o];
+      xi[ks] = a.wi[o];
+    }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const bool ok = okc && pidx(I, J, 4 * ks + (lane >> 4)) < a.n;
+      xr[ks] = ok ? xr[ks] : 0.0;
+      xi[ks] = ok ? xi[ks] : 0.0;
     }
     f64x4 orr[2], oii[2];
 #pragma unroll
@@ -375,6 +412,39 @@ __global__ __launch_bounds__(256) void count_above_kernel(const double* hr, cons
   if ((threadIdx.x & 63) == 0 && c > 0) atomicAdd(count, c);
 }
 
+// X = I + A with A_ij = H_ij / (H_ii - H_jj) for |H_ij| > tol, |A_ij| capped
+// at 1/2: the first-order rotation of a nearly diagonal Hermitian H towards
+// its eigenbasis (X H X^+ has no off-diagonal entries to first order; A is
+// skew-Hermitian).
+__global__ __launch_bounds__(256) void perturb_rotation_kernel(const double* hr, const double* hi, int64_t ldh, int p,
+                                                               const double* tol, double* xr, double* xi,
+                                                               int64_t ldx) {
+  const double t = *tol;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)p * p;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p), j = (int)(e % p);
+    double ar = 0.0, ai = 0.0;
+    if (i == j) {
+      ar = 1.0;
+    } else {
+      const double h_r = hr[(int64_t)i * ldh + j], h_i = hi[(int64_t)i * ldh + j];
+      const double mag = sqrt(h_r * h_r + h_i * h_i);
+      if (mag > t) {
+        const double g = hr[(int64_t)i * ldh + i] - hr[(int64_t)j * ldh + j];
+        double sc;
+        if (fabs(g) * 0.5 >= mag)
+          sc = 1.0 / g;
+        else
+          sc = (g >= 0.0 ? 0.5 : -0.5) / mag;
+        ar = sc * h_r;
+        ai = sc * h_i;
+      }
+    }
+    xr[(int64_t)i * ldx + j] = ar;
+    xi[(int64_t)i * ldx + j] = ai;
+  }
+}
+
 // H_ii = 0 for i < p.
 __global__ void zero_diag_kernel(double* hr, double* hi, int64_t ldh, int p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -447,6 +517,14 @@ unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n,
   PTEBD_HIP(hipMemcpyAsync(h_count, count, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
   return *h_count;
+}
+
+void perturb_rotation(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double* xr,
+                      double* xi, int64_t ldx, hipStream_t s) {
+  const int64_t n = (int64_t)p * p;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  perturb_rotation_kernel<<<grid, 256, 0, s>>>(hr, hi, ldh, p, tol, xr, xi, ldx);
+  PTEBD_LAUNCH_CHECK();
 }
 
 }  // namespace ptebd

@@ -179,3 +179,36 @@ def test_layer_workers_give_identical_results(pt):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     assert all(np.array_equal(x, y) for x, y in zip(a[3], b[3]))
     assert a[4] == b[4]
+
+
+@pytest.mark.parametrize("L,N,d,chi,steps", [(41, 11, 3, 24, 6), (121, 27, 5, 16, 3)])
+def test_centred_cdw_quasi_local(pt, L, N, d, chi, steps):
+    """The experiment's workload shape (Sec. II B): a centred CDW with empty
+    wings under simulation [c] of Table I(b), quasi-local observables
+    against the oracle's (same state, same truncation)."""
+    import json
+    import os
+    from workloads import centred_cdw_occupations
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_params.json")))
+    p = golden["sims"]["c"]
+    dt = golden["dt"]
+    m = Model(L=L, d=d, U=p["U"], J=p["J"], Jnnn=p["Jnnn"], K=p["K"])
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-12)
+    occ = centred_cdw_occupations(L, N)
+    centre = (L - 1) // 2
+    note(f"centred CDW L={L} N={N} d={d} chi={chi} steps={steps}")
+    ores = otebd.run(m, tr, dt, steps, mps=otebd.MPS.product(d, occ))
+    g = pt.MPS.product(gpu_model(pt, m), pt.make_opts(chi, tr.w_max, tr.eps), occ)
+    for _ in range(steps):
+        g.step(dt)
+    n, C, D = g.measure()
+    tol = bar(ores)
+    assert np.abs(n - ores["n"][-1]).max() <= tol
+    assert np.abs(C - ores["C"][-1]).max() <= tol
+    q = g.quasi_local(centre)
+    qo = otebd.quasi_local(ores["n"][-1], ores["C"][-1], centre)
+    assert abs(q["N"] - N) < 1e-9
+    for key in ("n_odd", "n_even", "A", "phi", "nu"):
+        assert abs(q[key] - qo[key]) <= 10 * tol, key
+    assert abs(q["C_even"] - qo["C_even"]) <= 10 * tol
+    g.close()

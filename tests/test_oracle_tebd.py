@@ -227,3 +227,61 @@ def test_gate_update_on_random_mps_keeps_gauge():
     for b in (3, 4):
         assert abs(np.sum(mps.lam[b] ** 2) - 1.0) < 1e-14
     assert mps.w_total > 0
+
+
+# ---------------------------------------------------------------- quasi-local observables (Sec. II B)
+def test_centred_cdw_occupations():
+    from workloads import centred_cdw_occupations
+    occ = centred_cdw_occupations(121, 27)
+    assert sum(occ) == 27 and len(occ) == 121
+    c = 60
+    # the centre (j = 0) is occupied, odd j are empty, wings of equal length
+    assert occ[c] == 1 and all(occ[c + j] == 0 for j in range(-59, 60, 2))
+    first = occ.index(1)
+    last = len(occ) - 1 - occ[::-1].index(1)
+    assert c - first == last - c == 26
+
+
+def test_quasi_local_initial_state_and_hand_example():
+    quasi_local = tebd.quasi_local
+    from workloads import centred_cdw_occupations
+    occ = np.array(centred_cdw_occupations(21, 5), dtype=float)
+    q = quasi_local(occ, np.zeros(20, dtype=complex), 10)
+    # CDW on the even sites: n_even = 1, n_odd = 0, A = 1, phi = 0, nu = 0
+    assert q["N"] == 5 and q["n_odd"] == 0.0 and q["n_even"] == 1.0
+    assert q["A"] == 1.0 and q["phi"] == 0.0 and q["nu"] == 0.0
+    # hand example: L = 5, centre 2 (j = -2..2), bonds j = -2..1
+    n = np.array([0.1, 0.2, 0.3, 0.4, 0.5])
+    C = np.array([0.1 + 0.2j, 0.3 - 0.1j, -0.2 + 0.05j, 0.05 + 0.0j])
+    q = quasi_local(n, C, 2)
+    N = 1.5
+    assert np.isclose(q["n_even"], (0.1 + 0.3 + 0.5) / N) and np.isclose(q["n_odd"], (0.2 + 0.4) / N)
+    ce = (C[0] + C[2]) / N          # bonds j = -2 and j = 0
+    assert np.isclose(q["C_even"], ce)
+    z = q["n_even"] - q["n_odd"] - 2j * ce.imag
+    assert np.isclose(q["A"], abs(z)) and np.isclose(q["phi"], np.angle(z))
+    assert np.isclose(q["nu"], 2 * np.sum(C.real) / N)
+
+
+def test_quasi_local_free_fermion_centred_cdw():
+    """Hard-core bosons (d = 2) from a centred CDW with empty wings: the
+    quasi-local values of the oracle's TEBD equal those of the Trotterised
+    free-fermion propagator (same dt, no truncation)."""
+    from workloads import centred_cdw_occupations
+    L, N, dt, steps = 13, 5, 0.05, 20
+    occ = centred_cdw_occupations(L, N)
+    m = Model(L=L, d=2, U=0.0, J=1.0, Jnnn=0.0, K=0.0)
+    mps = tebd.MPS.product(2, occ)
+    gates = tebd.GateCache(m)
+    for _ in range(steps):
+        tebd.step(mps, gates, dt, Trunc(chi_max=64, w_max=0.0, eps=1e-14))
+    n, C, _ = tebd.measure(mps)
+    q = tebd.quasi_local(n, C, (L - 1) // 2)
+    n_ex, C_ex, _ = ref.free_observables(ref.propagator_trotter(m, dt, steps), occ)
+    q_ex = tebd.quasi_local(n_ex, C_ex, (L - 1) // 2)
+    assert abs(q["N"] - N) < 1e-12
+    for key in ("n_odd", "n_even", "A", "phi", "nu"):
+        assert abs(q[key] - q_ex[key]) < 1e-10, key
+    assert abs(q["C_even"] - q_ex["C_even"]) < 1e-10
+    # the wave has begun to relax: particles have moved onto the odd sites
+    assert 0.05 < q["n_odd"] < 0.95

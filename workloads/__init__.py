@@ -76,6 +76,19 @@ def cdw_occupations(L: int, first_occupied: int = 1) -> List[int]:
     return [1 if (i % 2 == 0) == bool(first_occupied) else 0 for i in range(L)]
 
 
+def centred_cdw_occupations(L: int, N: int) -> List[int]:
+    """Centred charge-density wave with empty wings (Sec. II B): N bosons on
+    the sites j = 0, +-2, ..., +-(N-1) counted from the centre site
+    (L - 1) / 2, every other site empty.  L and N odd, N <= (L + 1) / 2."""
+    if L % 2 == 0 or N % 2 == 0 or N > (L + 1) // 2 or N < 1:
+        raise ValueError("L and N must be odd with N <= (L + 1) / 2")
+    c = (L - 1) // 2
+    occ = [0] * L
+    for k in range(-(N - 1), N, 2):
+        occ[c + k] = 1
+    return occ
+
+
 def bulk_bond_dims(L: int, d: int, chi: int) -> List[int]:
     """Bond dimensions chi_b = min(d^b, d^(L-b), chi), b = 0..L."""
     out = []
