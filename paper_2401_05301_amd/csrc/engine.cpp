@@ -400,13 +400,6 @@ int partial_sweeps() {
   return v;
 }
 
-// Intermediate Rayleigh-Ritz by one first-order rotation instead of partial
-// Jacobi sweeps (PTEBD_RR=perturb).
-bool rr_perturb() {
-  static const bool v = std::getenv("PTEBD_RR") && std::string(std::getenv("PTEBD_RR")) == "perturb";
-  return v;
-}
-
 int inner_sweeps() {
   static const int v = std::getenv("PTEBD_INNER_SWEEPS") ? std::atoi(std::getenv("PTEBD_INNER_SWEEPS")) : 1;
   return v;
@@ -708,18 +701,7 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, kDampRel * h_vals[0], M->ratio_bits,
                                        M->h_ratio, s);
     const bool jac = !(ratio <= kDiagCoupling);
-    if (jac && rr_perturb()) {
-      // first-order rotation X = I + A, A_ij = H_ij / (H_ii - H_jj), made
-      // unitary by a symmetric orthonormalisation of its rows
-      tebd_mps::Z X{M->sZ2.re, M->sZ2.im}, T{M->sY2.re, M->sY2.im};
-      perturb_rotation(M->sH.re, M->sH.im, p, p, M->info_d + 7, X.re, X.im, p, s);
-      lowdin(M, X, T, p, p);
-      PTEBD_HIP(hipMemcpyAsync(M->sW.re, X.re, sizeof(double) * (size_t)p * p, hipMemcpyDeviceToDevice, s));
-      PTEBD_HIP(hipMemcpyAsync(M->sW.im, X.im, sizeof(double) * (size_t)p * p, hipMemcpyDeviceToDevice, s));
-      rotate(M->sW, 0, p, true);
-      rayleigh(M, p, r);
-      herm_diag(M->sH.re, p, p, M->norms, s);
-    } else if (jac) {
+    if (jac) {
       run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, partial_sweeps());
       herm_diag(M->sH.re, p, p, M->norms, s);
       rotate(M->sW, 0, p, true);

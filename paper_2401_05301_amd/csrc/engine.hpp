@@ -38,7 +38,7 @@ struct tebd_mps {
   Z nY, nZ, nY2, nZ2;           // Newton-Schulz iterates (p x p)
   double* ns_part = nullptr;    // Newton-Schulz residual partial sums (256)
   double* h_part = nullptr;     // pinned host mirror of ns_part
-  unsigned long long* ratio_bits = nullptr;   // perturbative Rayleigh-Ritz: max coupling / gap (bits of a double)
+  unsigned long long* ratio_bits = nullptr;   // largest relative coupling of a Rayleigh matrix (bits of a double)
   unsigned long long* h_ratio = nullptr;      // pinned host mirror
   double* pwork = nullptr;      // Newton-Schulz scale: row sums and power-iteration vectors (5p + 1)
   int sub_p = 0;                // subspace width reserved (0: not reserved)

@@ -125,6 +125,79 @@ SpectralGate eig_three_site(const ModelP& m, int j) {
   return g;
 }
 
+// ---- super sites (Sec. II B: every two physical sites form one site of
+// dimension d^2, which makes the NNN model nearest-neighbour).  The NN hop
+// inside a super site and the on-site terms of its two sites are shared by
+// the gates containing that super site (one at a chain end, two in the bulk);
+// the NN hop between the super sites and both NNN hops across them belong to
+// gate K alone, so that the terms sum to H.
+int gates_containing_super(int Ls, int K) { return std::min(K, Ls - 2) - std::max(0, K - 1) + 1; }
+
+std::vector<double> supersite_term(const ModelP& m, int K) {
+  const int d = m.d, D = d * d * d * d, Ls = m.L / 2;
+  std::vector<double> h((size_t)D * D, 0.0);
+  auto id = [d](const int* s) { return ((s[0] * d + s[1]) * d + s[2]) * d + s[3]; };
+  const double inL = 1.0 / gates_containing_super(Ls, K), inR = 1.0 / gates_containing_super(Ls, K + 1);
+  int s[4];
+  for (s[0] = 0; s[0] < d; ++s[0])
+    for (s[1] = 0; s[1] < d; ++s[1])
+      for (s[2] = 0; s[2] < d; ++s[2])
+        for (s[3] = 0; s[3] < d; ++s[3]) {
+          const int in = id(s);
+          h[(size_t)in * D + in] += (onsite(m, 2 * K, s[0]) + onsite(m, 2 * K + 1, s[1])) * inL +
+                                    (onsite(m, 2 * K + 2, s[2]) + onsite(m, 2 * K + 3, s[3])) * inR;
+          // b_x^+ b_y with amplitude w: moves one boson from position y to x
+          auto hop = [&](int x, int y, double w) {
+            if (s[y] >= 1 && s[x] + 1 < d) {
+              const double amp = w * std::sqrt((double)(s[x] + 1)) * std::sqrt((double)s[y]);
+              int t[4] = {s[0], s[1], s[2], s[3]};
+              t[x] += 1;
+              t[y] -= 1;
+              h[(size_t)id(t) * D + in] += amp;
+            }
+          };
+          hop(0, 1, -m.J * inL); hop(1, 0, -m.J * inL);       // inside super site K
+          hop(2, 3, -m.J * inR); hop(3, 2, -m.J * inR);       // inside super site K+1
+          hop(1, 2, -m.J); hop(2, 1, -m.J);                   // NN across
+          hop(0, 2, -m.Jnnn); hop(2, 0, -m.Jnnn);             // NNN (2K, 2K+2)
+          hop(1, 3, -m.Jnnn); hop(3, 1, -m.Jnnn);             // NNN (2K+1, 2K+3)
+        }
+  return h;
+}
+
+SpectralGate eig_supersite(const ModelP& m, int K) {
+  const int d = m.d, D = d * d * d * d;
+  std::vector<double> h = supersite_term(m, K);
+  SpectralGate g;
+  g.n = D;
+  g.w.assign(D, 0.0);
+  g.V.assign((size_t)D * D, 0.0);
+  int col = 0;
+  for (int N = 0; N <= 4 * (d - 1); ++N) {
+    std::vector<int> idx;
+    for (int i = 0; i < D; ++i) {
+      int r = i, tot = 0;
+      for (int q = 0; q < 4; ++q) {
+        tot += r % d;
+        r /= d;
+      }
+      if (tot == N) idx.push_back(i);
+    }
+    const int n = (int)idx.size();
+    if (n == 0) continue;
+    std::vector<double> blk((size_t)n * n), w, v;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) blk[(size_t)p * n + q] = h[(size_t)idx[p] * D + idx[q]];
+    jacobi_sym(blk, n, w, v);
+    for (int k = 0; k < n; ++k, ++col) {
+      g.w[col] = w[k];
+      for (int p = 0; p < n; ++p) g.V[(size_t)idx[p] * D + col] = v[(size_t)p * n + k];
+    }
+  }
+  if (col != D) throw std::logic_error("gate sectors do not cover the super-site space");
+  return g;
+}
+
 void gate_matrix(const SpectralGate& g, double tau, std::vector<double>& re, std::vector<double>& im) {
   const int D = g.n;
   re.assign((size_t)D * D, 0.0);

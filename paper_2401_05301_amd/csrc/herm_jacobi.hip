@@ -412,39 +412,6 @@ __global__ __launch_bounds__(256) void count_above_kernel(const double* hr, cons
   if ((threadIdx.x & 63) == 0 && c > 0) atomicAdd(count, c);
 }
 
-// X = I + A with A_ij = H_ij / (H_ii - H_jj) for |H_ij| > tol, |A_ij| capped
-// at 1/2: the first-order rotation of a nearly diagonal Hermitian H towards
-// its eigenbasis (X H X^+ has no off-diagonal entries to first order; A is
-// skew-Hermitian).
-__global__ __launch_bounds__(256) void perturb_rotation_kernel(const double* hr, const double* hi, int64_t ldh, int p,
-                                                               const double* tol, double* xr, double* xi,
-                                                               int64_t ldx) {
-  const double t = *tol;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)p * p;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / p), j = (int)(e % p);
-    double ar = 0.0, ai = 0.0;
-    if (i == j) {
-      ar = 1.0;
-    } else {
-      const double h_r = hr[(int64_t)i * ldh + j], h_i = hi[(int64_t)i * ldh + j];
-      const double mag = sqrt(h_r * h_r + h_i * h_i);
-      if (mag > t) {
-        const double g = hr[(int64_t)i * ldh + i] - hr[(int64_t)j * ldh + j];
-        double sc;
-        if (fabs(g) * 0.5 >= mag)
-          sc = 1.0 / g;
-        else
-          sc = (g >= 0.0 ? 0.5 : -0.5) / mag;
-        ar = sc * h_r;
-        ai = sc * h_i;
-      }
-    }
-    xr[(int64_t)i * ldx + j] = ar;
-    xi[(int64_t)i * ldx + j] = ai;
-  }
-}
-
 // H_ii = 0 for i < p.
 __global__ void zero_diag_kernel(double* hr, double* hi, int64_t ldh, int p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -519,12 +486,5 @@ unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n,
   return *h_count;
 }
 
-void perturb_rotation(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double* xr,
-                      double* xi, int64_t ldx, hipStream_t s) {
-  const int64_t n = (int64_t)p * p;
-  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
-  perturb_rotation_kernel<<<grid, 256, 0, s>>>(hr, hi, ldh, p, tol, xr, xi, ldx);
-  PTEBD_LAUNCH_CHECK();
-}
 
 }  // namespace ptebd

@@ -72,10 +72,6 @@ double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, con
 // Number of entries i < j of H (n x n) with |H_ij| > *tol (synchronises).
 unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n, const double* tol,
                          unsigned int* count, unsigned int* h_count, hipStream_t s);
-// X = I + A, A_ij = H_ij / (H_ii - H_jj) for |H_ij| > *tol (|A_ij| <= 1/2):
-// first-order rotation of a nearly diagonal Hermitian H towards its eigenbasis.
-void perturb_rotation(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double* xr,
-                      double* xi, int64_t ldx, hipStream_t s);
 // H_ii = 0, i < p.
 void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s);
 // *out = c * u * sum_i |H_ii|
