@@ -94,6 +94,13 @@ typedef struct {
   int32_t workers;        /* gate workspaces run concurrently within a layer (own stream and host
                              thread each); 0 = min(4, gates per layer).  Device memory grows by one
                              gate workspace per worker. */
+  int32_t supersite;      /* 1: the paper's super-site chain (Sec. II B): every two physical sites
+                             form one site of dimension d^2 and two-site gates act on neighbouring
+                             super sites, Strang A(dt/2) B(dt) A(dt/2) over gates K even / K odd.
+                             The physical L must be even.  Inputs and measure_local stay physical
+                             (L sites); mps_bond_dims, mps_lambda and mps_site see the L/2 super
+                             sites (L/2 + 1 bonds); tebd_layer takes group 0 or 1;
+                             mps_init_state is three-site only.  0: three-site gates (default). */
 } tebd_opts;
 
 typedef struct tebd_mps tebd_mps;

@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("chi_max", ctypes.c_int32), ("trunc_weight", ctypes.c_double), ("trunc_rel", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("svd", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32)]
+                ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32), ("supersite", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -128,13 +128,14 @@ def make_model(L: int, d: int, U: float, J: float = 1.0, Jnnn: float = 0.0, K: f
 
 
 def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int = FP64, svd: int = SVD_JACOBI,
-              max_sweeps: int = 40, stream: Optional[int] = None, workers: int = 0) -> Opts:
+              max_sweeps: int = 40, stream: Optional[int] = None, workers: int = 0, supersite: bool = False) -> Opts:
     o = Opts()
     _lib.tebd_opts_default(ctypes.byref(o))
     o.chi_max, o.trunc_weight, o.trunc_rel = chi_max, w_max, eps
     o.prec, o.svd, o.max_sweeps = prec, svd, max_sweeps
     o.stream = stream
     o.workers = workers
+    o.supersite = int(bool(supersite))
     return o
 
 
@@ -329,20 +330,23 @@ def tebd_serve(requests, max_active: int = 8, hbm_budget: float = 0.0, prec: int
 class MPS:
     """Owning wrapper of a handle (frees it on close / garbage collection)."""
 
-    def __init__(self, handle, model: Model, keep=None):
+    def __init__(self, handle, model: Model, keep=None, supersite: bool = False):
         self.h = handle
         self.model = model
-        self.L = model.L
-        self.d = model.d
+        self.L = model.L                  # physical sites (observables)
+        self.supersite = bool(supersite)
+        # sites and local dimension of the chain the MPS lives on
+        self.sites = model.L // 2 if supersite else model.L
+        self.d = model.d * model.d if supersite else model.d
         self._keep = keep
 
     @classmethod
     def cdw(cls, model: Model, opts: Opts, first_occupied: int = 1):
-        return cls(mps_init_cdw(model, opts, first_occupied), model)
+        return cls(mps_init_cdw(model, opts, first_occupied), model, supersite=opts.supersite)
 
     @classmethod
     def from_tensors(cls, model: Model, opts: Opts, B, lam):
-        return cls(mps_init_state(model, opts, B, lam), model)
+        return cls(mps_init_state(model, opts, B, lam), model, supersite=opts.supersite)
 
     def layer(self, group: int, tau: float):
         tebd_layer(self.h, group, tau)
@@ -358,10 +362,10 @@ class MPS:
 
     @classmethod
     def product(cls, model: Model, opts: Opts, occ):
-        return cls(mps_init_product(model, opts, occ), model)
+        return cls(mps_init_product(model, opts, occ), model, supersite=opts.supersite)
 
     def bond_dims(self):
-        return mps_bond_dims(self.h, self.L)
+        return mps_bond_dims(self.h, self.sites)
 
     def lam(self, bond: int):
         return mps_lambda(self.h, bond)

@@ -60,7 +60,9 @@ tebd_status check_model(const tebd_model* m) {
 tebd_status check_opts(const tebd_opts* o, int d) {
   if (!o) return fail(TEBD_EINVAL, "opts is NULL");
   if (o->chi_max < 1) return fail(TEBD_EINVAL, "chi_max must be >= 1");
-  if ((int64_t)o->chi_max * d > 8192) return fail(TEBD_EINVAL, "chi_max * d must be <= 8192");
+  if (o->supersite != 0 && o->supersite != 1) return fail(TEBD_EINVAL, "supersite must be 0 or 1");
+  const int64_t dl = o->supersite ? (int64_t)d * d : d;   // local dimension of the chain the MPS lives on
+  if ((int64_t)o->chi_max * dl > 8192) return fail(TEBD_EINVAL, "chi_max * (local dimension) must be <= 8192");
   if (!finite(o->trunc_weight) || o->trunc_weight < 0) return fail(TEBD_EINVAL, "trunc_weight must be >= 0");
   if (!finite(o->trunc_rel) || o->trunc_rel < 0) return fail(TEBD_EINVAL, "trunc_rel must be >= 0");
   if (o->prec < TEBD_FP64 || o->prec > TEBD_FP32_SPLIT) return fail(TEBD_EINVAL, "bad precision");
@@ -80,11 +82,16 @@ tebd_status create(const tebd_model* model, const tebd_opts* opts, tebd_mps** ou
   if (st) return st;
   st = check_opts(opts, model->d);
   if (st) return st;
+  if (opts->supersite && (model->L % 2 != 0 || model->L < 4))
+    return fail(TEBD_EINVAL, "a super-site chain needs an even number of physical sites, at least 4");
   tebd_mps* M = new tebd_mps();
   st = guard([&] {
     M->opts = *opts;
-    M->L = model->L;
-    M->d = model->d;
+    M->phys_L = model->L;
+    M->pd = model->d;
+    M->super = opts->supersite != 0;
+    M->L = M->super ? model->L / 2 : model->L;
+    M->d = M->super ? model->d * model->d : model->d;
     M->chi_max = opts->chi_max;
     if (opts->stream) {
       M->stream = (hipStream_t)opts->stream;
@@ -160,6 +167,7 @@ tebd_status mps_init_state(const tebd_model* model, const tebd_opts* opts, const
   if (st) return st;
   st = check_opts(opts, model->d);
   if (st) return st;
+  if (opts->supersite) return fail(TEBD_EINVAL, "mps_init_state loads three-site chains only");
   ptebd::Sizes sz = ptebd::plan_sizes(model->L, model->d, opts->chi_max);
   if (chi[0] != 1 || chi[model->L] != 1) return fail(TEBD_EINVAL, "chi[0] and chi[L] must be 1");
   for (int b = 0; b <= model->L; ++b)
@@ -179,7 +187,8 @@ tebd_status mps_init_state(const tebd_model* model, const tebd_opts* opts, const
 tebd_status tebd_layer(tebd_mps* M, int32_t group, double tau) {
   tebd_status st = usable(M);
   if (st) return st;
-  if (group < 0 || group > 2) return fail(TEBD_EINVAL, "group must be 0, 1 or 2");
+  if (group < 0 || group > (M->super ? 1 : 2))
+    return fail(TEBD_EINVAL, M->super ? "group must be 0 or 1 on a super-site chain" : "group must be 0, 1 or 2");
   if (!std::isfinite(tau)) return fail(TEBD_EINVAL, "tau must be finite");
   ProfBind pb(M);
   return guard([&] { ptebd::layer(M, group, tau); });
@@ -192,6 +201,12 @@ tebd_status tebd_step(tebd_mps* M, double dt) {
   ProfBind pb(M);
   return guard([&] {
     const double h = 0.5 * dt;
+    if (M->super) {   // A(dt/2) B(dt) A(dt/2), A = even K, B = odd K
+      ptebd::layer(M, 0, h);
+      ptebd::layer(M, 1, dt);
+      ptebd::layer(M, 0, h);
+      return;
+    }
     ptebd::layer(M, 0, h);
     ptebd::layer(M, 1, h);
     ptebd::layer(M, 2, dt);
@@ -238,10 +253,10 @@ tebd_status measure_quasi_local(tebd_mps* M, int32_t centre, double* out) {
   tebd_status st = usable(M);
   if (st) return st;
   if (!out) return fail(TEBD_EINVAL, "out is NULL");
-  if (centre < 0 || centre >= M->L) return fail(TEBD_EINVAL, "centre must be a site index");
+  if (centre < 0 || centre >= M->phys_L) return fail(TEBD_EINVAL, "centre must be a site index");
   ProfBind pb(M);
   return guard([&] {
-    const int L = M->L;
+    const int L = M->phys_L;
     std::vector<double> n(L), c(2 * (L - 1));
     ptebd::measure(M, n.data(), c.data(), nullptr);
     // j = i - centre; the centre site is even
@@ -280,7 +295,7 @@ tebd_status mps_set_model(tebd_mps* M, const tebd_model* model) {
   if (st) return st;
   st = check_model(model);
   if (st) return st;
-  if (model->L != M->L || model->d != M->d) return fail(TEBD_EINVAL, "set_model must keep L and d");
+  if (model->L != M->phys_L || model->d != M->pd) return fail(TEBD_EINVAL, "set_model must keep L and d");
   return guard([&] {
     PTEBD_HIP(hipStreamSynchronize(M->stream));
     ptebd::set_model(M, to_model(model));
@@ -337,6 +352,14 @@ tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t
   if (st) return st;
   st = check_opts(opts, model->d);
   if (st) return st;
+  if (opts->supersite) {
+    if (model->L % 2 != 0 || model->L < 4)
+      return fail(TEBD_EINVAL, "a super-site chain needs an even number of physical sites, at least 4");
+    const int Ls = model->L / 2;
+    *bytes = ptebd::plan_sizes2(Ls, model->d * model->d, opts->chi_max)
+                 .bytes(ptebd::auto_workers(Ls, opts->workers, true));
+    return TEBD_OK;
+  }
   *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max).bytes(ptebd::auto_workers(model->L, opts->workers));
   return TEBD_OK;
 }
@@ -347,6 +370,10 @@ tebd_status tebd_prepare(tebd_mps* M, double dt) {
   if (!std::isfinite(dt)) return fail(TEBD_EINVAL, "dt must be finite");
   return guard([&] {
     ptebd::prepare_gates(M, 0, 0.5 * dt);
+    if (M->super) {
+      ptebd::prepare_gates(M, 1, dt);
+      return;
+    }
     ptebd::prepare_gates(M, 1, 0.5 * dt);
     ptebd::prepare_gates(M, 2, dt);
   });

@@ -95,13 +95,22 @@ __global__ __launch_bounds__(256) void site_densities_kernel(const double* const
   if (threadIdx.x == 0) n_out[i] = t;
 }
 
-__global__ void hop_kscale_kernel(const double* lam, int cl, int d, double* ks) {
+// Occupation that a creation operator raises, in local state s: the site
+// itself (mode 0, local dimension D = d) or the first / second physical site
+// of a super site (modes 1 / 2, s = s1 d + s2).
+__device__ __forceinline__ int op_level(int s, int d, int mode) { return mode == 0 ? s : (mode == 1 ? s / d : s % d); }
+
+// ks[r'] = Lambda[a]^2 sqrt(level(s)) for the row r = r' + shift = a D + s of
+// B (the row r' pairs with the state lowered by the operator), 0 when
+// level(s) = 0 (the paired row then belongs to another a or level).
+__global__ void op_kscale_kernel(const double* lam, int cl, int D, int d, int shift, int mode, double* ks) {
   const int rp = blockIdx.x * blockDim.x + threadIdx.x;
-  const int K = cl * d - 1;
+  const int K = cl * D - shift;
   if (rp >= K) return;
-  const int r = rp + 1;
-  const int a = r / d, s = r % d;
-  ks[rp] = s >= 1 ? lam[a] * lam[a] * sqrt((double)s) : 0.0;
+  const int r = rp + shift;
+  const int a = r / D, s = r % D;
+  const int lv = op_level(s, d, mode);
+  ks[rp] = lv >= 1 ? lam[a] * lam[a] * sqrt((double)lv) : 0.0;
 }
 
 // sum_{y, t>=1, c} sqrt(t) conj(B(y, t-1, c)) F(y, t, c), in two passes:
@@ -110,17 +119,20 @@ __global__ void hop_kscale_kernel(const double* lam, int cl, int d, double* ks) 
 constexpr int kHopBlocks = 256;
 
 __global__ __launch_bounds__(256) void close_hop_part_kernel(const double* br, const double* bi, const double* fr,
-                                                             const double* fi, int chi, int d, int cr, double* part) {
+                                                             const double* fi, int chi, int D, int cr, int d,
+                                                             int shift, int mode, double* part) {
   __shared__ double sh[4];
-  const int64_t tot = (int64_t)chi * (d - 1) * cr;
+  const int64_t tot = (int64_t)chi * D * cr;
   double accr = 0.0, acci = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)kHopBlocks * 256) {
-    const int y = (int)(e / ((int64_t)(d - 1) * cr));
-    const int t = 1 + (int)((e / cr) % (d - 1));
+    const int y = (int)(e / ((int64_t)D * cr));
+    const int t = (int)((e / cr) % D);
     const int c = (int)(e % cr);
-    const int64_t ob = ((int64_t)y * d + (t - 1)) * cr + c;
-    const int64_t of = ((int64_t)y * d + t) * cr + c;
-    const double w = sqrt((double)t);
+    const int lv = op_level(t, d, mode);
+    if (lv < 1) continue;
+    const int64_t ob = ((int64_t)y * D + (t - shift)) * cr + c;
+    const int64_t of = ((int64_t)y * D + t) * cr + c;
+    const double w = sqrt((double)lv);
     // conj(b) * f
     accr += w * (br[ob] * fr[of] + bi[ob] * fi[of]);
     acci += w * (br[ob] * fi[of] - bi[ob] * fr[of]);
@@ -130,6 +142,49 @@ __global__ __launch_bounds__(256) void close_hop_part_kernel(const double* br, c
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = sr;
     part[2 * blockIdx.x + 1] = si;
+  }
+}
+
+// Per super site K (one work-group each): n of its first and second
+// physical site and <b+_first b_second>, from Lambda_K^2 and B_K (D = d^2):
+// out[4 K ..] = (n1, n2, Re C, Im C).
+__global__ __launch_bounds__(256) void supersite_local_kernel(const double* const* br, const double* const* bi,
+                                                              const double* const* lam, const int* chil,
+                                                              const int* chir, int d, double* out) {
+  __shared__ double sh[4];
+  const int K = blockIdx.x;
+  const int D = d * d;
+  const int cl = chil[K], cr = chir[K];
+  const int64_t tot = (int64_t)cl * D * cr;
+  const double* pr = br[K];
+  const double* pi = bi[K];
+  const double* lm = lam[K];
+  double n1 = 0.0, n2 = 0.0, cre = 0.0, cim = 0.0;
+  for (int64_t e = threadIdx.x; e < tot; e += 256) {
+    const int a = (int)(e / ((int64_t)D * cr));
+    const int t = (int)((e / cr) % D);
+    const int t1 = t / d, t2 = t % d;
+    const double w = lm[a] * lm[a];
+    const double m2 = pr[e] * pr[e] + pi[e] * pi[e];
+    n1 += w * t1 * m2;
+    n2 += w * t2 * m2;
+    if (t2 >= 1 && t1 + 1 < d) {
+      // <s| b+_1 b_2 |t>, s = (t1 + 1, t2 - 1) = t + d - 1
+      const int64_t os = e + (int64_t)(d - 1) * cr;
+      const double amp = w * sqrt((double)(t1 + 1)) * sqrt((double)t2);
+      cre += amp * (pr[os] * pr[e] + pi[os] * pi[e]);
+      cim += amp * (pr[os] * pi[e] - pi[os] * pr[e]);
+    }
+  }
+  const double s1 = block_sum(n1, sh);
+  const double s2 = block_sum(n2, sh);
+  const double s3 = block_sum(cre, sh);
+  const double s4 = block_sum(cim, sh);
+  if (threadIdx.x == 0) {
+    out[4 * K] = s1;
+    out[4 * K + 1] = s2;
+    out[4 * K + 2] = s3;
+    out[4 * K + 3] = s4;
   }
 }
 
@@ -467,18 +522,24 @@ void site_densities(const double* const* br, const double* const* bi, const doub
   PTEBD_LAUNCH_CHECK();
 }
 
-void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s) {
-  const int K = cl * d - 1;
+void op_kscale(const double* lam, int cl, int D, int d, int shift, int mode, double* ks, hipStream_t s) {
+  const int K = cl * D - shift;
   if (K <= 0) return;
-  hop_kscale_kernel<<<ceil_div(K, 256), 256, 0, s>>>(lam, cl, d, ks);
+  op_kscale_kernel<<<ceil_div(K, 256), 256, 0, s>>>(lam, cl, D, d, shift, mode, ks);
   PTEBD_LAUNCH_CHECK();
 }
 
-void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d, int cr,
-               double* out, double* part, hipStream_t s) {
-  close_hop_part_kernel<<<kHopBlocks, 256, 0, s>>>(br, bi, fr, fi, chi, d, cr, part);
+void close_op(const double* br, const double* bi, const double* fr, const double* fi, int chi, int D, int cr, int d,
+              int shift, int mode, double* out, double* part, hipStream_t s) {
+  close_hop_part_kernel<<<kHopBlocks, 256, 0, s>>>(br, bi, fr, fi, chi, D, cr, d, shift, mode, part);
   PTEBD_LAUNCH_CHECK();
   close_hop_sum_kernel<<<1, 256, 0, s>>>(part, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void supersite_local(const double* const* br, const double* const* bi, const double* const* lam, const int* chil,
+                     const int* chir, int Ls, int d, double* out, hipStream_t s) {
+  supersite_local_kernel<<<Ls, 256, 0, s>>>(br, bi, lam, chil, chir, d, out);
   PTEBD_LAUNCH_CHECK();
 }
 

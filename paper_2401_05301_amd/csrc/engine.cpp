@@ -81,8 +81,10 @@ size_t Sizes::bytes(int workers) const {
   return (size_t)d * sizeof(double);
 }
 
-int auto_workers(int L, int requested) {
-  const int per_layer = std::max(1, (L - 2 + 2) / 3);
+int gates_per_layer(int L, bool super) { return super ? L / 2 : (L - 2 + 2) / 3; }
+
+int auto_workers(int L, int requested, bool super) {
+  const int per_layer = std::max(1, gates_per_layer(L, super));
   const int w = requested > 0 ? requested : 4;
   return std::max(1, std::min(w, per_layer));
 }
@@ -135,6 +137,41 @@ Sizes plan_sizes(int L, int d, int chi_max) {
   return s;
 }
 
+Sizes plan_sizes2(int Ls, int D, int chi_max) {
+  Sizes s;
+  s.cap.resize(Ls + 1);
+  for (int b = 0; b <= Ls; ++b) s.cap[b] = (int)ipow_cap(D, std::min(b, Ls - b), chi_max);
+  const auto& c = s.cap;
+  for (int i = 0; i < Ls; ++i) s.site_elems += (int64_t)c[i] * D * c[i + 1];
+  for (int b = 0; b <= Ls; ++b) s.lam_elems += c[b];
+  int64_t maxr = 1;
+  s.T1 = 1;
+  s.X2 = 1;
+  s.V1h = 1;
+  for (int K = 0; K + 1 < Ls; ++K) {
+    const int64_t cl = c[K], cr = c[K + 2];
+    const int64_t m = cl * D, n = (int64_t)D * cr, r = std::min(m, n);
+    s.psi = std::max(s.psi, cl * D * D * cr);
+    s.G = std::max(s.G, r * r);
+    s.vec = std::max(s.vec, std::max(m, n));
+    maxr = std::max(maxr, r);
+    const int64_t p = subspace_width((int)r, chi_max);
+    if (p > 0) {
+      s.sub_p = std::max(s.sub_p, p);
+      s.sub_r = std::max(s.sub_r, r);
+    }
+  }
+  s.W = s.G;
+  const int chi = *std::max_element(c.begin(), c.end());
+  s.meas_sq = (int64_t)chi * chi;
+  s.meas_rect = (int64_t)chi * D * chi;
+  s.vec = std::max<int64_t>(s.vec, (int64_t)chi * D);
+  const int64_t nb = (maxr + 15) / 16 + 2;
+  s.part = (nb / 2 + 1) * kNsplitMax * 1536;
+  s.gates = (int64_t)std::max(Ls - 1, 0) * 2 * 2 * (int64_t)D * D * D * D;
+  return s;
+}
+
 namespace {
 
 // Gate workspace of one worker W (sizes from plan_sizes).
@@ -182,7 +219,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
 }  // namespace
 
 void mps_allocate(tebd_mps* M) {
-  Sizes s = plan_sizes(M->L, M->d, M->chi_max);
+  Sizes s = M->super ? plan_sizes2(M->L, M->d, M->chi_max) : plan_sizes(M->L, M->d, M->chi_max);
   M->cap = s.cap;
   M->chi.assign(M->L + 1, 1);
   const int L = M->L, d = M->d;
@@ -202,7 +239,7 @@ void mps_allocate(tebd_mps* M) {
   M->F = zalloc(M, s.meas_rect);
   M->F3 = zalloc(M, s.meas_rect);
   M->ks = dalloc(M, s.vec);
-  M->meas = dalloc(M, 5 * (int64_t)L);
+  M->meas = dalloc(M, 8 * (int64_t)std::max(L, M->phys_L) + 8);
   M->hop_part = dalloc(M, 512);
   M->d_br = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
   M->d_bi = static_cast<double**>(dev_alloc(M, sizeof(double*) * L));
@@ -212,7 +249,7 @@ void mps_allocate(tebd_mps* M) {
   PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemsetAsync(M->ledger, 0, sizeof(double), M->stream));
-  const int nw = auto_workers(L, M->opts.workers);
+  const int nw = auto_workers(L, M->opts.workers, M->super);
   for (int w = 0; w < nw; ++w) {
     tebd_mps* W = new tebd_mps();
     M->workers.push_back(W);
@@ -258,6 +295,23 @@ void mps_release(tebd_mps* M) {
 }
 
 void upload_product(tebd_mps* M, const int* occ) {
+  if (M->super) {
+    // super site K holds physical sites 2K, 2K+1 as the index s_{2K} d + s_{2K+1}
+    std::vector<int> so(M->L);
+    for (int K = 0; K < M->L; ++K) so[K] = occ[2 * K] * M->pd + occ[2 * K + 1];
+    const int L = M->L, d = M->d;
+    std::vector<double> zr(d), zi(d, 0.0);
+    for (int i = 0; i < L; ++i) {
+      std::fill(zr.begin(), zr.end(), 0.0);
+      zr[so[i]] = 1.0;
+      PTEBD_HIP(hipMemcpy(M->Br[i], zr.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+      PTEBD_HIP(hipMemcpy(M->Bi[i], zi.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+    }
+    const double one = 1.0;
+    for (int b = 0; b <= L; ++b) PTEBD_HIP(hipMemcpy(M->lam[b], &one, sizeof(double), hipMemcpyHostToDevice));
+    M->chi.assign(L + 1, 1);
+    return;
+  }
   const int L = M->L, d = M->d;
   std::vector<double> zr(d), zi(d, 0.0);
   for (int i = 0; i < L; ++i) {
@@ -291,7 +345,10 @@ void upload_state(tebd_mps* M, const int* chi, const double* B, const double* la
 void set_model(tebd_mps* M, const ModelP& m) {
   M->model = m;
   M->spectra.clear();
-  for (int j = 0; j + 2 < M->L; ++j) M->spectra.push_back(eig_three_site(m, j));
+  if (M->super)
+    for (int K = 0; K + 1 < M->L; ++K) M->spectra.push_back(eig_supersite(m, K));
+  else
+    for (int j = 0; j + 2 < M->L; ++j) M->spectra.push_back(eig_three_site(m, j));
   // device gates are rebuilt lazily; keep their memory for reuse
   for (auto& kv : M->gates) {
     (void)kv;
@@ -913,6 +970,61 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   S->chi[j + 2] = k2;
 }
 
+// Two-site gate on super sites (K, K+1) (Sec. II B, d_eff = D = d^2):
+//   psi  = B_K B_{K+1}                     (chi_l D) x (D chi_r)        GEMM
+//   psi' = G psi (batched over chi_l)      D^2 x chi_r per left index   GEMM
+//   SVD of Lambda_K psi' as (chi_l D) x (D chi_r), truncate -> k
+//   B_K = psi' V / |S|,  B_{K+1} = V^+,  Lambda_{K+1} = S / |S|.
+void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G) {
+  hipStream_t s = W->stream;
+  const int D = W->d, D2 = D * D;
+  const int cl = S->chi[K], cm = S->chi[K + 1], cr = S->chi[K + 2];
+  const int prec = W->opts.prec;
+  {  // psi = B_K B_{K+1}
+    ZGemmArgs g;
+    g.m = cl * D; g.n = D * cr; g.k = cm;
+    g.ar = S->Br[K]; g.ai = S->Bi[K]; g.lda = cm;
+    g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = (int64_t)D * cr;
+    g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)D * cr;
+    zgemm(g, prec, s);
+  }
+  {  // psi'[a] = G psi[a]
+    ZGemmArgs g;
+    g.m = D2; g.n = cr; g.k = D2; g.batch = cl;
+    g.ar = G.first; g.ai = G.second; g.lda = D2; g.sA = 0;
+    g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)D2 * cr;
+    g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)D2 * cr;
+    zgemm(g, prec, s);
+  }
+  const int m1 = cl * D, n1 = D * cr;
+  SvdIn in{W->psip.re, W->psip.im, n1, m1, n1, S->lam[K], D};
+  // before the gate the left singular space across bond K+1 is spanned by
+  // the columns of Lambda_K B_K
+  in.warm.kind = 1;
+  in.warm.sr = S->Br[K]; in.warm.si = S->Bi[K]; in.warm.ld = cm;
+  in.warm.src_rows = m1; in.warm.src_cols = cm;
+  in.warm.rs = S->lam[K]; in.warm.rdiv = D;
+  // V^+ goes straight to B_{K+1}: psi' no longer needs the old B_{K+1}
+  const int k = svd_trunc(W, in, S->lam[K + 1], S->Br[K + 1], S->Bi[K + 1], 0, W->psi);
+  {  // B_K = psi' V / |S|
+    ZGemmArgs g;
+    g.m = m1; g.n = k; g.k = n1;
+    g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
+    g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = n1; g.transB = 1;
+    g.cr = S->Br[K]; g.ci = S->Bi[K]; g.ldc = k;
+    g.alpha_dev = W->info_d + 0; g.alpha_recip = 1;
+    zgemm(g, 0, s);
+  }
+  S->chi[K + 1] = k;
+}
+
+void update_gate(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {
+  if (S->super)
+    gate_update2(S, W, j, G);
+  else
+    gate_update(S, W, j, G);
+}
+
 }  // namespace
 
 namespace {
@@ -929,7 +1041,7 @@ void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::p
     tebd_mps* W = M->workers[0];
     for (size_t x = 0; x < js.size(); ++x) {
       W->ledger = M->wslots + js[x];
-      gate_update(M, W, js[x], G[x]);
+      update_gate(M, W, js[x], G[x]);
     }
   } else {
     // workers start after everything enqueued so far on the handle's stream
@@ -945,7 +1057,7 @@ void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::p
         tebd_mps* W = M->workers[w];
         for (size_t x = w; x < js.size(); x += nw) {
           W->ledger = M->wslots + js[x];
-          gate_update(M, W, js[x], G[x]);
+          update_gate(M, W, js[x], G[x]);
         }
       } catch (...) {
         err[w] = std::current_exception();
@@ -977,10 +1089,21 @@ void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::p
 
 }  // namespace
 
+// Left sites of the gates of one commuting group: j = group mod 3 for the
+// three-site chain, K = group mod 2 for the super-site chain.
+std::vector<int> group_gates(const tebd_mps* M, int group) {
+  std::vector<int> js;
+  if (M->super)
+    for (int K = group; K + 1 < M->L; K += 2) js.push_back(K);
+  else
+    for (int j = group; j + 2 < M->L; j += 3) js.push_back(j);
+  return js;
+}
+
 void layer(tebd_mps* M, int group, double tau) {
   std::vector<int> js;
   std::vector<std::pair<double*, double*>> G;
-  for (int j = group; j + 2 < M->L; j += 3) {
+  for (int j : group_gates(M, group)) {
     js.push_back(j);
     G.push_back(device_gate(M, j, tau));
   }
@@ -997,7 +1120,7 @@ void canonicalize(tebd_mps* M) {
   // decomposition across its two inner bonds given the left Lambda
   std::vector<int> js;
   std::vector<std::pair<double*, double*>> G;
-  for (int j = 0; j + 2 < M->L; ++j) {
+  for (int j = 0; j + (M->super ? 1 : 2) < M->L; ++j) {
     js.push_back(j);
     G.push_back(device_gate(M, j, 0.0));
   }
@@ -1019,10 +1142,91 @@ void sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
 }
 
 void prepare_gates(tebd_mps* M, int group, double tau) {
-  for (int j = group; j + 2 < M->L; j += 3) (void)device_gate(M, j, tau);
+  for (int j : group_gates(M, group)) (void)device_gate(M, j, tau);
 }
 
+namespace {
+
+// Physical n, <b+_i b_{i+1}> and <b+_i b_{i+2}> of a super-site chain: the
+// densities and the correlator inside a super site are local to it; the
+// correlators across super sites K, K+1 close an environment carrying the
+// creation operator on K with the annihilation operator on K+1.
+void measure_super(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
+  hipStream_t s = M->stream;
+  const int Ls = M->L, D = M->d, d = M->pd, L = M->phys_L;
+  PTEBD_HIP(hipMemcpyAsync(M->d_chi, M->chi.data(), sizeof(int) * (Ls + 1), hipMemcpyHostToDevice, s));
+  double* loc = M->meas;               // 4 per super site
+  double* c_odd = M->meas + 4 * Ls;    // <b+_{2K+1} b_{2K+2}>
+  double* d_even = M->meas + 6 * Ls;   // <b+_{2K} b_{2K+2}>
+  double* d_odd = M->meas + 8 * Ls;    // <b+_{2K+1} b_{2K+3}>
+  supersite_local(M->d_br, M->d_bi, M->d_lam, M->d_chi, M->d_chi + 1, Ls, d, loc, s);
+  const bool want = cnn || cnnn;
+  for (int K = 0; want && K + 1 < Ls; ++K) {
+    const int cl = M->chi[K], cr = M->chi[K + 1], cr2 = M->chi[K + 2];
+    // creation operator on the second (mode 2) then on the first (mode 1) site of K
+    for (int mode1 = 2; mode1 >= 1; --mode1) {
+      const int shift1 = mode1 == 1 ? d : 1;
+      op_kscale(M->lam[K], cl, D, d, shift1, mode1, M->ks, s);
+      {  // E = sum Lambda^2 sqrt(level) B(a, s, .)^+ B(a, s - shift, .)
+        ZGemmArgs g;
+        g.m = cr; g.n = cr; g.k = cl * D - shift1;
+        g.ar = M->Br[K] + (int64_t)shift1 * cr; g.ai = M->Bi[K] + (int64_t)shift1 * cr; g.lda = cr; g.transA = 1;
+        g.br = M->Br[K]; g.bi = M->Bi[K]; g.ldb = cr;
+        g.cr = M->E.re; g.ci = M->E.im; g.ldc = cr;
+        g.k_scale = M->ks;
+        zgemm(g, 0, s);
+      }
+      {  // F = E B_{K+1}
+        ZGemmArgs g;
+        g.m = cr; g.n = D * cr2; g.k = cr;
+        g.ar = M->E.re; g.ai = M->E.im; g.lda = cr;
+        g.br = M->Br[K + 1]; g.bi = M->Bi[K + 1]; g.ldb = (int64_t)D * cr2;
+        g.cr = M->F.re; g.ci = M->F.im; g.ldc = (int64_t)D * cr2;
+        zgemm(g, 0, s);
+      }
+      if (mode1 == 2) {
+        // b+_{2K+1} b_{2K+2} (first site of K+1) and b+_{2K+1} b_{2K+3} (second site)
+        close_op(M->Br[K + 1], M->Bi[K + 1], M->F.re, M->F.im, cr, D, cr2, d, d, 1, c_odd + 2 * K, M->hop_part, s);
+        close_op(M->Br[K + 1], M->Bi[K + 1], M->F.re, M->F.im, cr, D, cr2, d, 1, 2, d_odd + 2 * K, M->hop_part, s);
+      } else {
+        // b+_{2K} b_{2K+2}
+        close_op(M->Br[K + 1], M->Bi[K + 1], M->F.re, M->F.im, cr, D, cr2, d, d, 1, d_even + 2 * K, M->hop_part, s);
+      }
+    }
+  }
+  std::vector<double> h(10 * (size_t)Ls);
+  PTEBD_HIP(hipMemcpyAsync(h.data(), M->meas, sizeof(double) * 10 * Ls, hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  for (int K = 0; K < Ls; ++K) {
+    if (n_out) {
+      n_out[2 * K] = h[4 * K];
+      n_out[2 * K + 1] = h[4 * K + 1];
+    }
+    if (cnn) {
+      cnn[2 * (2 * K)] = h[4 * K + 2];
+      cnn[2 * (2 * K) + 1] = h[4 * K + 3];
+      if (K + 1 < Ls) {
+        cnn[2 * (2 * K + 1)] = h[4 * Ls + 2 * K];
+        cnn[2 * (2 * K + 1) + 1] = h[4 * Ls + 2 * K + 1];
+      }
+    }
+    if (cnnn && K + 1 < Ls) {
+      cnnn[2 * (2 * K)] = h[6 * Ls + 2 * K];
+      cnnn[2 * (2 * K) + 1] = h[6 * Ls + 2 * K + 1];
+      cnnn[2 * (2 * K + 1)] = h[8 * Ls + 2 * K];
+      cnnn[2 * (2 * K + 1) + 1] = h[8 * Ls + 2 * K + 1];
+    }
+  }
+  (void)L;
+}
+
+}  // namespace
+
 void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
+  if (M->super) {
+    measure_super(M, n_out, cnn, cnnn);
+    return;
+  }
   hipStream_t s = M->stream;
   const int L = M->L, d = M->d;
   PTEBD_HIP(hipMemcpyAsync(M->d_chi, M->chi.data(), sizeof(int) * (L + 1), hipMemcpyHostToDevice, s));
@@ -1033,7 +1237,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
   const bool want_hops = cnn || cnnn;
   for (int i = 0; want_hops && i + 1 < L; ++i) {
     const int cl = M->chi[i], cr = M->chi[i + 1], cr2 = M->chi[i + 2];
-    hop_kscale(M->lam[i], cl, d, M->ks, s);
+    op_kscale(M->lam[i], cl, d, d, 1, 0, M->ks, s);
     {  // E = sum Lambda^2 sqrt(s) B(a,s,.)^+ B(a,s-1,.)
       ZGemmArgs g;
       g.m = cr; g.n = cr; g.k = cl * d - 1;
@@ -1051,7 +1255,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
       g.cr = M->F.re; g.ci = M->F.im; g.ldc = (int64_t)d * cr2;
       zgemm(g, 0, s);
     }
-    close_hop(M->Br[i + 1], M->Bi[i + 1], M->F.re, M->F.im, cr, d, cr2, dc + 2 * i, M->hop_part, s);
+    close_op(M->Br[i + 1], M->Bi[i + 1], M->F.re, M->F.im, cr, d, cr2, d, 1, 0, dc + 2 * i, M->hop_part, s);
     if (i + 2 < L) {
       const int cr3 = M->chi[i + 3];
       {  // F2 = B_{i+1}^+ F   (rows (y, s) contracted)
@@ -1070,7 +1274,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
         g.cr = M->F3.re; g.ci = M->F3.im; g.ldc = (int64_t)d * cr3;
         zgemm(g, 0, s);
       }
-      close_hop(M->Br[i + 2], M->Bi[i + 2], M->F3.re, M->F3.im, cr2, d, cr3, dd + 2 * i, M->hop_part, s);
+      close_op(M->Br[i + 2], M->Bi[i + 2], M->F3.re, M->F3.im, cr2, d, cr3, d, 1, 0, dd + 2 * i, M->hop_part, s);
     }
   }
   std::vector<double> h(5 * (size_t)L);

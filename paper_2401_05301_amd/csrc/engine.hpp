@@ -16,7 +16,9 @@ struct tebd_mps {
   tebd_opts opts{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  int L = 0, d = 0, chi_max = 0;
+  int L = 0, d = 0, chi_max = 0;    // sites and local dimension of the chain the MPS lives on
+  bool super = false;               // super-site chain: L = phys_L / 2 sites of dimension d = pd^2
+  int phys_L = 0, pd = 0;           // physical sites and their local dimension
   std::vector<int> cap;   // bond capacity, b = 0..L
   std::vector<int> chi;   // current bond dimension, b = 0..L (host mirror)
 
@@ -90,10 +92,13 @@ struct Sizes {
 };
 
 // Number of gate workers of a handle: opts.workers if positive, else 4,
-// at most the number of gates in a layer.
-int auto_workers(int L, int requested);
+// at most the number of gates in a layer (L sites of the chain the MPS lives
+// on; two-site gates on a super-site chain).
+int auto_workers(int L, int requested, bool super = false);
 
 Sizes plan_sizes(int L, int d, int chi_max);
+// Sizes of a super-site chain of Ls sites of dimension D (two-site gates).
+Sizes plan_sizes2(int Ls, int D, int chi_max);
 // Width of the subspace used for the top-k eigenpairs of an r x r Gram
 // matrix when keeping at most chi_max values (0: solve the whole matrix).
 int subspace_width(int r, int chi_max);

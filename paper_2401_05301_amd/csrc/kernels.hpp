@@ -144,11 +144,18 @@ void square_expand(const double* x, int div, int n, double* y, hipStream_t s);
 // Measurement helpers.
 void site_densities(const double* const* br, const double* const* bi, const double* const* lam,
                     const int* chil, const int* chir, int L, int d, double* n_out, hipStream_t s);
-void hop_kscale(const double* lam, int cl, int d, double* ks, hipStream_t s);
-// out[0] += sum_{y, t>=1, c} sqrt(t) conj(B(y, t-1, c)) F(y, t, c) (complex; out[0]=re, out[1]=im)
-// part: 512 doubles of scratch.
-void close_hop(const double* br, const double* bi, const double* fr, const double* fi, int chi, int d,
-               int cr, double* out, double* part, hipStream_t s);
+// Correlators <O1 O2> across neighbouring sites, with O1 a creation and O2
+// an annihilation operator acting on the whole site (mode 0, D = d) or on the
+// first / second physical site of a super site (modes 1 / 2, D = d^2); shift
+// is the change of the local index (1, d or 1).
+// ks[r'] = Lambda[a]^2 sqrt(level) weights of the environment GEMM.
+void op_kscale(const double* lam, int cl, int D, int d, int shift, int mode, double* ks, hipStream_t s);
+// out[0..1] = sum_{y,t,c} sqrt(level(t)) conj(B(y, t - shift, c)) F(y, t, c); part: 512 doubles of scratch.
+void close_op(const double* br, const double* bi, const double* fr, const double* fi, int chi, int D, int cr, int d,
+              int shift, int mode, double* out, double* part, hipStream_t s);
+// Per super site: (n_first, n_second, Re, Im <b+_first b_second>) into out[4 K ..].
+void supersite_local(const double* const* br, const double* const* bi, const double* const* lam, const int* chil,
+                     const int* chir, int Ls, int d, double* out, hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
 // *acc += sum_{i<n} slots[i], summed in index order by one thread.
 void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s);

@@ -212,3 +212,33 @@ def test_centred_cdw_quasi_local(pt, L, N, d, chi, steps):
         assert abs(q[key] - qo[key]) <= 10 * tol, key
     assert abs(q["C_even"] - qo["C_even"]) <= 10 * tol
     g.close()
+
+
+@pytest.mark.parametrize("L,d,chi,steps,svd", [(8, 3, 81, 10, 0), (12, 3, 16, 8, 0), (16, 5, 24, 4, 0), (16, 5, 24, 4, 1)])
+def test_supersite_two_site_variant(pt, L, d, chi, steps, svd):
+    """The paper's super-site chain (Sec. II B, d_eff = d^2, two-site gates)
+    against the super-site oracle, same inputs and truncation."""
+    from oracle import supersite as oss
+    from workloads import cdw_occupations
+    m = Model(L=L, d=d, U=3.0, J=1.0, Jnnn=0.1, K=0.01)
+    tr = Trunc(chi_max=chi, w_max=0.0 if chi == 81 else 1e-12, eps=1e-14 if chi == 81 else 1e-12)
+    dt = 0.02
+    occ = cdw_occupations(L, 1)
+    note(f"super-site L={L} d={d} chi={chi} steps={steps} svd={svd}")
+    ores = oss.run2(m, tr, dt, steps, occ)
+    g = pt.MPS.product(gpu_model(pt, m), pt.make_opts(chi, tr.w_max, tr.eps, svd=svd, supersite=True), occ)
+    assert len(g.bond_dims()) == L // 2 + 1
+    for _ in range(steps):
+        g.step(dt)
+    n, C, D = g.measure()
+    # the Gram route drops values below 1e-6 s_0 (see test_gram_variant)
+    tol = bar(ores) if svd == 0 else 2e-8
+    assert np.abs(n - ores["n"][-1]).max() <= tol, np.abs(n - ores["n"][-1]).max()
+    assert np.abs(C - ores["C"][-1]).max() <= tol, np.abs(C - ores["C"][-1]).max()
+    assert np.abs(D - ores["D"][-1]).max() <= tol, np.abs(D - ores["D"][-1]).max()
+    if svd == 0:
+        assert g.bond_dims() == ores["mps"].bond_dims()
+        for b in range(1, L // 2):
+            assert np.abs(g.lam(b) - ores["mps"].lam[b]).max() <= tol, b
+        assert abs(g.discarded_weight() - ores["w_total"][-1]) <= 1e-12 + 1e-6 * ores["w_total"][-1]
+    g.close()
