@@ -138,6 +138,120 @@ def random_mps(L: int, d: int, chi: int, seed: int = 0, tau: float = 30.0,
     return B, lam
 
 
+def u1_bond_sectors(L: int, d: int, chi: int, N: int, sigma: float = 2.0) -> List[dict]:
+    """Particle-number sectors of a random U(1) MPS: for every bond b a dict
+    {q: multiplicity}, q the number of bosons left of the bond.
+
+    Bond 0 holds {0: 1} and bond L {N: 1}.  Inner bonds spread
+    min(d^b, d^(L-b), chi) indices over the particle numbers q reachable from
+    both sides, with weights exp(-(q - N b / L)^2 / (2 sigma^2)), at most as
+    many indices per q as there are Fock states of the b sites on the left
+    with q bosons and of the L - b sites on the right with N - q, and as the
+    bond to the right offers (sum over s of its multiplicity of q + s), so
+    that the blocks of a right-orthonormal tensor can have orthonormal rows.
+    A last left-to-right pass drops particle numbers the left bond cannot
+    reach, so every index is reached from the left.
+    """
+    targets = bulk_bond_dims(L, d, chi)
+
+    def fock_counts(n_sites):
+        c = {0: 1}
+        for _ in range(n_sites):
+            nxt = {}
+            for q, v in c.items():
+                for s in range(d):
+                    nxt[q + s] = min(chi, nxt.get(q + s, 0) + v)
+            c = nxt
+        return c
+
+    left = [fock_counts(b) for b in range(L + 1)]
+    right = [fock_counts(L - b) for b in range(L + 1)]
+    mult: List[dict] = [dict() for _ in range(L + 1)]
+    mult[L] = {N: 1}
+    mult[0] = {0: 1}
+    for b in range(L - 1, 0, -1):
+        caps = {}
+        for q, lv in left[b].items():
+            rv = right[b].get(N - q, 0)
+            offer = sum(mult[b + 1].get(q + s, 0) for s in range(d))
+            c = min(lv, rv, offer)
+            if c > 0:
+                caps[q] = c
+        qbar = N * b / L
+        w = {q: np.exp(-(q - qbar) ** 2 / (2.0 * sigma * sigma)) for q in caps}
+        wsum = sum(w.values())
+        T = min(targets[b], sum(caps.values()))
+        ideal = {q: T * w[q] / wsum for q in caps}
+        alloc = {q: min(caps[q], int(round(ideal[q]))) for q in caps}
+        while sum(alloc.values()) < T:
+            q = max((q for q in caps if alloc[q] < caps[q]), key=lambda q: (ideal[q] - alloc[q], -abs(q - qbar)))
+            alloc[q] += 1
+        while sum(alloc.values()) > T:
+            q = max((q for q in caps if alloc[q] > 0), key=lambda q: (alloc[q] - ideal[q], abs(q - qbar)))
+            alloc[q] -= 1
+        mult[b] = {q: v for q, v in sorted(alloc.items()) if v > 0}
+    for b in range(1, L):
+        mult[b] = {q: v for q, v in mult[b].items()
+                   if any(mult[b - 1].get(q - s, 0) > 0 for s in range(d))}
+    return mult
+
+
+def random_mps_u1(L: int, d: int, chi: int, N: int, seed: int = 0, tau: float = 30.0,
+                  sigma: float = 2.0, bias: float | None = None):
+    """Random right-orthonormal MPS with a definite number N of bosons.
+
+    Every bond index carries a particle number q (bosons left of the bond),
+    sectors from ``u1_bond_sectors``, indices ordered by q.  B_i[a, s, b] is
+    zero unless q_{i+1}[b] = q_i[a] + s; each block of rows with one q_i is
+    the conjugate transpose of the Q factor of a complex Gaussian (columns
+    for right index rank r inside its sector weighted by exp(-r / bias) when
+    ``bias`` is given).  Lambda_b is imposed, not derived: index t of sector q
+    gets exp(-(q - N b / L)^2 / (4 sigma^2) - t / tau), normalised.
+
+    Returns (B, lam, charges) with charges[b] the particle numbers of bond b.
+    """
+    rng = np.random.default_rng(seed)
+    mult = u1_bond_sectors(L, d, chi, N, sigma)
+    charges = []
+    for b in range(L + 1):
+        q = []
+        for k, v in sorted(mult[b].items()):
+            q += [k] * v
+        charges.append(np.array(q, dtype=np.int64))
+    B = []
+    for i in range(L):
+        ql, qr = charges[i], charges[i + 1]
+        cl, cr = len(ql), len(qr)
+        T = np.zeros((cl, d, cr), dtype=np.complex128)
+        rank_r = np.zeros(cr, dtype=np.int64)
+        for k in np.unique(qr):
+            idx = np.nonzero(qr == k)[0]
+            rank_r[idx] = np.arange(len(idx))
+        for k in np.unique(ql):
+            rows = np.nonzero(ql == k)[0]
+            cols = [(s, b) for s in range(d) for b in np.nonzero(qr == k + s)[0]]
+            if len(cols) < len(rows):
+                raise ValueError("sector too small for orthonormal rows")
+            g = rng.standard_normal((len(cols), len(rows))) + 1j * rng.standard_normal((len(cols), len(rows)))
+            if bias is not None:
+                g *= np.array([np.exp(-rank_r[b] / bias) for _, b in cols])[:, None]
+            qf, _ = np.linalg.qr(g)
+            blk = qf.conj().T
+            for t, (s, b) in enumerate(cols):
+                T[rows, s, b] = blk[:, t]
+        B.append(T)
+    lam = []
+    for b in range(L + 1):
+        q = charges[b]
+        t = np.zeros(len(q))
+        for k in np.unique(q):
+            idx = np.nonzero(q == k)[0]
+            t[idx] = np.arange(len(idx))
+        v = np.exp(-(q - N * b / L) ** 2 / (4.0 * sigma * sigma) - t / tau)
+        lam.append(v / np.sqrt(np.sum(v * v)))
+    return B, lam, charges
+
+
 def serving_requests(n: int = 64, seed: int = 5, rate: float = 1.0, small: bool = False):
     """Poisson stream of quench requests (arrival times in seconds).
 
