@@ -128,6 +128,10 @@ def main():
     ap.add_argument("--serve", type=int, default=16, help="requests in the serving sample (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference for the HBM counters) and exit")
+    ap.add_argument("--u1", action="store_true",
+                    help="U(1) block-sparse SVDs on a random state of L/2 bosons with definite numbers per bond index")
+    ap.add_argument("--sigma", type=float, default=2.0,
+                    help="--u1: width of the particle-number distribution over each bond's indices")
     ap.add_argument("--serve-scale", type=float, default=0.1,
                     help="fraction of each request's horizon served in the sample")
     args = ap.parse_args()
@@ -153,7 +157,7 @@ def main():
     import torch
 
     import paper_2401_05301_amd as pt
-    from workloads import CONFIGS, random_mps
+    from workloads import CONFIGS, random_mps, random_mps_u1
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
@@ -165,10 +169,14 @@ def main():
     svd = {"gram": pt.SVD_GRAM_EIG, "jacobi": pt.SVD_JACOBI}[args.svd]
 
     t0 = time.perf_counter()
-    B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
-    log(f"synthetic input L={L} d={d} chi={chi} generated in {time.perf_counter() - t0:.1f} s")
+    if args.u1:
+        B, lam, _ = random_mps_u1(L, d, chi, L // 2, seed=args.seed, tau=args.tau, sigma=args.sigma, bias=args.bias)
+    else:
+        B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
+    log(f"synthetic input L={L} d={d} chi={chi} u1={args.u1} generated in {time.perf_counter() - t0:.1f} s")
     model = pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre())
-    opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream, workers=args.workers)
+    opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream, workers=args.workers,
+                        u1=args.u1)
     keep = pt.torch_allocator(opts, stream=stream)
     g = pt.MPS.from_tensors(model, opts, B, lam)
     g._keep = keep
@@ -217,7 +225,7 @@ def main():
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
             "launches": gemm_n, "avg_launch_ms": gemm_ms / max(gemm_n, 1),
             "flops_per_launch": gemm_fl / max(gemm_n, 1)}
-    if prec == pt.FP64 and L == 64 and chi == 1024 and args.svd == "gram":
+    if prec == pt.FP64 and L == 64 and chi == 1024 and args.svd == "gram" and not args.u1:
         roof["traffic"] = measured_traffic()
     out = {
         "metric": METRIC,
@@ -232,10 +240,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == pt.FP64 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "bulk_L64_chi1024", "L": L, "d": d, "chi_max": chi, "U": mdl.U, "J": mdl.J,
+        "config": {"workload": "bulk_L64_chi1024" + ("_u1" if args.u1 else ""), "L": L, "d": d, "chi_max": chi, "U": mdl.U, "J": mdl.J,
                    "Jnnn": mdl.Jnnn, "K": mdl.K, "dt": dt, "svd": args.svd, "theta_gate_prec": args.prec,
                    "gate_updates_per_step": nsteps_gu, "w_max": 1e-12, "eps": 1e-12,
-                   "input": (f"random right-orthonormal MPS (seed {args.seed}, right-index weight exp(-b/{args.bias:g})), "
+                   "u1": bool(args.u1),
+                   "input": (f"random right-orthonormal MPS (seed {args.seed}, right-index weight exp(-b/{args.bias:g})"
+                             + (f", {L // 2} bosons, sector width sigma {args.sigma:g}" if args.u1 else "") + "), "
                              + ("canonicalised by an identity sweep" if not args.no_canonicalize else "as generated"))},
         "roofline": roof,
         "path_roofline": {"unit_flops": F_GU, "achieved_TFLOPs": F_GU * value / 1e12, "peak": PEAK_FP64,

@@ -101,6 +101,15 @@ typedef struct {
                              (L sites); mps_bond_dims, mps_lambda and mps_site see the L/2 super
                              sites (L/2 + 1 bonds); tebd_layer takes group 0 or 1;
                              mps_init_state is three-site only.  0: three-site gates (default). */
+  int32_t u1;             /* 1: U(1) block-sparse SVDs (Sec. II B keeps the tensors in particle-number
+                             sectors).  Every bond index carries the number of bosons on its left;
+                             each gate's SVD is done per sector and the truncation rule runs over
+                             the union of the sector spectra, so the result is the dense one.  Bond
+                             indices are kept ordered by that number, then by decreasing Schmidt
+                             value (mps_lambda and mps_site return this order; mps_bond_charges the
+                             numbers).  Product states qualify; mps_init_state infers the numbers
+                             from the non-zero entries and fails with TEBD_EINVAL when an index is
+                             reached by entries of two numbers or by none.  0: dense (default). */
 } tebd_opts;
 
 typedef struct tebd_mps tebd_mps;
@@ -163,8 +172,14 @@ tebd_status mps_set_model(tebd_mps* mps, const tebd_model* model);
 /* Current bond dimensions chi[L+1] (host copy; synchronises). */
 tebd_status mps_bond_dims(const tebd_mps* mps, int32_t* chi);
 
-/* Schmidt values of bond b into s[cap]; *len receives chi_b (synchronises). */
+/* Schmidt values of bond b into s[cap] in decreasing order (with opts.u1: grouped by
+ * particle number, decreasing within each group); *len receives chi_b (synchronises). */
 tebd_status mps_lambda(const tebd_mps* mps, int32_t bond, double* s, int32_t cap, int32_t* len);
+
+/* With opts.u1: number of bosons left of bond `bond` for each of its indices
+ * (same order as mps_lambda) into q[cap]; *len = the bond dimension.
+ * TEBD_ESTATE when the handle does not track particle numbers. */
+tebd_status mps_bond_charges(const tebd_mps* mps, int32_t bond, int32_t* q, int32_t cap, int32_t* len);
 
 /* Site tensor B_i (planar: chi_i*d*chi_{i+1} reals then imaginaries) into buf[cap]. */
 tebd_status mps_site(const tebd_mps* mps, int32_t site, double* buf, int64_t cap);

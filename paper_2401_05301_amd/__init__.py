@@ -26,6 +26,7 @@ EXPORTS = [
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
     "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve", "measure_quasi_local",
+    "mps_bond_charges",
 ]
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "herm_eig": 2, "herm_apply": 3, "jac_gram": 4, "jac_rotate": 5}
 
@@ -49,7 +50,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("chi_max", ctypes.c_int32), ("trunc_weight", ctypes.c_double), ("trunc_rel", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("svd", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32), ("supersite", ctypes.c_int32)]
+                ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32), ("supersite", ctypes.c_int32),
+                ("u1", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -87,6 +89,7 @@ def _load():
         "mps_set_model": (st, [H, P(Model)]),
         "mps_bond_dims": (st, [H, P(ctypes.c_int32)]),
         "mps_lambda": (st, [H, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32, P(ctypes.c_int32)]),
+        "mps_bond_charges": (st, [H, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int32)]),
         "mps_site": (st, [H, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int64]),
         "mps_discarded_weight": (st, [H, P(ctypes.c_double)]),
         "mps_sweep_stats": (st, [H, P(ctypes.c_int64), P(ctypes.c_int64)]),
@@ -128,7 +131,8 @@ def make_model(L: int, d: int, U: float, J: float = 1.0, Jnnn: float = 0.0, K: f
 
 
 def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int = FP64, svd: int = SVD_JACOBI,
-              max_sweeps: int = 40, stream: Optional[int] = None, workers: int = 0, supersite: bool = False) -> Opts:
+              max_sweeps: int = 40, stream: Optional[int] = None, workers: int = 0, supersite: bool = False,
+              u1: bool = False) -> Opts:
     o = Opts()
     _lib.tebd_opts_default(ctypes.byref(o))
     o.chi_max, o.trunc_weight, o.trunc_rel = chi_max, w_max, eps
@@ -136,6 +140,7 @@ def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int 
     o.stream = stream
     o.workers = workers
     o.supersite = int(bool(supersite))
+    o.u1 = int(bool(u1))
     return o
 
 
@@ -237,6 +242,13 @@ def mps_lambda(h, bond: int, cap: int = 16384):
     n = ctypes.c_int32()
     _check(_lib.mps_lambda(h, bond, _dptr(s), cap, ctypes.byref(n)))
     return s[:n.value].copy()
+
+
+def mps_bond_charges(h, bond: int, cap: int = 16384):
+    q = np.zeros(cap, dtype=np.int32)
+    n = ctypes.c_int32()
+    _check(_lib.mps_bond_charges(h, bond, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap, ctypes.byref(n)))
+    return q[:n.value].astype(np.int64)
 
 
 def mps_site(h, site: int, shape):
@@ -369,6 +381,9 @@ class MPS:
 
     def lam(self, bond: int):
         return mps_lambda(self.h, bond)
+
+    def charges(self, bond: int):
+        return mps_bond_charges(self.h, bond)
 
     def site(self, i: int):
         chi = self.bond_dims()

@@ -61,6 +61,7 @@ tebd_status check_opts(const tebd_opts* o, int d) {
   if (!o) return fail(TEBD_EINVAL, "opts is NULL");
   if (o->chi_max < 1) return fail(TEBD_EINVAL, "chi_max must be >= 1");
   if (o->supersite != 0 && o->supersite != 1) return fail(TEBD_EINVAL, "supersite must be 0 or 1");
+  if (o->u1 != 0 && o->u1 != 1) return fail(TEBD_EINVAL, "u1 must be 0 or 1");
   const int64_t dl = o->supersite ? (int64_t)d * d : d;   // local dimension of the chain the MPS lives on
   if ((int64_t)o->chi_max * dl > 8192) return fail(TEBD_EINVAL, "chi_max * (local dimension) must be <= 8192");
   if (!finite(o->trunc_weight) || o->trunc_weight < 0) return fail(TEBD_EINVAL, "trunc_weight must be >= 0");
@@ -92,6 +93,10 @@ tebd_status create(const tebd_model* model, const tebd_opts* opts, tebd_mps** ou
     M->super = opts->supersite != 0;
     M->L = M->super ? model->L / 2 : model->L;
     M->d = M->super ? model->d * model->d : model->d;
+    M->u1 = opts->u1 != 0;
+    // bosons of every local level: s, or s1 + s2 for the super-site index s1 d + s2
+    M->qs.resize(M->d);
+    for (int t = 0; t < M->d; ++t) M->qs[t] = M->super ? t / model->d + t % model->d : t;
     M->chi_max = opts->chi_max;
     if (opts->stream) {
       M->stream = (hipStream_t)opts->stream;
@@ -320,6 +325,17 @@ tebd_status mps_lambda(const tebd_mps* M, int32_t bond, double* s, int32_t cap, 
   });
 }
 
+tebd_status mps_bond_charges(const tebd_mps* M, int32_t bond, int32_t* q, int32_t cap, int32_t* len) {
+  if (!M || !q || !len) return fail(TEBD_EINVAL, "NULL argument");
+  if (!M->u1) return fail(TEBD_ESTATE, "particle numbers are tracked only with opts.u1 = 1");
+  if (bond < 0 || bond > M->L) return fail(TEBD_EINVAL, "bond out of range");
+  const int n = M->chi[bond];
+  *len = n;
+  if (cap < n) return fail(TEBD_EINVAL, "output capacity smaller than the bond dimension");
+  for (int a = 0; a < n; ++a) q[a] = M->q[bond][a];
+  return TEBD_OK;
+}
+
 tebd_status mps_site(const tebd_mps* M, int32_t site, double* buf, int64_t cap) {
   if (!M || !buf) return fail(TEBD_EINVAL, "NULL argument");
   if (site < 0 || site >= M->L) return fail(TEBD_EINVAL, "site out of range");
@@ -357,10 +373,11 @@ tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t
       return fail(TEBD_EINVAL, "a super-site chain needs an even number of physical sites, at least 4");
     const int Ls = model->L / 2;
     *bytes = ptebd::plan_sizes2(Ls, model->d * model->d, opts->chi_max)
-                 .bytes(ptebd::auto_workers(Ls, opts->workers, true));
+                 .bytes(ptebd::auto_workers(Ls, opts->workers, true), opts->u1 != 0);
     return TEBD_OK;
   }
-  *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max).bytes(ptebd::auto_workers(model->L, opts->workers));
+  *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max)
+               .bytes(ptebd::auto_workers(model->L, opts->workers), opts->u1 != 0);
   return TEBD_OK;
 }
 

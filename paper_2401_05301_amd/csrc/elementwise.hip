@@ -188,6 +188,42 @@ __global__ __launch_bounds__(256) void supersite_local_kernel(const double* cons
   }
 }
 
+// One particle-number sector of diag(rs) A: out(i, j) = rs[r_i / rdiv] A(r_i, c_j)
+// with r_i = rows[i], c_j = cols[j] (trans == 0, out m x n), or its conjugate
+// transpose (trans == 1, out n x m).  Consecutive threads write consecutive
+// output elements.
+__global__ void gather_block_kernel(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv,
+                                    const int* rows, int m, const int* cols, int n, int trans, double* outr,
+                                    double* outi) {
+  const int64_t tot = (int64_t)m * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = trans ? (int)(e % m) : (int)(e / n);
+    const int j = trans ? (int)(e / m) : (int)(e % n);
+    const int r = rows[i];
+    const int64_t src = (int64_t)r * lda + cols[j];
+    const double sc = rs ? rs[r / rdiv] : 1.0;
+    outr[e] = ar[src] * sc;
+    outi[e] = trans ? -ai[src] * sc : ai[src] * sc;
+  }
+}
+
+// One work-group per entry: copies len values from (sr, si) to (dr, di),
+// to dr[cols[t]] when cols is given, scaled by scale[sidx] when sidx >= 0.
+__global__ __launch_bounds__(256) void rows_copy_kernel(const RowCopy* tab, const double* scale) {
+  const RowCopy t = tab[blockIdx.x];
+  const double sc = t.sidx >= 0 ? scale[t.sidx] : 1.0;
+  for (int64_t c = threadIdx.x; c < t.len; c += 256) {
+    const int64_t dst = t.cols ? (int64_t)t.cols[c] : c;
+    t.dr[dst] = t.sr[c] * sc;
+    t.di[dst] = t.si[c] * sc;
+  }
+}
+
+__global__ void take_kernel(const double* src, const int* idx, int k, double* dst) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o < k) dst[o] = src[idx[o]];
+}
+
 __global__ __launch_bounds__(256) void close_hop_sum_kernel(const double* part, double* out) {
   __shared__ double sh[4];
   const double sr = block_sum(threadIdx.x < kHopBlocks ? part[2 * threadIdx.x] : 0.0, sh);
@@ -534,6 +570,27 @@ void close_op(const double* br, const double* bi, const double* fr, const double
   close_hop_part_kernel<<<kHopBlocks, 256, 0, s>>>(br, bi, fr, fi, chi, D, cr, d, shift, mode, part);
   PTEBD_LAUNCH_CHECK();
   close_hop_sum_kernel<<<1, 256, 0, s>>>(part, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void gather_block(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv, const int* rows, int m,
+                  const int* cols, int n, int trans, double* outr, double* outi, hipStream_t s) {
+  const int64_t tot = (int64_t)m * n;
+  if (tot <= 0) return;
+  gather_block_kernel<<<(int)std::min<int64_t>((tot + 255) / 256, 8192), 256, 0, s>>>(ar, ai, lda, rs, rdiv, rows, m,
+                                                                                      cols, n, trans, outr, outi);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void rows_copy(const RowCopy* tab, int count, const double* scale, hipStream_t s) {
+  if (count <= 0) return;
+  rows_copy_kernel<<<count, 256, 0, s>>>(tab, scale);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void take(const double* src, const int* idx, int k, double* dst, hipStream_t s) {
+  if (k <= 0) return;
+  take_kernel<<<ceil_div(k, 256), 256, 0, s>>>(src, idx, k, dst);
   PTEBD_LAUNCH_CHECK();
 }
 

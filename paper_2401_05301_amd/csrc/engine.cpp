@@ -71,12 +71,13 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 
 }  // namespace
 
-size_t Sizes::bytes(int workers) const {
+size_t Sizes::bytes(int workers, bool u1) const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
   int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
   w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
   w += 6 * vec + part + 64 + 5 * sub_p + 8;
+  if (u1) w += 2 * uv + (idx + vec) / 2 + 1 + 2 * vec * (int64_t)(sizeof(RowCopy) / sizeof(double));
   d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
 }
@@ -115,6 +116,9 @@ Sizes plan_sizes(int L, int d, int chi_max) {
     s.psi = std::max(s.psi, cl * d * d * d * cr);
     s.V1h = std::max(s.V1h, k1 * n1);
     s.X2 = std::max(s.X2, m2 * n2);
+    const int64_t k2 = std::min<int64_t>(r2, c2);
+    s.uv = std::max(s.uv, std::max(k1 * n1, k2 * n2));
+    s.idx = std::max(s.idx, std::max(m1 + n1, m2 + n2));
     s.G = std::max(s.G, std::max(r1 * r1, r2 * r2));
     s.vec = std::max(s.vec, std::max(std::max(r1, r2), std::max(m1, m2)));
     maxr = std::max(maxr, std::max(r1, r2));
@@ -152,6 +156,8 @@ Sizes plan_sizes2(int Ls, int D, int chi_max) {
     const int64_t cl = c[K], cr = c[K + 2];
     const int64_t m = cl * D, n = (int64_t)D * cr, r = std::min(m, n);
     s.psi = std::max(s.psi, cl * D * D * cr);
+    s.uv = std::max(s.uv, std::min<int64_t>(r, c[K + 1]) * n);
+    s.idx = std::max(s.idx, m + n);
     s.G = std::max(s.G, r * r);
     s.vec = std::max(s.vec, std::max(m, n));
     maxr = std::max(maxr, r);
@@ -189,6 +195,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->sq = dalloc(W, s.vec);
   W->perm = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
   W->flags = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
+  W->flags_cap = s.vec;
   if (s.sub_p > 0 && W->opts.svd == TEBD_SVD_GRAM_EIG) {
     W->sub_p = (int)s.sub_p;
     W->sZ = zalloc(W, s.sub_p * s.sub_r);
@@ -207,6 +214,17 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   }
   W->part = dalloc(W, s.part);
   W->part_cap = s.part;
+  if (W->opts.u1) {
+    W->u_idx_cap = s.idx + s.vec;
+    W->u_idx = static_cast<int*>(dev_alloc(W, sizeof(int) * W->u_idx_cap));
+    W->u_tab_cap = 2 * s.vec;
+    W->u_tab = static_cast<RowCopy*>(dev_alloc(W, sizeof(RowCopy) * W->u_tab_cap));
+    W->uv = zalloc(W, s.uv);
+    // at most one batched matrix per two values of the union (each has n >= 2)
+    const int64_t cnt = s.vec / 2 + 1;
+    W->u_batch_cap = (int64_t)(sizeof(HermArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) * cnt + 128;
+    W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
+  }
   W->info_i = static_cast<int*>(dev_alloc(W, sizeof(int) * 8));
   W->info_d = dalloc(W, 16);
   W->counter = static_cast<unsigned int*>(dev_alloc(W, sizeof(unsigned int) * 4));
@@ -310,6 +328,8 @@ void upload_product(tebd_mps* M, const int* occ) {
     const double one = 1.0;
     for (int b = 0; b <= L; ++b) PTEBD_HIP(hipMemcpy(M->lam[b], &one, sizeof(double), hipMemcpyHostToDevice));
     M->chi.assign(L + 1, 1);
+    M->q.assign(L + 1, std::vector<int>(1, 0));
+    for (int b = 1; b <= L; ++b) M->q[b][0] = M->q[b - 1][0] + M->qs[so[b - 1]];
     return;
   }
   const int L = M->L, d = M->d;
@@ -323,10 +343,13 @@ void upload_product(tebd_mps* M, const int* occ) {
   const double one = 1.0;
   for (int b = 0; b <= L; ++b) PTEBD_HIP(hipMemcpy(M->lam[b], &one, sizeof(double), hipMemcpyHostToDevice));
   M->chi.assign(L + 1, 1);
+  M->q.assign(L + 1, std::vector<int>(1, 0));
+  for (int b = 1; b <= L; ++b) M->q[b][0] = M->q[b - 1][0] + M->qs[occ[b - 1]];
 }
 
 void upload_state(tebd_mps* M, const int* chi, const double* B, const double* lam) {
   const int L = M->L, d = M->d;
+  if (M->u1) M->q = infer_charges(M, chi, B);
   int64_t off = 0;
   for (int i = 0; i < L; ++i) {
     const int64_t n = (int64_t)chi[i] * d * chi[i + 1];
@@ -897,6 +920,357 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   return k;
 }
 
+// Independent Hermitian matrices (H n x n in place, eigenvector rows into W,
+// both with leading dimension n) for one batched Jacobi.
+struct BatchItem {
+  double* hr;
+  double* hi;
+  double* wr;
+  double* wi;
+  int n;
+};
+
+// Two-sided block Jacobi on every matrix of the batch at once: each round
+// launches the pair solves and the rotations of all matrices still above
+// their own threshold (c u trace of that matrix), so small matrices share
+// the device instead of running their latency-bound rounds one after the
+// other.  Convergence is counted per matrix before every sweep.
+void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
+  hipStream_t s = M->stream;
+  const int count = (int)items.size();
+  // device layout in u_batch: HermArgs[count], eig_first[count+1], app_first[count+1],
+  // active[count], counts[count], tol[count]
+  const size_t need = sizeof(HermArgs) * count + 2 * sizeof(int64_t) * (count + 1) + 2 * sizeof(int) * count +
+                      sizeof(double) * count + 64;
+  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "U(1) SVD: batched Jacobi tables exceed their buffer");
+  char* base = static_cast<char*>(M->u_batch);
+  HermArgs* d_tab = reinterpret_cast<HermArgs*>(base);
+  int64_t* d_eig = reinterpret_cast<int64_t*>(d_tab + count);
+  int64_t* d_app = d_eig + (count + 1);
+  int* d_active = reinterpret_cast<int*>(d_app + (count + 1));
+  unsigned int* d_counts = reinterpret_cast<unsigned int*>(d_active + count);
+  double* d_tol = reinterpret_cast<double*>(reinterpret_cast<char*>(d_counts + count) +
+                                            ((8 - (reinterpret_cast<uintptr_t>(d_counts + count) & 7)) & 7));
+  std::vector<HermArgs>& tab = M->h_herm;
+  tab.assign(count, HermArgs{});
+  std::vector<int64_t>& first = M->h_first;
+  first.assign(2 * (count + 1), 0);
+  int64_t qoff = 0, foff = 0;
+  int max_n = 0;
+  for (int i = 0; i < count; ++i) {
+    const BatchItem& it = items[i];
+    HermArgs& a = tab[i];
+    int nb = (it.n + 15) / 16;
+    if (nb < 2) nb = 2;
+    if (nb & 1) ++nb;
+    a.hr = it.hr; a.hi = it.hi; a.ldh = it.n; a.n = it.n; a.nb = nb;
+    a.wr = it.wr; a.wi = it.wi; a.ldw = it.n;
+    a.wcols = 128;
+    a.wchunks = (it.n + a.wcols - 1) / a.wcols;
+    a.qbuf = M->part + qoff;
+    a.flag = M->flags + foff;
+    a.rotated = M->counter;
+    a.tol_abs = d_tol + i;
+    a.inner_sweeps = inner_sweeps();
+    qoff += (int64_t)(nb / 2) * 2 * 32 * 32;
+    foff += nb / 2;
+    first[i + 1] = first[i] + nb / 2;
+    first[count + 1 + i + 1] = first[count + 1 + i] + herm_apply_groups(a);
+    max_n = std::max(max_n, it.n);
+    herm_tol(it.hr, it.n, it.n, herm_tol_units(), d_tol + i, s);
+    set_identity(it.wr, it.wi, it.n, it.n, s);
+  }
+  if (qoff > M->part_cap || foff > M->flags_cap) throw Error(-1, "U(1) SVD: batched Jacobi scratch too small");
+  PTEBD_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(HermArgs) * count, hipMemcpyHostToDevice, s));
+  PTEBD_HIP(hipMemcpyAsync(d_eig, first.data(), sizeof(int64_t) * 2 * (count + 1), hipMemcpyHostToDevice, s));
+  std::vector<int>& act = M->h_active;
+  act.assign(count, 1);
+  std::vector<unsigned int>& cnt = M->h_counts;
+  cnt.assign(count, 0);
+  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
+  PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+  for (int sweep = 0;; ++sweep) {
+    PTEBD_HIP(hipMemsetAsync(d_counts, 0, sizeof(unsigned int) * count, s));
+    count_above_batched(d_tab, count, d_active, max_n, d_counts, s);
+    PTEBD_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    int rounds = 0;
+    for (int i = 0; i < count; ++i) {
+      if (act[i] && cnt[i] == 0) act[i] = 0;
+      if (act[i]) rounds = std::max(rounds, tab[i].nb - 1);
+    }
+    if (rounds == 0) {
+      M->last_sweeps = sweep;
+      M->total_sweeps += sweep;
+      return;
+    }
+    if (sweep == max_sweeps) {
+      M->failed = true;
+      throw Error(-4, "batched Hermitian Jacobi did not converge within max_sweeps (" + std::to_string(count) +
+                          " sectors)");
+    }
+    PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    for (int t = 0; t < rounds; ++t)
+      herm_round_batched(d_tab, d_eig, first[count], d_app, first[2 * (count + 1) - 1], count,
+                         d_active, t, s);
+  }
+}
+
+// U(1) block-sparse truncated SVD (Sec. II B: the tensors are kept in
+// particle-number sectors).  With the rows and columns of A grouped by their
+// particle number, diag(rs) A is block diagonal, so its singular triplets are
+// those of the blocks: each block is gathered into xbuf and decomposed on its
+// own (Jacobi: one-sided Jacobi on the rows of the block or of its conjugate
+// transpose; Gram: the smaller Gram matrix of the block and its eigenpairs),
+// and the truncation rule runs once over the union of the sector spectra, so
+// that the kept values, the discarded weight and the ledger are those of the
+// dense SVD.  The kept rows of V^+ are scattered back to the dense column
+// positions; every other entry of the output rows is zero.
+int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const std::vector<int>& cq,
+                 double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf, std::vector<int>& kept_q) {
+  hipStream_t s = M->stream;
+  const int m = in.m, n = in.n;
+  const bool gram = M->opts.svd == TEBD_SVD_GRAM_EIG;
+  double* nrm = M->info_d + 2 * slot;
+  int* kdev = M->info_i + slot;
+  const double eps = gram ? std::max(M->opts.trunc_rel, kGramSigmaFloor) : M->opts.trunc_rel;
+  const double w_max = M->opts.trunc_weight;
+  struct Sector {
+    int q = 0;
+    std::vector<int> rows, cols;
+    int m = 0, n = 0, r = 0;
+    bool left = true;        // decompose the block itself (Jacobi on its rows, Gram B B^+), else its conjugate transpose
+    int64_t off = 0;         // block in xbuf
+    int64_t goff = 0;        // r x r Gram / eigenvector rows / rotations in G and W
+    int u0 = 0;              // first value of the sector in the union
+    int64_t ro = 0, co = 0;  // row and column lists in u_idx
+    std::vector<int> kept;   // ranks (by decreasing value) of the kept values
+    int64_t xoff = 0, yoff = 0;
+  };
+  std::map<int, Sector> by_q;
+  for (int r = 0; r < m; ++r) by_q[rq[r]].rows.push_back(r);
+  for (int c = 0; c < n; ++c) {
+    auto it = by_q.find(cq[c]);
+    if (it != by_q.end()) it->second.cols.push_back(c);
+  }
+  std::vector<Sector*> secs;
+  std::vector<BatchItem> batch;
+  int64_t off = 0, goff = 0, io = 0;
+  int nvals = 0;
+  M->h_idx.clear();
+  for (auto& kv : by_q) {
+    Sector& S = kv.second;
+    if (S.cols.empty()) continue;   // rows of this number meet no column: they are zero
+    S.q = kv.first;
+    S.m = (int)S.rows.size();
+    S.n = (int)S.cols.size();
+    S.r = std::min(S.m, S.n);
+    S.left = in.prefer_right ? (S.m < S.n) : (S.m <= S.n);
+    S.off = off;
+    off += (int64_t)S.m * S.n;
+    S.goff = goff;
+    goff += (int64_t)S.r * S.r;
+    S.u0 = nvals;
+    nvals += S.r;
+    S.ro = io;
+    M->h_idx.insert(M->h_idx.end(), S.rows.begin(), S.rows.end());
+    io += S.m;
+    S.co = io;
+    M->h_idx.insert(M->h_idx.end(), S.cols.begin(), S.cols.end());
+    io += S.n;
+    secs.push_back(&S);
+  }
+  if (secs.empty()) throw Error(-1, "U(1) SVD: no particle-number sector has both rows and columns");
+  if (io + std::min(m, n) > M->u_idx_cap) throw Error(-1, "U(1) SVD: sector lists exceed their buffer");
+  PTEBD_HIP(hipMemcpyAsync(M->u_idx, M->h_idx.data(), sizeof(int) * io, hipMemcpyHostToDevice, s));
+  for (Sector* S : secs) {
+    const int* rows = M->u_idx + S->ro;
+    const int* cols = M->u_idx + S->co;
+    double* br = xbuf.re + S->off;
+    double* bi = xbuf.im + S->off;
+    double* wr = M->W.re + S->goff;
+    double* wi = M->W.im + S->goff;
+    if (!gram) {
+      if (S->left) {
+        // rows of the block become sigma_i v_i^+
+        gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, s);
+        if (S->m > 1) run_jacobi(M, br, bi, S->n, nullptr, nullptr, 0, S->m, S->n, jacobi_tol(S->n), 0.0);
+      } else {
+        // rows of the conjugate transpose (n x m) become sigma_i u_i^+; the
+        // accumulated rotations are the rows v_i^+
+        gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 1, br, bi, s);
+        if (S->n > 1)
+          run_jacobi(M, br, bi, S->m, wr, wi, S->n, S->n, S->m, jacobi_tol(S->m), 0.0);
+        else
+          set_identity(wr, wi, 1, 1, s);
+      }
+    } else {
+      gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, s);
+      double* gr = M->G.re + S->goff;
+      double* gi = M->G.im + S->goff;
+      ZGemmArgs g;
+      if (S->left) {   // B B^+ (m x m)
+        g.m = S->m; g.n = S->m; g.k = S->n;
+        g.ar = br; g.ai = bi; g.lda = S->n;
+        g.br = br; g.bi = bi; g.ldb = S->n; g.transB = 1;
+      } else {         // B^+ B (n x n)
+        g.m = S->n; g.n = S->n; g.k = S->m;
+        g.ar = br; g.ai = bi; g.lda = S->n; g.transA = 1;
+        g.br = br; g.bi = bi; g.ldb = S->n;
+      }
+      g.cr = gr; g.ci = gi; g.ldc = S->r;
+      g.herm_out = 1;
+      zgemm(g, 0, s);
+      if (S->r > 1)
+        batch.push_back(BatchItem{gr, gi, wr, wi, S->r});
+      else
+        set_identity(wr, wi, 1, 1, s);
+    }
+  }
+  // all sector eigenproblems of the Gram route in one batched Jacobi
+  if (!batch.empty()) run_herm_jacobi_batched(M, batch);
+  // the union of the sector spectra (after every Jacobi run, which uses
+  // M->norms as its own scratch)
+  for (Sector* S : secs) {
+    double* out = M->norms + S->u0;
+    if (!gram) {
+      if (S->left)
+        row_norms(xbuf.re + S->off, xbuf.im + S->off, S->n, S->m, S->n, out, s);
+      else
+        row_norms(xbuf.re + S->off, xbuf.im + S->off, S->m, S->n, S->m, out, s);
+    } else {
+      herm_diag(M->G.re + S->goff, S->r, S->r, out, s);
+    }
+  }
+  select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
+                  M->ledger, nullptr, s);
+  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  const int k = M->h_info[0];
+  M->h_perm.resize(k);
+  PTEBD_HIP(hipMemcpyAsync(M->h_perm.data(), M->perm, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  std::vector<int> u0s;
+  for (Sector* S : secs) u0s.push_back(S->u0);
+  for (int i = 0; i < k; ++i) {
+    const int u = M->h_perm[i];
+    const int si = (int)(std::upper_bound(u0s.begin(), u0s.end(), u) - u0s.begin()) - 1;
+    if (si < 0 || u >= secs[si]->u0 + secs[si]->r) throw Error(-3, "U(1) SVD: kept value outside every sector");
+    secs[si]->kept.push_back(i);
+  }
+  // output order: by particle number, then by rank
+  kept_q.clear();
+  M->h_order.clear();
+  for (Sector* S : secs)
+    for (int i : S->kept) {
+      M->h_order.push_back(i);
+      kept_q.push_back(S->q);
+    }
+  int* d_order = M->u_idx + io;
+  PTEBD_HIP(hipMemcpyAsync(d_order, M->h_order.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
+  take(lam_out, d_order, k, M->sq, s);
+  PTEBD_HIP(hipMemcpyAsync(lam_out, M->sq, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+  // row-copy table: for the left Gram route the scaled eigenvector rows
+  // S^-1 U^+ of every sector first (into G), then the output rows
+  M->h_tab.clear();
+  int nx = 0;
+  if (gram) {
+    int64_t xo = 0, yo = 0;
+    for (Sector* S : secs) {
+      if (!S->left || S->kept.empty()) continue;
+      S->xoff = xo;
+      S->yoff = yo;
+      for (size_t t = 0; t < S->kept.size(); ++t) {
+        const int i = S->kept[t];
+        const int64_t loc = M->h_perm[i] - S->u0;
+        M->h_tab.push_back(RowCopy{M->W.re + S->goff + loc * S->m, M->W.im + S->goff + loc * S->m,
+                                   M->G.re + xo + (int64_t)t * S->m, M->G.im + xo + (int64_t)t * S->m, nullptr,
+                                   (int64_t)S->m, (int64_t)i});
+      }
+      xo += (int64_t)S->kept.size() * S->m;
+      yo += (int64_t)S->kept.size() * S->n;
+    }
+    nx = (int)M->h_tab.size();
+  }
+  int64_t o = 0;
+  for (Sector* S : secs) {
+    for (size_t t = 0; t < S->kept.size(); ++t, ++o) {
+      const int i = S->kept[t];
+      const int64_t loc = M->h_perm[i] - S->u0;
+      const double* sr;
+      const double* si;
+      int64_t sidx = -1;
+      if (!gram && S->left) {
+        sr = xbuf.re + S->off + loc * S->n;
+        si = xbuf.im + S->off + loc * S->n;
+        sidx = i;
+      } else if (gram && S->left) {
+        sr = M->uv.re + S->yoff + (int64_t)t * S->n;
+        si = M->uv.im + S->yoff + (int64_t)t * S->n;
+      } else {
+        sr = M->W.re + S->goff + loc * S->n;
+        si = M->W.im + S->goff + loc * S->n;
+      }
+      M->h_tab.push_back(RowCopy{sr, si, vhr + o * n, vhi + o * n, M->u_idx + S->co, (int64_t)S->n, sidx});
+    }
+  }
+  if ((int64_t)M->h_tab.size() > M->u_tab_cap) throw Error(-1, "U(1) SVD: row table exceeds its buffer");
+  PTEBD_HIP(hipMemcpyAsync(M->u_tab, M->h_tab.data(), sizeof(RowCopy) * M->h_tab.size(), hipMemcpyHostToDevice, s));
+  if (nx > 0) {
+    rows_copy(M->u_tab, nx, M->inv_sig, s);
+    for (Sector* S : secs) {
+      if (!S->left || S->kept.empty()) continue;
+      ZGemmArgs v;   // V^+ rows of the sector = (S^-1 U^+) B
+      v.m = (int)S->kept.size(); v.n = S->n; v.k = S->m;
+      v.ar = M->G.re + S->xoff; v.ai = M->G.im + S->xoff; v.lda = S->m;
+      v.br = xbuf.re + S->off; v.bi = xbuf.im + S->off; v.ldb = S->n;
+      v.cr = M->uv.re + S->yoff; v.ci = M->uv.im + S->yoff; v.ldc = S->n;
+      zgemm(v, 0, s);
+    }
+  }
+  fill_zero(vhr, (int64_t)k * n, s);
+  fill_zero(vhi, (int64_t)k * n, s);
+  rows_copy(M->u_tab + nx, k, M->inv_sig, s);
+  // the host tables stay untouched until the next call, which synchronises first
+  return k;
+}
+
+std::vector<std::vector<int>> infer_charges(const tebd_mps* M, const int* chi, const double* B) {
+  const int L = M->L, d = M->d;
+  std::vector<std::vector<int>> q(L + 1);
+  q[0].assign(1, 0);
+  int64_t off = 0;
+  for (int i = 0; i < L; ++i) {
+    const int cl = chi[i], cr = chi[i + 1];
+    const int64_t nel = (int64_t)cl * d * cr;
+    const double* re = B + off;
+    const double* im = B + off + nel;
+    std::vector<int> qr(cr, 0);
+    std::vector<char> seen(cr, 0);
+    for (int a = 0; a < cl; ++a)
+      for (int t = 0; t < d; ++t)
+        for (int b = 0; b < cr; ++b) {
+          const int64_t e = ((int64_t)a * d + t) * cr + b;
+          if (re[e] == 0.0 && im[e] == 0.0) continue;
+          const int v = q[i][a] + M->qs[t];
+          if (!seen[b]) {
+            seen[b] = 1;
+            qr[b] = v;
+          } else if (qr[b] != v) {
+            throw Error(-1, "state has no definite particle number on bond " + std::to_string(i + 1) + " index " +
+                                std::to_string(b));
+          }
+        }
+    for (int b = 0; b < cr; ++b)
+      if (!seen[b])
+        throw Error(-1, "bond " + std::to_string(i + 1) + " index " + std::to_string(b) +
+                            " is reached by no non-zero entry of its left tensor");
+    q[i + 1] = std::move(qr);
+    off += 2 * nel;
+  }
+  return q;
+}
+
 namespace {
 
 // One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
@@ -938,7 +1312,23 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   in1.warm.sr = S->Br[j]; in1.warm.si = S->Bi[j]; in1.warm.ld = c1;
   in1.warm.src_rows = m1; in1.warm.src_cols = c1;
   in1.warm.rs = S->lam[j]; in1.warm.rdiv = d;
-  const int k1 = svd_trunc(W, in1, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi);
+  std::vector<int> q1, q2;
+  int k1;
+  if (S->u1) {
+    // rows (a, s1) hold q_j[a] + s1 bosons left of bond j+1; columns
+    // (s2, s3, b) hold q_{j+3}[b] - s2 - s3
+    const std::vector<int>& ql = S->q[j];
+    const std::vector<int>& qr = S->q[j + 3];
+    std::vector<int> rq((size_t)m1), cq((size_t)n1);
+    for (int a = 0; a < cl; ++a)
+      for (int t = 0; t < d; ++t) rq[(size_t)a * d + t] = ql[a] + S->qs[t];
+    for (int t2 = 0; t2 < d; ++t2)
+      for (int t3 = 0; t3 < d; ++t3)
+        for (int b = 0; b < cr; ++b) cq[((size_t)t2 * d + t3) * cr + b] = qr[b] - S->qs[t2] - S->qs[t3];
+    k1 = svd_trunc_u1(W, in1, rq, cq, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi, q1);
+  } else {
+    k1 = svd_trunc(W, in1, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi);
+  }
   {  // B_j = psi' V1 / |S1|
     ZGemmArgs g;
     g.m = m1; g.n = k1; g.k = n1;
@@ -956,7 +1346,19 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   in2.warm.kind = 2;
   in2.warm.sr = S->Br[j + 2]; in2.warm.si = S->Bi[j + 2]; in2.warm.ld = n2;
   in2.warm.src_rows = c2; in2.warm.src_cols = n2;
-  const int k2 = svd_trunc(W, in2, S->lam[j + 2], S->Br[j + 2], S->Bi[j + 2], 1, W->X2);
+  int k2;
+  if (S->u1) {
+    // rows (a', s2): q1[a'] + s2; columns (s3, b): q_{j+3}[b] - s3
+    const std::vector<int>& qr = S->q[j + 3];
+    std::vector<int> rq((size_t)m2), cq((size_t)n2);
+    for (int a = 0; a < k1; ++a)
+      for (int t = 0; t < d; ++t) rq[(size_t)a * d + t] = q1[a] + S->qs[t];
+    for (int t3 = 0; t3 < d; ++t3)
+      for (int b = 0; b < cr; ++b) cq[(size_t)t3 * cr + b] = qr[b] - S->qs[t3];
+    k2 = svd_trunc_u1(W, in2, rq, cq, S->lam[j + 2], S->Br[j + 2], S->Bi[j + 2], 1, W->X2, q2);
+  } else {
+    k2 = svd_trunc(W, in2, S->lam[j + 2], S->Br[j + 2], S->Bi[j + 2], 1, W->X2);
+  }
   {  // B_{j+1} = V1^+ V2 / |S2|
     ZGemmArgs g;
     g.m = m2; g.n = k2; g.k = n2;
@@ -968,6 +1370,10 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   }
   S->chi[j + 1] = k1;
   S->chi[j + 2] = k2;
+  if (S->u1) {
+    S->q[j + 1] = std::move(q1);
+    S->q[j + 2] = std::move(q2);
+  }
 }
 
 // Two-site gate on super sites (K, K+1) (Sec. II B, d_eff = D = d^2):
@@ -1005,7 +1411,21 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
   in.warm.src_rows = m1; in.warm.src_cols = cm;
   in.warm.rs = S->lam[K]; in.warm.rdiv = D;
   // V^+ goes straight to B_{K+1}: psi' no longer needs the old B_{K+1}
-  const int k = svd_trunc(W, in, S->lam[K + 1], S->Br[K + 1], S->Bi[K + 1], 0, W->psi);
+  std::vector<int> qk;
+  int k;
+  if (S->u1) {
+    // rows (a, s1): q_K[a] + bosons of s1; columns (s2, b): q_{K+2}[b] - bosons of s2
+    const std::vector<int>& ql = S->q[K];
+    const std::vector<int>& qr = S->q[K + 2];
+    std::vector<int> rq((size_t)m1), cq((size_t)n1);
+    for (int a = 0; a < cl; ++a)
+      for (int t = 0; t < D; ++t) rq[(size_t)a * D + t] = ql[a] + S->qs[t];
+    for (int t = 0; t < D; ++t)
+      for (int b = 0; b < cr; ++b) cq[(size_t)t * cr + b] = qr[b] - S->qs[t];
+    k = svd_trunc_u1(W, in, rq, cq, S->lam[K + 1], S->Br[K + 1], S->Bi[K + 1], 0, W->psi, qk);
+  } else {
+    k = svd_trunc(W, in, S->lam[K + 1], S->Br[K + 1], S->Bi[K + 1], 0, W->psi);
+  }
   {  // B_K = psi' V / |S|
     ZGemmArgs g;
     g.m = m1; g.n = k; g.k = n1;
@@ -1016,6 +1436,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     zgemm(g, 0, s);
   }
   S->chi[K + 1] = k;
+  if (S->u1) S->q[K + 1] = std::move(qk);
 }
 
 void update_gate(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {

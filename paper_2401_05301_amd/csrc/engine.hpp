@@ -19,6 +19,12 @@ struct tebd_mps {
   int L = 0, d = 0, chi_max = 0;    // sites and local dimension of the chain the MPS lives on
   bool super = false;               // super-site chain: L = phys_L / 2 sites of dimension d = pd^2
   int phys_L = 0, pd = 0;           // physical sites and their local dimension
+  // Particle-number sectors (opts.u1): bosons left of every bond index
+  // (b = 0..L, chi[b] entries each; held by the state) and bosons of every
+  // local level (d entries).
+  bool u1 = false;
+  std::vector<std::vector<int>> q;
+  std::vector<int> qs;
   std::vector<int> cap;   // bond capacity, b = 0..L
   std::vector<int> chi;   // current bond dimension, b = 0..L (host mirror)
 
@@ -78,6 +84,23 @@ struct tebd_mps {
   std::vector<tebd_mps*> workers;
   tebd_mps* parent = nullptr;
   double* wslots = nullptr;   // discarded weight of each gate of the current layer (device, L)
+
+  // Sector tables of one U(1) SVD (workers only): row and column lists and
+  // the output order on the device, the row-copy table, the projected rows.
+  int* u_idx = nullptr;
+  int64_t u_idx_cap = 0;
+  ptebd::RowCopy* u_tab = nullptr;
+  int64_t u_tab_cap = 0;
+  Z uv;
+  std::vector<int> h_idx, h_perm, h_order;
+  std::vector<ptebd::RowCopy> h_tab;
+  void* u_batch = nullptr;        // batched Jacobi tables of the sector eigenproblems
+  int64_t u_batch_cap = 0;        // bytes
+  int64_t flags_cap = 0;          // entries of flags
+  std::vector<ptebd::HermArgs> h_herm;
+  std::vector<int64_t> h_first;
+  std::vector<int> h_active;
+  std::vector<unsigned int> h_counts;
 };
 
 namespace ptebd {
@@ -88,7 +111,8 @@ struct Sizes {
   int64_t T1 = 0, psi = 0, X2 = 0, G = 0, W = 0, V1h = 0, meas_sq = 0, meas_rect = 0, vec = 0, part = 0;
   int64_t sub_p = 0, sub_r = 0;   // subspace iteration width and row length
   int64_t gates = 0;
-  size_t bytes(int workers) const;
+  int64_t uv = 0, idx = 0;         // U(1) SVD: projected rows (k x n) and sector lists (m + n)
+  size_t bytes(int workers, bool u1 = false) const;
 };
 
 // Number of gate workers of a handle: opts.workers if positive, else 4,
@@ -141,6 +165,18 @@ struct SvdIn {
 };
 // Truncated SVD of diag(rs) A with the handle's settings (see engine.cpp).
 int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf);
+// The same for an A whose rows and columns carry particle numbers rq[m] and
+// cq[n], A(r, c) = 0 unless rq[r] == cq[c]: every sector is decomposed on its
+// own and the truncation rule is applied to the union of their spectra.  The
+// kept rows of V^+ (and kept_q, their particle numbers) are ordered by
+// particle number, then by decreasing singular value; lam_out likewise.
+int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const std::vector<int>& cq,
+                 double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf, std::vector<int>& kept_q);
+// Particle numbers of every bond index of an uploaded state, inferred from
+// the non-zero entries of its tensors (host copies in mps_init_state
+// layout); throws an EINVAL Error when an index is reached by entries of two
+// numbers or by none.
+std::vector<std::vector<int>> infer_charges(const tebd_mps* M, const int* chi, const double* B);
 void* dev_alloc(tebd_mps* M, size_t bytes);
 
 }  // namespace ptebd

@@ -139,13 +139,13 @@ __device__ void block_eig(double (*Cr)[PR + 1], double (*Ci)[PR + 1], double (*Q
 // Threads per pair solve: one per (pair, pair) 2 x 2 block of the 32 x 32 block.
 constexpr int kEigThreads = 256;
 
-// grid: nb/2 work-groups.  Writes Q of each pair (or flag 0 if the pair is
-// already diagonal to the threshold).
-__global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
-  __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
+// Pair `pair` of the round: writes its Q (or flag 0 if the pair is already
+// diagonal to the threshold).
+__device__ __forceinline__ void herm_eig_pair(const HermArgs& a, int round, int pair, double (*Cr)[PR + 1],
+                                              double (*Ci)[PR + 1], double (*Qr)[PR + 1], double (*Qi)[PR + 1]) {
   const int tid = threadIdx.x;
   int I, J;
-  round_pair(a.nb, round, blockIdx.x, I, J);
+  round_pair(a.nb, round, pair, I, J);
   double vc[PR * PR / kEigThreads][2];
 #pragma unroll
   for (int u = 0; u < PR * PR / kEigThreads; ++u) {
@@ -172,13 +172,13 @@ __global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
     const int p = idx / PR, q = idx % PR;
     if (p < q && hypot(Cr[p][q], Ci[p][q]) > thr) need = 1;
   }
-  double* qout = a.qbuf + (int64_t)blockIdx.x * 2 * PR * PR;
+  double* qout = a.qbuf + (int64_t)pair * 2 * PR * PR;
   if (!__syncthreads_or(need)) {
-    if (tid == 0) a.flag[blockIdx.x] = 0;
+    if (tid == 0) a.flag[pair] = 0;
     return;
   }
   if (tid == 0) {
-    a.flag[blockIdx.x] = 1;
+    a.flag[pair] = 1;
     atomicAdd(a.rotated, 1u);
   }
   block_eig(Cr, Ci, Qr, Qi, 0.5 * thr, a.inner_sweeps);
@@ -188,16 +188,36 @@ __global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
   }
 }
 
-// grid.x = npairs*(npairs+1)/2 block-pair sandwiches, then npairs * wchunks
-// W-row updates.
-__global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
-  __shared__ double Ar[PR][PR + 1], Ai[PR][PR + 1], Tr[PR][PR + 1], Ti[PR][PR + 1];
-  __shared__ double Q1r[PR][PR + 1], Q1i[PR][PR + 1], Q2r[PR][PR + 1], Q2i[PR][PR + 1];
+// grid: nb/2 work-groups, one pair each.
+__global__ __launch_bounds__(kEigThreads) void herm_eig(HermArgs a, int round) {
+  __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
+  herm_eig_pair(a, round, blockIdx.x, Cr, Ci, Qr, Qi);
+}
+
+// Work-groups of one round: npairs*(npairs+1)/2 block-pair sandwiches, then
+// npairs * wchunks W-row updates.
+__host__ __device__ __forceinline__ int64_t apply_groups(const HermArgs& a) {
+  const int64_t npairs = a.nb / 2;
+  return npairs * (npairs + 1) / 2 + (a.wr ? npairs * a.wchunks : 0);
+}
+
+struct ApplyLds {
+  double Ar[PR][PR + 1], Ai[PR][PR + 1], Tr[PR][PR + 1], Ti[PR][PR + 1];
+  double Q1r[PR][PR + 1], Q1i[PR][PR + 1], Q2r[PR][PR + 1], Q2i[PR][PR + 1];
+};
+
+__device__ __forceinline__ void herm_apply_group(const HermArgs& a, int round, int bid, ApplyLds& L) {
+  auto& Ar = L.Ar;
+  auto& Ai = L.Ai;
+  auto& Tr = L.Tr;
+  auto& Ti = L.Ti;
+  auto& Q1r = L.Q1r;
+  auto& Q1i = L.Q1i;
+  auto& Q2r = L.Q2r;
+  auto& Q2i = L.Q2i;
   const int tid = threadIdx.x;
   const int npairs = a.nb / 2;
   const int nsand = npairs * (npairs + 1) / 2;
-  int bid = blockIdx.x;
-  const int round = a.round;
   if (bid < nsand) {
     // decode (P1, P2), P1 >= P2
     int P1 = 0;
@@ -353,6 +373,66 @@ __global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
+  __shared__ ApplyLds L;
+  herm_apply_group(a, a.round, blockIdx.x, L);
+}
+
+// Batched form: the same round on many independent Hermitian matrices (one
+// HermArgs each, in the device table tab), for the particle-number sectors
+// of one SVD.  first[i] is the first work-group of matrix i (first[count] the
+// total); a matrix takes part while active[i] != 0 and round < nb_i - 1 (its
+// own sweep may be shorter than the longest one).
+__device__ __forceinline__ int batch_owner(const int64_t* first, int count, int64_t bid) {
+  int lo = 0, hi = count;   // first[lo] <= bid < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kEigThreads) void herm_eig_batched(const HermArgs* tab, const int64_t* first, int count,
+                                                                const int* active, int round) {
+  __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
+  const int i = batch_owner(first, count, blockIdx.x);
+  const HermArgs a = tab[i];
+  if (!active[i] || round >= a.nb - 1) return;
+  herm_eig_pair(a, round, (int)(blockIdx.x - first[i]), Cr, Ci, Qr, Qi);
+}
+
+__global__ __launch_bounds__(256) void herm_apply_batched(const HermArgs* tab, const int64_t* first, int count,
+                                                          const int* active, int round) {
+  __shared__ ApplyLds L;
+  const int i = batch_owner(first, count, blockIdx.x);
+  const HermArgs a = tab[i];
+  if (!active[i] || round >= a.nb - 1) return;
+  herm_apply_group(a, round, (int)(blockIdx.x - first[i]), L);
+}
+
+// Per matrix i: number of off-diagonal entries above its threshold, into
+// count[i] (grid.y = matrix).
+__global__ __launch_bounds__(256) void count_above_batched_kernel(const HermArgs* tab, int count, const int* active,
+                                                                  unsigned int* out) {
+  const int i = blockIdx.y;
+  if (i >= count || !active[i]) return;
+  const HermArgs a = tab[i];
+  const double t = *a.tol_abs;
+  const int n = a.n;
+  unsigned int c = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n), q = (int)(e % n);
+    if (r < q && hypot(a.hr[(int64_t)r * a.ldh + q], a.hi[(int64_t)r * a.ldh + q]) > t) ++c;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0 && c > 0) atomicAdd(out + i, c);
+}
+
 // Absolute off-diagonal target c u sum_i |H_ii|: for the positive
 // semi-definite Gram matrices this is c units of rounding of their trace,
 // the scale of the absolute error their entries carry.
@@ -448,6 +528,30 @@ void herm_round(HermArgs a, int round, hipStream_t s) {
     herm_apply<<<nsand + nw, 256, 0, s>>>(a);
     PTEBD_LAUNCH_CHECK();
   }
+}
+
+int64_t herm_apply_groups(const HermArgs& a) { return apply_groups(a); }
+
+void herm_round_batched(const HermArgs* tab, const int64_t* eig_first, int64_t eig_total, const int64_t* app_first,
+                        int64_t app_total, int count, const int* active, int round, hipStream_t s) {
+  {
+    ProfScope ps(K_HERM_EIG, 0.0, s);
+    herm_eig_batched<<<(unsigned)eig_total, kEigThreads, 0, s>>>(tab, eig_first, count, active, round);
+    PTEBD_LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps(K_HERM_APPLY, 0.0, s);
+    herm_apply_batched<<<(unsigned)app_total, 256, 0, s>>>(tab, app_first, count, active, round);
+    PTEBD_LAUNCH_CHECK();
+  }
+}
+
+void count_above_batched(const HermArgs* tab, int count, const int* active, int max_n, unsigned int* out,
+                         hipStream_t s) {
+  const int64_t total = (int64_t)max_n * max_n;
+  dim3 g((unsigned)std::min<int64_t>((total + 255) / 256, 256), (unsigned)count);
+  count_above_batched_kernel<<<g, 256, 0, s>>>(tab, count, active, out);
+  PTEBD_LAUNCH_CHECK();
 }
 
 void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s) {

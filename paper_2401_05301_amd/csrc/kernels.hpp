@@ -64,6 +64,18 @@ struct HermArgs {
   int round;
   int inner_sweeps;                         // sweeps of the 32 x 32 pair solve per visit
 };
+// Work-groups herm_apply uses for one round of a.
+int64_t herm_apply_groups(const HermArgs& a);
+// One round on each of `count` independent matrices (device table tab;
+// eig_first / app_first: prefix sums of nb/2 and herm_apply_groups over the
+// table, count + 1 entries; totals are their last entries).  Matrices with
+// active[i] == 0, or whose sweep has fewer rounds, sit the round out.
+void herm_round_batched(const HermArgs* tab, const int64_t* eig_first, int64_t eig_total, const int64_t* app_first,
+                        int64_t app_total, int count, const int* active, int round, hipStream_t s);
+// out[i] += number of off-diagonal entries of matrix i above *tab[i].tol_abs
+// (active matrices only; max_n bounds every n; out must start at zero).
+void count_above_batched(const HermArgs* tab, int count, const int* active, int max_n, unsigned int* out,
+                         hipStream_t s);
 // Largest |H_ij| / sqrt(max(H_ii, floor) max(H_jj, floor)) over the
 // off-diagonal entries above *tol of a Hermitian PSD H (synchronises; 0 when
 // none is above tol).
@@ -156,6 +168,28 @@ void close_op(const double* br, const double* bi, const double* fr, const double
 // Per super site: (n_first, n_second, Re, Im <b+_first b_second>) into out[4 K ..].
 void supersite_local(const double* const* br, const double* const* bi, const double* const* lam, const int* chil,
                      const int* chir, int Ls, int d, double* out, hipStream_t s);
+// Particle-number sectors (U(1) block-sparse SVD).
+// out = the block rows[0..m) x cols[0..n) of diag(rs) A (rs[r / rdiv], may be
+// null): out(i, j) with leading dimension n (trans == 0), or its conjugate
+// transpose out(j, i) with leading dimension m (trans == 1).
+void gather_block(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv, const int* rows, int m,
+                  const int* cols, int n, int trans, double* outr, double* outi, hipStream_t s);
+// One row copy: len values from (sr, si) into (dr, di) at positions cols[t]
+// (or t when cols is null), times scale[sidx] when sidx >= 0.
+struct RowCopy {
+  const double* sr;
+  const double* si;
+  double* dr;
+  double* di;
+  const int* cols;
+  int64_t len;
+  int64_t sidx;
+};
+// count entries of the device table tab, one work-group each; destinations
+// must not overlap.
+void rows_copy(const RowCopy* tab, int count, const double* scale, hipStream_t s);
+// dst[o] = src[idx[o]], o < k (dst must not alias src).
+void take(const double* src, const int* idx, int k, double* dst, hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
 // *acc += sum_{i<n} slots[i], summed in index order by one thread.
 void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s);

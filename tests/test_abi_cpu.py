@@ -56,6 +56,14 @@ def test_validation_without_gpu():
     with pytest.raises(pt.TebdError) as e:
         pt.mps_init_product(pt.make_model(L=4, d=3, U=1.0), opts, [0, 3, 0, 0])
     assert e.value.status == pt.TEBD_EINVAL
+    bad = pt.make_opts(chi_max=16)
+    bad.u1 = 2
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_init_cdw(pt.make_model(L=8, d=3, U=1.0), bad)
+    assert e.value.status == pt.TEBD_EINVAL and "u1" in str(e.value)
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_bond_charges(ctypes.c_void_p(None), 0)
+    assert e.value.status == pt.TEBD_EINVAL
 
 
 def test_footprint_scales_with_chi():
@@ -66,6 +74,8 @@ def test_footprint_scales_with_chi():
     assert 0 < small < big
     # chi = 1024, d = 5, L = 64: state ~5.4 GB plus a few GB of gate workspace
     assert 8e9 < big < 40e9
+    # the sector SVD adds its projected-row buffer per worker
+    assert pt.mps_footprint(m, pt.make_opts(chi_max=1024, u1=True)) > big
 
 
 def test_serve_validation_without_gpu():

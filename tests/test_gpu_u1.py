@@ -1,0 +1,168 @@
+"""U(1) block-sparse SVDs (tebd_opts.u1) against the dense FP64 oracle.
+
+The sector decomposition reaches the dense result up to rounding order, so
+observables, Schmidt spectra (compared after sorting, since the library
+orders each bond by particle number), bond dimensions and the ledger are
+held to the dense bars, and the particle number the library attaches to
+every Schmidt value is checked against its definition (oracle/u1.py)."""
+import numpy as np
+import pytest
+
+from gpu_util import note
+from oracle import supersite as oss
+from oracle import tebd as otebd
+from oracle import u1 as ou1
+from workloads import CONFIGS, Model, Trunc, cdw_occupations, random_mps, random_mps_u1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pt():
+    import paper_2401_05301_amd as pt
+    return pt
+
+
+def gpu_model(pt, m: Model):
+    return pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre())
+
+
+def bar(om, base=1e-10):
+    return base if om.min_gap >= 1e-8 else max(base, 2 * om.w_total)
+
+
+def check_bonds(g, om, tol):
+    """Sorted spectra, bond dimensions, the library's order and the particle
+    number of every Schmidt value where the oracle's value is isolated."""
+    assert g.bond_dims() == om.bond_dims()
+    q_ref = ou1.bond_charges(om)
+    for b in range(1, om.L):
+        lam_g, q_g = g.lam(b), g.charges(b)
+        assert len(q_g) == len(lam_g)
+        assert np.all(np.diff(q_g) >= 0)
+        for qq in np.unique(q_g):
+            assert np.all(np.diff(lam_g[q_g == qq]) <= 0)
+        og = np.argsort(-lam_g, kind="stable")
+        oo = np.argsort(-om.lam[b], kind="stable")
+        s = om.lam[b][oo]
+        assert np.abs(lam_g[og] - s).max() <= tol, b
+        gap = np.full(len(s), np.inf)
+        if len(s) > 1:
+            dd = np.abs(np.diff(s))
+            gap[:-1] = np.minimum(gap[:-1], dd)
+            gap[1:] = np.minimum(gap[1:], dd)
+        iso = gap > 1e-6
+        assert np.all(np.round(q_ref[b][oo][iso]).astype(np.int64) == q_g[og][iso]), b
+
+
+@pytest.mark.parametrize("svd", [0, 1])
+def test_u1_cdw_matches_dense_oracle(pt, svd):
+    m = Model(L=10, d=3, U=2.7, J=1.0, Jnnn=0.13, K=0.03)
+    tr = Trunc(chi_max=16, w_max=1e-12, eps=1e-12)
+    dt, steps = 0.05, 8
+    note(f"u1 cdw L={m.L} d={m.d} chi={tr.chi_max} svd={svd}")
+    # The Gram route cannot resolve singular values below 1e-6 s_0 and drops
+    # them (as on the dense path): the oracle applies the same floor through
+    # its relative tolerance, so both sides keep the same values.
+    otr = tr if svd == 0 else Trunc(tr.chi_max, tr.w_max, max(tr.eps, 1e-6))
+    ores = otebd.run(m, otr, dt, steps)
+    g = pt.MPS.cdw(gpu_model(pt, m), pt.make_opts(tr.chi_max, tr.w_max, tr.eps, svd=svd, u1=True))
+    # Gram route: eigenvectors of values near the floor carry errors of order
+    # u s_0^2 / (s_i gap), a few 1e-9 in the observables here
+    tol = bar(ores["mps"]) if svd == 0 else bar(ores["mps"], 1e-8)
+    for t in range(steps):
+        g.step(dt)
+        n, C, D = g.measure()
+        assert np.abs(n - ores["n"][t]).max() <= tol
+        assert np.abs(C - ores["C"][t]).max() <= tol
+        assert np.abs(D - ores["D"][t]).max() <= tol
+    check_bonds(g, ores["mps"], tol)
+    assert abs(g.discarded_weight() - ores["w_total"][-1]) <= 1e-12 + 1e-6 * ores["w_total"][-1]
+    g.close()
+
+
+@pytest.mark.parametrize("svd", [0, 1])
+def test_u1_random_state_layers(pt, svd):
+    """One layer of each group on a random right-orthonormal state of N = 6
+    bosons with many sectors per bond; the library infers the particle
+    numbers from the tensors."""
+    L, d, chi, N = 12, 4, 40, 6
+    B, lam, charges = random_mps_u1(L, d, chi, N, seed=2, tau=8.0)
+    m = Model(L=L, d=d, U=3.0, J=1.0, Jnnn=0.1, K=0.01)
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-12)
+    om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12, svd=svd, u1=True), B, lam)
+    for b in range(L + 1):
+        assert np.array_equal(g.charges(b), charges[b])
+    gates = otebd.GateCache(m)
+    for group, tau in [(0, 0.03), (1, 0.03), (2, 0.06)]:
+        note(f"u1 random layer group={group} svd={svd}")
+        otebd.apply_layer(om, gates, group, tau, tr)
+        g.layer(group, tau)
+        n, C, D = g.measure()
+        on, oC, oD = otebd.measure(om)
+        tol = bar(om) if svd == 0 else 1e-7
+        assert np.abs(n - on).max() < tol
+        assert np.abs(C - oC).max() < tol
+        assert np.abs(D - oD).max() < tol
+    if svd == 0:
+        check_bonds(g, om, bar(om))
+        assert abs(g.discarded_weight() - om.w_total) < 1e-12 + 1e-8 * om.w_total
+    g.close()
+
+
+def test_u1_supersite(pt):
+    L, d, chi, steps, dt = 12, 3, 20, 6, 0.02
+    m = Model(L=L, d=d, U=3.0, J=1.0, Jnnn=0.1, K=0.01)
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-12)
+    occ = cdw_occupations(L, 1)
+    note(f"u1 super-site L={L} chi={chi}")
+    ores = oss.run2(m, tr, dt, steps, occ)
+    g = pt.MPS.product(gpu_model(pt, m), pt.make_opts(chi, tr.w_max, tr.eps, supersite=True, u1=True), occ)
+    for _ in range(steps):
+        g.step(dt)
+    n, C, D = g.measure()
+    tol = bar(ores["mps"])
+    assert np.abs(n - ores["n"][-1]).max() <= tol
+    assert np.abs(C - ores["C"][-1]).max() <= tol
+    assert np.abs(D - ores["D"][-1]).max() <= tol
+    assert g.bond_dims() == ores["mps"].bond_dims()
+    # super-site bond K carries the bosons of physical sites 0..2K-1
+    pref = np.concatenate([[0], np.cumsum(occ)])
+    for K in range(L // 2 + 1):
+        w = g.lam(K) ** 2
+        assert abs(np.dot(w, g.charges(K)) - np.sum(n[:2 * K])) < 1e-9
+    assert g.charges(L // 2)[0] == pref[-1]
+    g.close()
+
+
+def test_u1_config2_shape(pt):
+    cfg = CONFIGS["nnn_L32_d5_chi256"]
+    m, tr, dt = cfg["model"], cfg["trunc"], cfg["dt"]
+    steps = 3
+    note("u1 config2 shape")
+    ores = otebd.run(m, tr, dt, steps)
+    g = pt.MPS.cdw(gpu_model(pt, m), pt.make_opts(tr.chi_max, tr.w_max, tr.eps, u1=True))
+    for t in range(steps):
+        g.step(dt)
+    n, C, D = g.measure()
+    tol = bar(ores["mps"])
+    assert np.abs(n - ores["n"][-1]).max() <= tol
+    assert np.abs(C - ores["C"][-1]).max() <= tol
+    assert np.abs(D - ores["D"][-1]).max() <= tol
+    check_bonds(g, ores["mps"], tol)
+    g.close()
+
+
+def test_u1_rejects_state_without_definite_numbers(pt):
+    L, d, chi = 8, 3, 9
+    B, lam = random_mps(L, d, chi, seed=1)
+    m = Model(L=L, d=d, U=1.0)
+    with pytest.raises(pt.TebdError) as e:
+        pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, u1=True), B, lam)
+    assert e.value.status == pt.TEBD_EINVAL
+    g = pt.MPS.cdw(gpu_model(pt, m), pt.make_opts(chi))
+    with pytest.raises(pt.TebdError) as e:
+        g.charges(0)
+    assert e.value.status == pt.TEBD_ESTATE
+    g.close()

@@ -236,9 +236,9 @@ def random_mps_u1(L: int, d: int, chi: int, N: int, seed: int = 0, tau: float = 
             if bias is not None:
                 g *= np.array([np.exp(-rank_r[b] / bias) for _, b in cols])[:, None]
             qf, _ = np.linalg.qr(g)
-            blk = qf.conj().T
-            for t, (s, b) in enumerate(cols):
-                T[rows, s, b] = blk[:, t]
+            s_idx = np.array([c[0] for c in cols])
+            b_idx = np.array([c[1] for c in cols])
+            T[rows[:, None], s_idx[None, :], b_idx[None, :]] = qf.conj().T
         B.append(T)
     lam = []
     for b in range(L + 1):
