@@ -195,6 +195,7 @@ def main():
         log(f"warmup step {w + 1}/{args.warmup} done")
 
     w0 = g.discarded_weight()
+    sweeps0 = pt.mps_sweep_stats(g.h)[1]
     g.profile(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -212,6 +213,7 @@ def main():
     prof = g.profile_read()
     g.profile(False)
     w1 = g.discarded_weight()
+    sweeps1 = pt.mps_sweep_stats(g.h)[1]
     chis = g.bond_dims()
 
     secs = dev_ms / 1e3
@@ -254,6 +256,7 @@ def main():
         "kernel_ms": {k: v[0] for k, v in prof.items()},
         "dominant_kernel_class": dom[0],
         "discarded_weight_per_step": (w1 - w0) / args.steps,
+        "jacobi_sweeps_per_gate_update": (sweeps1 - sweeps0) / (nsteps_gu * args.steps),
         "max_bond": max(chis),
     }
     g.close()

@@ -932,9 +932,10 @@ struct BatchItem {
 
 // Two-sided block Jacobi on every matrix of the batch at once: each round
 // launches the pair solves and the rotations of all matrices still above
-// their own threshold (c u trace of that matrix), so small matrices share
-// the device instead of running their latency-bound rounds one after the
-// other.  Convergence is counted per matrix before every sweep.
+// the threshold (c u times the summed trace of the batch), so small
+// matrices share the device instead of running their latency-bound rounds
+// one after the other.  Convergence is counted per matrix before every
+// sweep.
 void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
   hipStream_t s = M->stream;
   const int count = (int)items.size();
@@ -981,6 +982,12 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
     set_identity(it.wr, it.wi, it.n, it.n, s);
   }
   if (qoff > M->part_cap || foff > M->flags_cap) throw Error(-1, "U(1) SVD: batched Jacobi scratch too small");
+  // The sector Gram matrices are diagonal blocks of one Gram matrix, whose
+  // entries all carry absolute errors of order u times its trace: every
+  // sector takes the threshold of the whole (the sum of the sector
+  // thresholds), the target the dense route uses, instead of chasing
+  // rounding noise below it in the small sectors.
+  share_sum(d_tol, count, s);
   PTEBD_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(HermArgs) * count, hipMemcpyHostToDevice, s));
   PTEBD_HIP(hipMemcpyAsync(d_eig, first.data(), sizeof(int64_t) * 2 * (count + 1), hipMemcpyHostToDevice, s));
   std::vector<int>& act = M->h_active;
@@ -998,6 +1005,12 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
     for (int i = 0; i < count; ++i) {
       if (act[i] && cnt[i] == 0) act[i] = 0;
       if (act[i]) rounds = std::max(rounds, tab[i].nb - 1);
+    }
+    if (debug_enabled()) {
+      std::string line;
+      for (int i = 0; i < count; ++i)
+        if (act[i]) line += " " + std::to_string(tab[i].n) + ":" + std::to_string(cnt[i]);
+      std::fprintf(stderr, "[ptebd] batched-jacobi sweep=%d active(n:above)%s\n", sweep, line.c_str());
     }
     if (rounds == 0) {
       M->last_sweeps = sweep;

@@ -532,6 +532,26 @@ void herm_round(HermArgs a, int round, hipStream_t s) {
 
 int64_t herm_apply_groups(const HermArgs& a) { return apply_groups(a); }
 
+namespace {
+// Every entry becomes the sum of all (one work-group, index order).
+__global__ __launch_bounds__(256) void share_sum_kernel(double* v, int n) {
+  __shared__ double total;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += v[i];
+    total = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) v[i] = total;
+}
+}  // namespace
+
+void share_sum(double* v, int n, hipStream_t s) {
+  if (n <= 0) return;
+  share_sum_kernel<<<1, 256, 0, s>>>(v, n);
+  PTEBD_LAUNCH_CHECK();
+}
+
 void herm_round_batched(const HermArgs* tab, const int64_t* eig_first, int64_t eig_total, const int64_t* app_first,
                         int64_t app_total, int count, const int* active, int round, hipStream_t s) {
   {

@@ -64,6 +64,8 @@ struct HermArgs {
   int round;
   int inner_sweeps;                         // sweeps of the 32 x 32 pair solve per visit
 };
+// v[i] = sum_j v[j] for every i < n.
+void share_sum(double* v, int n, hipStream_t s);
 // Work-groups herm_apply uses for one round of a.
 int64_t herm_apply_groups(const HermArgs& a);
 // One round on each of `count` independent matrices (device table tab;
