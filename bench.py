@@ -64,6 +64,25 @@ def cpu_baseline(chi: int, L_ref: int, steps_scale: float):
                        f"to the chi=1024 unit")}
 
 
+def measured_gemm_peak(pt, torch, n: int = 4096):
+    """Square complex FP64 GEMM rate on this device: this library's kernel and
+    torch's complex128 matmul (rocBLAS), n x n x n, 8 n^3 flops each."""
+    fl = 8.0 * n ** 3
+    ours = fl / (pt.tebd_diag_zgemm_time(n, n, n, pt.FP64, 5) / 1e3) / 1e12
+    a = torch.randn(n, n, dtype=torch.complex128, device="cuda")
+    b = torch.randn(n, n, dtype=torch.complex128, device="cuda")
+    torch.matmul(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        torch.matmul(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    lib = fl / (e0.elapsed_time(e1) / 5 / 1e3) / 1e12
+    return {"n": n, "zgemm_kernel_TFLOPs": ours, "rocblas_zgemm_TFLOPs": lib}
+
+
 def measured_traffic():
     """HBM bytes per launch of the FP64 GEMM from the committed rocprofv3
     counter summary, or None when it is missing or the kernel source has
@@ -251,7 +270,11 @@ def main():
                              + ("canonicalised by an identity sweep" if not args.no_canonicalize else "as generated"))},
         "roofline": roof,
         "path_roofline": {"unit_flops": F_GU, "achieved_TFLOPs": F_GU * value / 1e12, "peak": PEAK_FP64,
-                          "frac": F_GU * value / 1e12 / PEAK_FP64},
+                          "frac": F_GU * value / 1e12 / PEAK_FP64,
+                          # with --u1 the sector SVDs do far less than the dense count F_GU: the
+                          # figure is then a dense-equivalent rate, not work done
+                          "dense_equivalent": bool(args.u1)},
+        "measured_square_gemm": measured_gemm_peak(pt, torch),
         "wall_s": wall,
         "kernel_ms": {k: v[0] for k, v in prof.items()},
         "dominant_kernel_class": dom[0],

@@ -92,8 +92,8 @@ int auto_workers(int L, int requested, bool super) {
 
 int subspace_width(int r, int chi_max) {
   const int keep = std::min(chi_max, r);
-  // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 8)
-  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 8;
+  // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 16)
+  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 16;
   const int p = ((keep + std::max(64, keep / den)) + 15) / 16 * 16;
   // below ~1.5 p the whole Gram matrix is cheaper to diagonalise directly
   return (3 * p < 2 * r) ? p : 0;
