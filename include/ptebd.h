@@ -86,7 +86,7 @@ typedef struct {
   double trunc_rel;       /* eps (>= 0) */
   int32_t prec;           /* tebd_precision */
   int32_t svd;            /* tebd_svd */
-  int32_t max_sweeps;     /* Jacobi sweep limit; <= 0 selects the default (40) */
+  int32_t max_sweeps;     /* Jacobi sweep limit; <= 0 selects the default (80) */
   void* stream;           /* hipStream_t to run on; NULL = the library creates one per handle */
   void* (*dev_alloc)(size_t bytes, void* ctx);  /* optional device allocator (e.g. torch caching allocator) */
   void (*dev_free)(void* ptr, void* ctx);

@@ -131,7 +131,7 @@ def make_model(L: int, d: int, U: float, J: float = 1.0, Jnnn: float = 0.0, K: f
 
 
 def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int = FP64, svd: int = SVD_JACOBI,
-              max_sweeps: int = 40, stream: Optional[int] = None, workers: int = 0, supersite: bool = False,
+              max_sweeps: int = 80, stream: Optional[int] = None, workers: int = 0, supersite: bool = False,
               u1: bool = False) -> Opts:
     o = Opts()
     _lib.tebd_opts_default(ctypes.byref(o))

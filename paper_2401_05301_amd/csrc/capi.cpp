@@ -135,7 +135,7 @@ void tebd_opts_default(tebd_opts* o) {
   o->trunc_rel = 1e-12;
   o->prec = TEBD_FP64;
   o->svd = TEBD_SVD_JACOBI;
-  o->max_sweeps = 40;
+  o->max_sweeps = 80;
 }
 
 tebd_status mps_init_product(const tebd_model* model, const tebd_opts* opts, const int32_t* occ, tebd_mps** out) {

@@ -190,11 +190,11 @@ __global__ __launch_bounds__(256) void supersite_local_kernel(const double* cons
 
 // One particle-number sector of diag(rs) A: out(i, j) = rs[r_i / rdiv] A(r_i, c_j)
 // with r_i = rows[i], c_j = cols[j] (trans == 0, out m x n), or its conjugate
-// transpose (trans == 1, out n x m).  Consecutive threads write consecutive
-// output elements.
+// transpose (trans == 1, out n x m); ldo is the leading dimension of out.
+// Consecutive threads write consecutive output elements of a row.
 __global__ void gather_block_kernel(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv,
                                     const int* rows, int m, const int* cols, int n, int trans, double* outr,
-                                    double* outi) {
+                                    double* outi, int64_t ldo) {
   const int64_t tot = (int64_t)m * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = trans ? (int)(e % m) : (int)(e / n);
@@ -202,8 +202,21 @@ __global__ void gather_block_kernel(const double* ar, const double* ai, int64_t 
     const int r = rows[i];
     const int64_t src = (int64_t)r * lda + cols[j];
     const double sc = rs ? rs[r / rdiv] : 1.0;
-    outr[e] = ar[src] * sc;
-    outi[e] = trans ? -ai[src] * sc : ai[src] * sc;
+    const int64_t o = trans ? (int64_t)j * ldo + i : (int64_t)i * ldo + j;
+    outr[o] = ar[src] * sc;
+    outi[o] = trans ? -ai[src] * sc : ai[src] * sc;
+  }
+}
+
+// Row i of Z (r columns) keeps columns [lo[i], hi[i]) and is zero elsewhere.
+__global__ void mask_rows_kernel(double* zr, double* zi, int64_t ldz, int p, int r, const int* lo, const int* hi) {
+  const int64_t tot = (int64_t)p * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / r), c = (int)(e % r);
+    if (c < lo[i] || c >= hi[i]) {
+      zr[(int64_t)i * ldz + c] = 0.0;
+      zi[(int64_t)i * ldz + c] = 0.0;
+    }
   }
 }
 
@@ -574,11 +587,18 @@ void close_op(const double* br, const double* bi, const double* fr, const double
 }
 
 void gather_block(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv, const int* rows, int m,
-                  const int* cols, int n, int trans, double* outr, double* outi, hipStream_t s) {
+                  const int* cols, int n, int trans, double* outr, double* outi, int64_t ldo, hipStream_t s) {
   const int64_t tot = (int64_t)m * n;
   if (tot <= 0) return;
-  gather_block_kernel<<<(int)std::min<int64_t>((tot + 255) / 256, 8192), 256, 0, s>>>(ar, ai, lda, rs, rdiv, rows, m,
-                                                                                      cols, n, trans, outr, outi);
+  gather_block_kernel<<<(int)std::min<int64_t>((tot + 255) / 256, 8192), 256, 0, s>>>(
+      ar, ai, lda, rs, rdiv, rows, m, cols, n, trans, outr, outi, ldo);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void mask_rows(double* zr, double* zi, int64_t ldz, int p, int r, const int* lo, const int* hi, hipStream_t s) {
+  const int64_t tot = (int64_t)p * r;
+  if (tot <= 0) return;
+  mask_rows_kernel<<<(int)std::min<int64_t>((tot + 255) / 256, 8192), 256, 0, s>>>(zr, zi, ldz, p, r, lo, hi);
   PTEBD_LAUNCH_CHECK();
 }
 

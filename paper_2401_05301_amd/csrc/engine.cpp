@@ -28,6 +28,11 @@ constexpr int kNsplitMax = 16;
 constexpr double kGramSigmaFloor = 1e-6;   // Gram route: singular values below this (relative) are noise
 constexpr double kDampRel = 1e-10;         // subspace iteration: power-step scale floor (relative to the top value)
 constexpr double kDiagCoupling = 0.05;     // subspace iteration: largest relative coupling treated as diagonal
+// Jacobi sweep limit when opts.max_sweeps <= 0.  Cyclic Jacobi on a matrix
+// whose leading vectors are spread over many coordinates (raw-basis Gram
+// blocks of a particle-number sector) can spend 30-40 sweeps in its linear
+// phase before the quadratic one.
+constexpr int kDefaultSweeps = 80;
 
 int64_t ipow_cap(int d, int e, int cap) {
   int64_t v = 1;
@@ -75,9 +80,11 @@ size_t Sizes::bytes(int workers, bool u1) const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
   int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
-  w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
-  w += 6 * vec + part + 64 + 5 * sub_p + 8;
-  if (u1) w += 2 * uv + (idx + vec) / 2 + 1 + 2 * vec * (int64_t)(sizeof(RowCopy) / sizeof(double));
+  // the U(1) subspace reserves 256 more rows (the Gram route only; counted always)
+  const int64_t sp = (u1 && sub_p > 0) ? std::min<int64_t>(sub_p + 256, sub_r) : sub_p;
+  w += 2 * (4 * sp * sub_r + 6 * sp * sp);
+  w += 6 * vec + part + 64 + 5 * sp + 8;
+  if (u1) w += 2 * uv + (idx + 4 * vec) / 2 + 1 + 2 * vec * (int64_t)(sizeof(RowCopy) / sizeof(double));
   d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
 }
@@ -187,6 +194,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->psip = zalloc(W, s.psi);
   W->X2 = zalloc(W, s.X2);
   W->G = zalloc(W, s.G);
+  W->g_cap = s.G;
   W->W = zalloc(W, s.W);
   W->V1h = zalloc(W, s.V1h);
   W->ks = dalloc(W, s.vec);
@@ -197,25 +205,28 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->flags = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
   W->flags_cap = s.vec;
   if (s.sub_p > 0 && W->opts.svd == TEBD_SVD_GRAM_EIG) {
-    W->sub_p = (int)s.sub_p;
-    W->sZ = zalloc(W, s.sub_p * s.sub_r);
-    W->sY = zalloc(W, s.sub_p * s.sub_r);
-    W->sZ2 = zalloc(W, s.sub_p * s.sub_r);
-    W->sY2 = zalloc(W, s.sub_p * s.sub_r);
-    W->sH = zalloc(W, s.sub_p * s.sub_p);
-    W->sW = zalloc(W, s.sub_p * s.sub_p);
-    W->nY = zalloc(W, s.sub_p * s.sub_p);
-    W->nZ = zalloc(W, s.sub_p * s.sub_p);
-    W->nY2 = zalloc(W, s.sub_p * s.sub_p);
-    W->nZ2 = zalloc(W, s.sub_p * s.sub_p);
+    // the U(1) subspace gives every particle-number sector a few rows of its own
+    const int64_t sp = W->opts.u1 ? std::min<int64_t>(s.sub_p + 256, s.sub_r) : s.sub_p;
+    W->sub_p = (int)sp;
+    W->sub_r = (int)s.sub_r;
+    W->sZ = zalloc(W, sp * s.sub_r);
+    W->sY = zalloc(W, sp * s.sub_r);
+    W->sZ2 = zalloc(W, sp * s.sub_r);
+    W->sY2 = zalloc(W, sp * s.sub_r);
+    W->sH = zalloc(W, sp * sp);
+    W->sW = zalloc(W, sp * sp);
+    W->nY = zalloc(W, sp * sp);
+    W->nZ = zalloc(W, sp * sp);
+    W->nY2 = zalloc(W, sp * sp);
+    W->nZ2 = zalloc(W, sp * sp);
     W->ns_part = dalloc(W, 256);
     W->ratio_bits = static_cast<unsigned long long*>(dev_alloc(W, sizeof(unsigned long long)));
-    W->pwork = dalloc(W, 5 * s.sub_p + 8);
+    W->pwork = dalloc(W, 5 * sp + 8);
   }
   W->part = dalloc(W, s.part);
   W->part_cap = s.part;
   if (W->opts.u1) {
-    W->u_idx_cap = s.idx + s.vec;
+    W->u_idx_cap = s.idx + 4 * s.vec;
     W->u_idx = static_cast<int*>(dev_alloc(W, sizeof(int) * W->u_idx_cap));
     W->u_tab_cap = 2 * s.vec;
     W->u_tab = static_cast<RowCopy*>(dev_alloc(W, sizeof(RowCopy) * W->u_tab_cap));
@@ -425,6 +436,16 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
   row_norms(xr, xi, ldx, r, c, M->norms, s);
   negligible_norm2(M->norms, r, M->info_d + 6, s);
   a.tiny2 = M->info_d + 6;
+  {
+    // Rows left at the rounding level by the rotations of a rank-deficient
+    // X carry noise of order u |X|_F, and so do their inner products: an
+    // inner product below (64 u |X|_F)^2 counts as converged, whatever the
+    // norms of the two rows (tiny2 = (4 u)^2 |X|_F^2).
+    double t2 = 0.0;
+    PTEBD_HIP(hipMemcpyAsync(&t2, M->info_d + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    a.tol_abs = std::max(a.tol_abs, 256.0 * t2);
+  }
   if (wr) set_identity(wr, wi, ldw, r, s);
   if (const char* dump = std::getenv("PTEBD_DUMP")) {
     // debugging aid: keep the last Jacobi input on disk (r, c, then planar data)
@@ -441,7 +462,7 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
       std::fclose(f);
     }
   }
-  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
+  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : kDefaultSweeps;
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
     PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
     for (int t = 0; t < nb - 1; ++t) jacobi_round(a, t, s);
@@ -516,7 +537,7 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
     herm_tol(hr, ldh, n, herm_tol_units(), M->info_d + 7, s);
   a.tol_abs = M->info_d + 7;
   if (wr) set_identity(wr, wi, ldw, n, s);
-  const int max_sweeps = sweep_cap > 0 ? sweep_cap : (M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40);
+  const int max_sweeps = sweep_cap > 0 ? sweep_cap : (M->opts.max_sweeps > 0 ? M->opts.max_sweeps : kDefaultSweeps);
   if (debug_enabled()) std::fprintf(stderr, "[ptebd] herm-jacobi start n=%d cap=%d\n", n, sweep_cap);
   // Convergence is checked before every sweep by counting the off-diagonal
   // entries above the target, so no sweep runs only to find nothing to do.
@@ -558,7 +579,9 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
 // X = I, with c >= lambda_max(A) (Gershgorin), so that X -> (A / c)^{-1/2}.
 // With in_place the result is copied back into Z's memory (Z may then be a
 // view of leading rows of a larger basis); otherwise Z and T swap.
-void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_place = false) {
+// With soft set, a Newton-Schulz run that does not converge returns false
+// (Z unchanged, the handle left usable) instead of failing the handle.
+bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_place = false, bool soft = false) {
   hipStream_t s = M->stream;
   normalize_rows(Z.re, Z.im, r, p, r, nullptr, s);
   // every product below is a polynomial in the Hermitian A, hence Hermitian:
@@ -619,6 +642,7 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
     std::fprintf(stderr, "[ptebd] lowdin p=%d newton-schulz iterations=%d c=%.3f\n", p, it + 1, hc);
   }
   if (it == 40) {
+    if (soft) return false;
     M->failed = true;
     throw Error(-4, "Newton-Schulz orthonormalisation did not converge (basis of width " + std::to_string(p) + ")");
   }
@@ -636,6 +660,7 @@ void lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
   } else {
     std::swap(Z, T);
   }
+  return true;
 }
 
 // H = Y Z^+ (p x p) for the basis rows Z and their images Y = Z G.
@@ -649,27 +674,178 @@ void rayleigh(tebd_mps* M, int p, int r) {
   zgemm(h, 0, M->stream);
 }
 
+// Independent Hermitian matrices (H n x n in place, eigenvector rows into W,
+// both with leading dimension ld, n when ld is 0) for one batched Jacobi.
+struct BatchItem {
+  double* hr;
+  double* hi;
+  double* wr;
+  double* wi;
+  int n;
+  int64_t ld = 0;
+};
+
+// Two-sided block Jacobi on every matrix of the batch at once: each round
+// launches the pair solves and the rotations of all matrices still above
+// the threshold (c u times the summed trace of the batch), so small
+// matrices share the device instead of running their latency-bound rounds
+// one after the other.  Convergence is counted per matrix before every
+// sweep.  With sweep_cap > 0 at most that many sweeps run and unconverged
+// matrices are returned as they stand (partial diagonalisation).
+void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items, int sweep_cap = 0) {
+  hipStream_t s = M->stream;
+  const int count = (int)items.size();
+  // device layout in u_batch: HermArgs[count], eig_first[count+1], app_first[count+1],
+  // active[count], counts[count], tol[count]
+  const size_t need = sizeof(HermArgs) * count + 2 * sizeof(int64_t) * (count + 1) + 2 * sizeof(int) * count +
+                      sizeof(double) * count + 64;
+  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "U(1) SVD: batched Jacobi tables exceed their buffer");
+  char* base = static_cast<char*>(M->u_batch);
+  HermArgs* d_tab = reinterpret_cast<HermArgs*>(base);
+  int64_t* d_eig = reinterpret_cast<int64_t*>(d_tab + count);
+  int64_t* d_app = d_eig + (count + 1);
+  int* d_active = reinterpret_cast<int*>(d_app + (count + 1));
+  unsigned int* d_counts = reinterpret_cast<unsigned int*>(d_active + count);
+  double* d_tol = reinterpret_cast<double*>(reinterpret_cast<char*>(d_counts + count) +
+                                            ((8 - (reinterpret_cast<uintptr_t>(d_counts + count) & 7)) & 7));
+  std::vector<HermArgs>& tab = M->h_herm;
+  tab.assign(count, HermArgs{});
+  std::vector<int64_t>& first = M->h_first;
+  first.assign(2 * (count + 1), 0);
+  int64_t qoff = 0, foff = 0;
+  int max_n = 0;
+  for (int i = 0; i < count; ++i) {
+    const BatchItem& it = items[i];
+    HermArgs& a = tab[i];
+    int nb = (it.n + 15) / 16;
+    if (nb < 2) nb = 2;
+    if (nb & 1) ++nb;
+    const int64_t ld = it.ld > 0 ? it.ld : it.n;
+    a.hr = it.hr; a.hi = it.hi; a.ldh = ld; a.n = it.n; a.nb = nb;
+    a.wr = it.wr; a.wi = it.wi; a.ldw = ld;
+    a.wcols = 128;
+    a.wchunks = (it.n + a.wcols - 1) / a.wcols;
+    a.qbuf = M->part + qoff;
+    a.flag = M->flags + foff;
+    a.rotated = M->counter;
+    a.tol_abs = d_tol + i;
+    a.inner_sweeps = inner_sweeps();
+    qoff += (int64_t)(nb / 2) * 2 * 32 * 32;
+    foff += nb / 2;
+    first[i + 1] = first[i] + nb / 2;
+    first[count + 1 + i + 1] = first[count + 1 + i] + herm_apply_groups(a);
+    max_n = std::max(max_n, it.n);
+    herm_tol(it.hr, ld, it.n, herm_tol_units(), d_tol + i, s);
+    set_identity(it.wr, it.wi, ld, it.n, s);
+  }
+  if (qoff > M->part_cap || foff > M->flags_cap) throw Error(-1, "U(1) SVD: batched Jacobi scratch too small");
+  // The sector Gram matrices are diagonal blocks of one Gram matrix, whose
+  // entries all carry absolute errors of order u times its trace: every
+  // sector takes the threshold of the whole (the sum of the sector
+  // thresholds), the target the dense route uses, instead of chasing
+  // rounding noise below it in the small sectors.
+  share_sum(d_tol, count, s);
+  PTEBD_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(HermArgs) * count, hipMemcpyHostToDevice, s));
+  PTEBD_HIP(hipMemcpyAsync(d_eig, first.data(), sizeof(int64_t) * 2 * (count + 1), hipMemcpyHostToDevice, s));
+  std::vector<int>& act = M->h_active;
+  act.assign(count, 1);
+  std::vector<unsigned int>& cnt = M->h_counts;
+  cnt.assign(count, 0);
+  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : kDefaultSweeps;
+  PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+  for (int sweep = 0;; ++sweep) {
+    PTEBD_HIP(hipMemsetAsync(d_counts, 0, sizeof(unsigned int) * count, s));
+    count_above_batched(d_tab, count, d_active, max_n, d_counts, s);
+    PTEBD_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    int rounds = 0;
+    for (int i = 0; i < count; ++i) {
+      if (act[i] && cnt[i] == 0) act[i] = 0;
+      if (act[i]) rounds = std::max(rounds, tab[i].nb - 1);
+    }
+    if (debug_enabled()) {
+      std::string line;
+      for (int i = 0; i < count; ++i)
+        if (act[i]) line += " " + std::to_string(tab[i].n) + ":" + std::to_string(cnt[i]);
+      std::fprintf(stderr, "[ptebd] batched-jacobi sweep=%d active(n:above)%s\n", sweep, line.c_str());
+    }
+    if (rounds == 0) {
+      M->last_sweeps = sweep;
+      M->total_sweeps += sweep;
+      return;
+    }
+    if (sweep_cap > 0 && sweep == sweep_cap) {
+      M->last_sweeps = sweep;
+      M->total_sweeps += sweep;
+      return;
+    }
+    if (sweep == max_sweeps) {
+      M->failed = true;
+      throw Error(-4, "batched Hermitian Jacobi did not converge within max_sweeps (" + std::to_string(count) +
+                          " sectors)");
+    }
+    PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    for (int t = 0; t < rounds; ++t)
+      herm_round_batched(d_tab, d_eig, first[count], d_app, first[2 * (count + 1) - 1], count,
+                         d_active, t, s);
+  }
+}
+
 // Top-p eigenpairs of the Hermitian PSD G (r x r) by subspace iteration with
 // Rayleigh-Ritz.  On return sZ holds the Ritz vectors as rows (conjugated,
 // as W in run_herm_jacobi), M->norms the Ritz values, and info_d[5] the
 // weight of G outside the subspace (trace minus the Ritz values).
-void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w) {
+//
+// With blocks given, G is block diagonal (particle-number sectors) and the
+// caller has filled the p starting rows of sZ, orthonormal, each supported on
+// the columns of one sector, grouped by sector; blocks lists the diagonal blocks of the
+// p x p Rayleigh matrix (one per sector, leading dimension p).  Every GEMM
+// and Newton-Schulz product then keeps the rows inside their sectors, and
+// the Jacobi steps run batched on the diagonal blocks only.
+// Returns false when an orthonormalisation does not converge (a start
+// that is nearly dependent on the null space of a rank-deficient G); the
+// caller then solves G directly.
+bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w,
+                   const std::vector<BatchItem>* blocks = nullptr) {
   hipStream_t s = M->stream;
-  fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
-  fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
+  if (!blocks) {
+    fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
+    fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
+  }
+  // eigenpairs of the Rayleigh matrix (partially with a sweep cap)
+  auto rr_jacobi = [&](int cap) {
+    if (!blocks) {
+      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, cap);
+      return;
+    }
+    fill_zero(M->sW.re, (int64_t)p * p, s);
+    fill_zero(M->sW.im, (int64_t)p * p, s);
+    std::vector<BatchItem> big;
+    for (const BatchItem& b : *blocks) {
+      if (b.n > 1)
+        big.push_back(b);
+      else
+        set_identity(b.wr, b.wi, b.ld, 1, s);
+    }
+    if (!big.empty()) run_herm_jacobi_batched(M, big, cap);
+  };
   int kw = 0;   // warm rows at the top of the basis
-  if (w.kind == 1 && w.src_cols <= p && w.src_rows == r) {
+  if (blocks) {
+    // rows prepared by the caller
+  } else if (w.kind == 1 && w.src_cols <= p && w.src_rows == r) {
     conj_transpose_scaled(w.sr, w.si, w.ld, w.rs, w.rdiv, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
     kw = w.src_cols;
   } else if (w.kind == 2 && w.src_rows <= p && w.src_cols == r) {
     scale_rows_copy(w.sr, w.si, w.ld, nullptr, 1, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
     kw = w.src_rows;
   }
-  if (kw > 0 && kw < p) {
+  if (blocks) {
+    // orthonormal already
+  } else if (kw > 0 && kw < p) {
     // Orthonormalise the warm rows on their own and take the random rows
     // out of their span, so that the basis keeps the warm rows as they are
     // (a joint symmetric orthonormalisation would mix them with noise).
-    lowdin(M, M->sZ, M->sZ2, kw, r, true);
+    if (!lowdin(M, M->sZ, M->sZ2, kw, r, true, true)) return false;
     tebd_mps::Z rnd{M->sZ.re + (size_t)kw * r, M->sZ.im + (size_t)kw * r};
     ZGemmArgs c;   // C = R Zw^+  ((p - kw) x kw)
     c.m = p - kw; c.n = kw; c.k = r;
@@ -684,10 +860,10 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     u.cr = rnd.re; u.ci = rnd.im; u.ldc = r;
     u.alpha = -1.0; u.beta = 1;
     zgemm(u, 0, s);
-    lowdin(M, rnd, M->sZ2, p - kw, r, true);
+    if (!lowdin(M, rnd, M->sZ2, p - kw, r, true, true)) return false;
   } else {
-    lowdin(M, M->sZ, M->sZ2, p, r);
-    lowdin(M, M->sZ, M->sZ2, p, r);
+    if (!lowdin(M, M->sZ, M->sZ2, p, r, false, true)) return false;
+    if (!lowdin(M, M->sZ, M->sZ2, p, r, false, true)) return false;
   }
   // trace of G: scale of the rounding noise in the Ritz values
   tail_rest(gr, r, r, M->norms, 0, M->info_d + 4, s);
@@ -756,13 +932,20 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     // outside (or less than the rounding level of G) and no kept value moved
     // by more than 1e-10 of the largest.
     const double gain = kept - prev_kept;
-    const bool done = (it >= 1 && gain <= std::max(1e-4 * (trace - kept), 64 * u * trace) &&
-                       delta <= 1e-10 * h_vals[0]) ||
+    const bool stable = delta <= 1e-10 * h_vals[0];
+    const bool done = (it >= 1 && gain <= std::max(1e-4 * (trace - kept), 64 * u * trace) && stable) ||
                       it == max_it - 1;
+    if (it == max_it - 1 && !stable) {
+      // kept values still moving at the last iteration: the subspace has
+      // not found the leading eigenvectors (a start nearly inside the null
+      // space of a rank-deficient G); the caller solves G directly
+      if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d: not converged\n", r, p);
+      return false;
+    }
     prev_kept = kept;
     if (done) {
       // final Rayleigh-Ritz: exact eigenvectors of H
-      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p);
+      rr_jacobi(0);
       herm_diag(M->sH.re, p, p, M->norms, s);
       rotate(M->sW, 0, p, false);
       if (debug_enabled())
@@ -780,9 +963,15 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     herm_tol(M->sH.re, p, p, herm_tol_units(), M->info_d + 7, s);
     const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, kDampRel * h_vals[0], M->ratio_bits,
                                        M->h_ratio, s);
+    if (!(ratio <= 1.5)) {
+      // |H_ij| <= sqrt(H_ii H_jj) holds for the positive semi-definite
+      // Z G Z^+: a larger coupling means the basis has lost its accuracy
+      if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d: Rayleigh matrix not PSD (%.2e)\n", r, p, ratio);
+      return false;
+    }
     const bool jac = !(ratio <= kDiagCoupling);
     if (jac) {
-      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, partial_sweeps());
+      rr_jacobi(partial_sweeps());
       herm_diag(M->sH.re, p, p, M->norms, s);
       rotate(M->sW, 0, p, true);
     }
@@ -806,9 +995,13 @@ void subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     damped_power_rows(M->sZ.re, M->sZ.im, M->sY.re, M->sY.im, r, p, r, M->norms, 1.0, kDampRel,
                       kGramSigmaFloor * kGramSigmaFloor, s);
     std::swap(M->sZ, M->sY);
-    lowdin(M, M->sZ, M->sZ2, p, r);
+    if (!lowdin(M, M->sZ, M->sZ2, p, r, false, true)) {
+      if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d: orthonormalisation failed\n", r, p);
+      return false;
+    }
   }
   tail_rest(gr, r, r, M->norms, p, M->info_d + 5, s);
+  return true;
 }
 
 // Relative orthogonality target of the one-sided Jacobi for rows of length c:
@@ -852,8 +1045,17 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   }
   // Gram route: G = A_s A_s^+ (m <= n) or A_s^+ A_s (m > n), r x r
   const double eps_g = std::max(eps, kGramSigmaFloor);
-  const int r = std::min(m, n);
-  const bool left = in.prefer_right ? (m < n) : (m <= n);
+  // The smaller Gram matrix, except that the right one is kept where the
+  // warm start lives on that side and the subspace iteration will run on
+  // it, unless it is clearly the larger one (and while it fits the Gram
+  // workspace).
+  bool left = in.prefer_right ? (m < n) : (m <= n);
+  if (in.prefer_right && left && 5 * (int64_t)m >= 4 * (int64_t)n && M->sub_p > 0 &&
+      (int64_t)n * n <= M->g_cap) {
+    const int pr = subspace_width(n, M->chi_max);
+    if (pr > 0 && pr <= M->sub_p && n <= M->sub_r) left = false;
+  }
+  const int r = left ? m : n;
   if (left) {
     ZGemmArgs g;
     g.m = m; g.n = m; g.k = n;
@@ -884,9 +1086,9 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   const double* rows_i;
   int nvals;
   const double* extra = nullptr;
-  const int p = M->sub_p > 0 ? subspace_width(r, M->chi_max) : 0;
-  if (p > 0 && p <= M->sub_p) {
-    subspace_topk(M, M->G.re, M->G.im, r, p, std::min(M->chi_max, r), in.warm);
+  static const bool no_sub = std::getenv("PTEBD_NO_SUBSPACE") != nullptr;   // debugging aid
+  const int p = (M->sub_p > 0 && !no_sub) ? subspace_width(r, M->chi_max) : 0;
+  if (p > 0 && p <= M->sub_p && subspace_topk(M, M->G.re, M->G.im, r, p, std::min(M->chi_max, r), in.warm)) {
     rows_r = M->sZ.re;
     rows_i = M->sZ.im;
     nvals = p;
@@ -920,115 +1122,6 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   return k;
 }
 
-// Independent Hermitian matrices (H n x n in place, eigenvector rows into W,
-// both with leading dimension n) for one batched Jacobi.
-struct BatchItem {
-  double* hr;
-  double* hi;
-  double* wr;
-  double* wi;
-  int n;
-};
-
-// Two-sided block Jacobi on every matrix of the batch at once: each round
-// launches the pair solves and the rotations of all matrices still above
-// the threshold (c u times the summed trace of the batch), so small
-// matrices share the device instead of running their latency-bound rounds
-// one after the other.  Convergence is counted per matrix before every
-// sweep.
-void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
-  hipStream_t s = M->stream;
-  const int count = (int)items.size();
-  // device layout in u_batch: HermArgs[count], eig_first[count+1], app_first[count+1],
-  // active[count], counts[count], tol[count]
-  const size_t need = sizeof(HermArgs) * count + 2 * sizeof(int64_t) * (count + 1) + 2 * sizeof(int) * count +
-                      sizeof(double) * count + 64;
-  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "U(1) SVD: batched Jacobi tables exceed their buffer");
-  char* base = static_cast<char*>(M->u_batch);
-  HermArgs* d_tab = reinterpret_cast<HermArgs*>(base);
-  int64_t* d_eig = reinterpret_cast<int64_t*>(d_tab + count);
-  int64_t* d_app = d_eig + (count + 1);
-  int* d_active = reinterpret_cast<int*>(d_app + (count + 1));
-  unsigned int* d_counts = reinterpret_cast<unsigned int*>(d_active + count);
-  double* d_tol = reinterpret_cast<double*>(reinterpret_cast<char*>(d_counts + count) +
-                                            ((8 - (reinterpret_cast<uintptr_t>(d_counts + count) & 7)) & 7));
-  std::vector<HermArgs>& tab = M->h_herm;
-  tab.assign(count, HermArgs{});
-  std::vector<int64_t>& first = M->h_first;
-  first.assign(2 * (count + 1), 0);
-  int64_t qoff = 0, foff = 0;
-  int max_n = 0;
-  for (int i = 0; i < count; ++i) {
-    const BatchItem& it = items[i];
-    HermArgs& a = tab[i];
-    int nb = (it.n + 15) / 16;
-    if (nb < 2) nb = 2;
-    if (nb & 1) ++nb;
-    a.hr = it.hr; a.hi = it.hi; a.ldh = it.n; a.n = it.n; a.nb = nb;
-    a.wr = it.wr; a.wi = it.wi; a.ldw = it.n;
-    a.wcols = 128;
-    a.wchunks = (it.n + a.wcols - 1) / a.wcols;
-    a.qbuf = M->part + qoff;
-    a.flag = M->flags + foff;
-    a.rotated = M->counter;
-    a.tol_abs = d_tol + i;
-    a.inner_sweeps = inner_sweeps();
-    qoff += (int64_t)(nb / 2) * 2 * 32 * 32;
-    foff += nb / 2;
-    first[i + 1] = first[i] + nb / 2;
-    first[count + 1 + i + 1] = first[count + 1 + i] + herm_apply_groups(a);
-    max_n = std::max(max_n, it.n);
-    herm_tol(it.hr, it.n, it.n, herm_tol_units(), d_tol + i, s);
-    set_identity(it.wr, it.wi, it.n, it.n, s);
-  }
-  if (qoff > M->part_cap || foff > M->flags_cap) throw Error(-1, "U(1) SVD: batched Jacobi scratch too small");
-  // The sector Gram matrices are diagonal blocks of one Gram matrix, whose
-  // entries all carry absolute errors of order u times its trace: every
-  // sector takes the threshold of the whole (the sum of the sector
-  // thresholds), the target the dense route uses, instead of chasing
-  // rounding noise below it in the small sectors.
-  share_sum(d_tol, count, s);
-  PTEBD_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(HermArgs) * count, hipMemcpyHostToDevice, s));
-  PTEBD_HIP(hipMemcpyAsync(d_eig, first.data(), sizeof(int64_t) * 2 * (count + 1), hipMemcpyHostToDevice, s));
-  std::vector<int>& act = M->h_active;
-  act.assign(count, 1);
-  std::vector<unsigned int>& cnt = M->h_counts;
-  cnt.assign(count, 0);
-  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : 40;
-  PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-  for (int sweep = 0;; ++sweep) {
-    PTEBD_HIP(hipMemsetAsync(d_counts, 0, sizeof(unsigned int) * count, s));
-    count_above_batched(d_tab, count, d_active, max_n, d_counts, s);
-    PTEBD_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    int rounds = 0;
-    for (int i = 0; i < count; ++i) {
-      if (act[i] && cnt[i] == 0) act[i] = 0;
-      if (act[i]) rounds = std::max(rounds, tab[i].nb - 1);
-    }
-    if (debug_enabled()) {
-      std::string line;
-      for (int i = 0; i < count; ++i)
-        if (act[i]) line += " " + std::to_string(tab[i].n) + ":" + std::to_string(cnt[i]);
-      std::fprintf(stderr, "[ptebd] batched-jacobi sweep=%d active(n:above)%s\n", sweep, line.c_str());
-    }
-    if (rounds == 0) {
-      M->last_sweeps = sweep;
-      M->total_sweeps += sweep;
-      return;
-    }
-    if (sweep == max_sweeps) {
-      M->failed = true;
-      throw Error(-4, "batched Hermitian Jacobi did not converge within max_sweeps (" + std::to_string(count) +
-                          " sectors)");
-    }
-    PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-    for (int t = 0; t < rounds; ++t)
-      herm_round_batched(d_tab, d_eig, first[count], d_app, first[2 * (count + 1) - 1], count,
-                         d_active, t, s);
-  }
-}
-
 // U(1) block-sparse truncated SVD (Sec. II B: the tensors are kept in
 // particle-number sectors).  With the rows and columns of A grouped by their
 // particle number, diag(rs) A is block diagonal, so its singular triplets are
@@ -1057,6 +1150,13 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     int64_t goff = 0;        // r x r Gram / eigenvector rows / rotations in G and W
     int u0 = 0;              // first value of the sector in the union
     int64_t ro = 0, co = 0;  // row and column lists in u_idx
+    std::vector<int> warm;   // warm-start bond indices of this number (subspace path)
+    int p = 0, z0 = 0;       // subspace rows of the sector and the first of them
+    bool full = false;       // the subspace is the whole sector (identity rows)
+    int v0 = 0, vn = 0;      // the sector's values in the selection: [v0, v0 + vn)
+    const double* vbr = nullptr;   // eigenvector (Ritz) row loc at vbr + loc * vld
+    const double* vbi = nullptr;
+    int64_t vld = 0;
     std::vector<int> kept;   // ranks (by decreasing value) of the kept values
     int64_t xoff = 0, yoff = 0;
   };
@@ -1067,7 +1167,6 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     if (it != by_q.end()) it->second.cols.push_back(c);
   }
   std::vector<Sector*> secs;
-  std::vector<BatchItem> batch;
   int64_t off = 0, goff = 0, io = 0;
   int nvals = 0;
   M->h_idx.clear();
@@ -1094,8 +1193,82 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     secs.push_back(&S);
   }
   if (secs.empty()) throw Error(-1, "U(1) SVD: no particle-number sector has both rows and columns");
+  // Subspace path of the Gram route: with the bond's previous particle
+  // numbers at hand, each sector gets p_Q rows, its warm rows (the previous
+  // Schmidt vectors of that number) plus a few random ones, and the whole
+  // block-diagonal Gram matrix goes through one subspace iteration.
+  const WarmStart& w = in.warm;
+  int P = 0;
+  bool sub = false;
+  int64_t wo = io;   // warm index lists follow the sector lists in u_idx
+  if (gram && w.q && (w.kind == 1 || w.kind == 2) && M->sub_p > 0) {
+    const std::vector<int>& wq = *w.q;
+    for (Sector* S : secs) {
+      S->warm.clear();
+      // warm rows exist on the side the previous Schmidt vectors live on; a
+      // sector whose Gram matrix lies on the other side is solved whole
+      const bool match = (w.kind == 1) == S->left;
+      if (match)
+        for (int x = 0; x < (int)wq.size(); ++x)
+          if (wq[x] == S->q) S->warm.push_back(x);
+      // A few random rows join the warm ones.  They must leave at least as
+      // much room in the sector again (random rows filling most of the
+      // complement of the warm rows would be ill-conditioned); otherwise the
+      // sector is taken whole, with identity rows.
+      const int kw = (int)S->warm.size();
+      const int extra = std::max(4, kw / 16);
+      S->full = !(match && kw + 2 * extra <= S->r);
+      if (S->full) {
+        S->p = S->r;
+        S->warm.clear();
+      } else {
+        S->p = kw + extra;
+      }
+      S->z0 = P;
+      P += S->p;
+    }
+    static const double frac =
+        std::getenv("PTEBD_U1_SUBSPACE_FRAC") ? std::atof(std::getenv("PTEBD_U1_SUBSPACE_FRAC")) : 0.667;
+    sub = P <= M->sub_p && nvals <= M->sub_r && (double)P < frac * nvals;
+  }
+  if (debug_enabled() && gram)
+    std::fprintf(stderr, "[ptebd] U(1) gram m=%d n=%d sectors=%zu union=%d warm=%d P=%d sub_p=%d sub_r=%d -> %s\n", m,
+                 n, secs.size(), nvals, w.q ? (int)w.q->size() : -1, P, M->sub_p, M->sub_r,
+                 sub ? "subspace" : "direct");
+  // The starting rows are built in stages, as on the dense path: the warm
+  // rows of every sector first (rows [0, KW)), then the random rows of every
+  // sector; then they are permuted into sector order (sector Q at rows
+  // [z0, z0 + p)).
+  int KW = 0;
+  for (Sector* S : secs) KW += (int)S->warm.size();
+  int64_t need_idx = io + std::min(m, n);
+  if (sub) {
+    need_idx += KW + 2 * (int64_t)(P - KW) + P;
+    if (need_idx > M->u_idx_cap) sub = false;
+  }
   if (io + std::min(m, n) > M->u_idx_cap) throw Error(-1, "U(1) SVD: sector lists exceed their buffer");
-  PTEBD_HIP(hipMemcpyAsync(M->u_idx, M->h_idx.data(), sizeof(int) * io, hipMemcpyHostToDevice, s));
+  int64_t lo_off = 0, perm_off = 0;
+  if (sub) {
+    for (Sector* S : secs) M->h_idx.insert(M->h_idx.end(), S->warm.begin(), S->warm.end());
+    lo_off = (int64_t)M->h_idx.size();
+    for (Sector* S : secs)
+      for (int t = (int)S->warm.size(); t < S->p; ++t) M->h_idx.push_back(S->u0);
+    for (Sector* S : secs)
+      for (int t = (int)S->warm.size(); t < S->p; ++t) M->h_idx.push_back(S->u0 + S->r);
+    perm_off = (int64_t)M->h_idx.size();
+    int wz = 0, rz = KW;
+    for (Sector* S : secs) {
+      const int kw = (int)S->warm.size();
+      for (int t = 0; t < kw; ++t) M->h_idx.push_back(wz + t);
+      for (int t = kw; t < S->p; ++t) M->h_idx.push_back(rz + (t - kw));
+      wz += kw;
+      rz += S->p - kw;
+    }
+  }
+  PTEBD_HIP(hipMemcpyAsync(M->u_idx, M->h_idx.data(), sizeof(int) * M->h_idx.size(), hipMemcpyHostToDevice, s));
+  const int64_t idx_end = (int64_t)M->h_idx.size();
+  // gather every sector block (Gram: as it stands; Jacobi: rows, or the
+  // conjugate transpose for a tall block) and decompose it
   for (Sector* S : secs) {
     const int* rows = M->u_idx + S->ro;
     const int* cols = M->u_idx + S->co;
@@ -1106,21 +1279,31 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     if (!gram) {
       if (S->left) {
         // rows of the block become sigma_i v_i^+
-        gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, s);
+        gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, S->n, s);
         if (S->m > 1) run_jacobi(M, br, bi, S->n, nullptr, nullptr, 0, S->m, S->n, jacobi_tol(S->n), 0.0);
       } else {
         // rows of the conjugate transpose (n x m) become sigma_i u_i^+; the
         // accumulated rotations are the rows v_i^+
-        gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 1, br, bi, s);
+        gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 1, br, bi, S->m, s);
         if (S->n > 1)
           run_jacobi(M, br, bi, S->m, wr, wi, S->n, S->n, S->m, jacobi_tol(S->m), 0.0);
         else
           set_identity(wr, wi, 1, 1, s);
       }
     } else {
-      gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, s);
-      double* gr = M->G.re + S->goff;
-      double* gi = M->G.im + S->goff;
+      gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, S->n, s);
+    }
+  }
+  // The Gram matrix of every sector: packed r x r blocks (direct path), or
+  // the diagonal blocks of one nvals x nvals matrix (subspace path).
+  auto sector_grams = [&](bool dense_layout) {
+    if (dense_layout) {
+      fill_zero(M->G.re, (int64_t)nvals * nvals, s);
+      fill_zero(M->G.im, (int64_t)nvals * nvals, s);
+    }
+    for (Sector* S : secs) {
+      const double* br = xbuf.re + S->off;
+      const double* bi = xbuf.im + S->off;
       ZGemmArgs g;
       if (S->left) {   // B B^+ (m x m)
         g.m = S->m; g.n = S->m; g.k = S->n;
@@ -1131,45 +1314,163 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
         g.ar = br; g.ai = bi; g.lda = S->n; g.transA = 1;
         g.br = br; g.bi = bi; g.ldb = S->n;
       }
-      g.cr = gr; g.ci = gi; g.ldc = S->r;
+      if (dense_layout) {
+        g.cr = M->G.re + (int64_t)S->u0 * nvals + S->u0; g.ci = M->G.im + (int64_t)S->u0 * nvals + S->u0;
+        g.ldc = nvals;
+      } else {
+        g.cr = M->G.re + S->goff; g.ci = M->G.im + S->goff; g.ldc = S->r;
+      }
       g.herm_out = 1;
       zgemm(g, 0, s);
-      if (S->r > 1)
-        batch.push_back(BatchItem{gr, gi, wr, wi, S->r});
-      else
-        set_identity(wr, wi, 1, 1, s);
     }
-  }
-  // all sector eigenproblems of the Gram route in one batched Jacobi
-  if (!batch.empty()) run_herm_jacobi_batched(M, batch);
-  // the union of the sector spectra (after every Jacobi run, which uses
-  // M->norms as its own scratch)
-  for (Sector* S : secs) {
-    double* out = M->norms + S->u0;
-    if (!gram) {
-      if (S->left)
-        row_norms(xbuf.re + S->off, xbuf.im + S->off, S->n, S->m, S->n, out, s);
-      else
-        row_norms(xbuf.re + S->off, xbuf.im + S->off, S->m, S->n, S->m, out, s);
-    } else {
-      herm_diag(M->G.re + S->goff, S->r, S->r, out, s);
+  };
+  auto read_kept = [&]() {
+    PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    const int k = M->h_info[0];
+    M->h_perm.resize(k);
+    PTEBD_HIP(hipMemcpyAsync(M->h_perm.data(), M->perm, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    std::vector<int> v0s;
+    for (Sector* S : secs) {
+      v0s.push_back(S->v0);
+      S->kept.clear();
     }
+    for (int i = 0; i < k; ++i) {
+      const int v = M->h_perm[i];
+      const int si = (int)(std::upper_bound(v0s.begin(), v0s.end(), v) - v0s.begin()) - 1;
+      if (si < 0 || v >= secs[si]->v0 + secs[si]->vn) throw Error(-3, "U(1) SVD: kept value outside every sector");
+      secs[si]->kept.push_back(i);
+    }
+    return k;
+  };
+  int k = 0;
+  bool done = false;
+  if (sub) {
+    sector_grams(true);
+    // warm rows (zero outside their sector), then random rows masked to
+    // their sector's columns
+    const int nr = P - KW;
+    fill_zero(M->sZ.re, (int64_t)KW * nvals, s);
+    fill_zero(M->sZ.im, (int64_t)KW * nvals, s);
+    tebd_mps::Z rnd{M->sZ.re + (int64_t)KW * nvals, M->sZ.im + (int64_t)KW * nvals};
+    fill_random(rnd.re, (int64_t)nr * nvals, 0x5eed1234abcdull, s);
+    fill_random(rnd.im, (int64_t)nr * nvals, 0x0bad5eedfeedull, s);
+    mask_rows(rnd.re, rnd.im, nvals, nr, nvals, M->u_idx + lo_off, M->u_idx + lo_off + nr, s);
+    std::vector<BatchItem> blocks;
+    int64_t wpos = wo;
+    int wz = 0, rz = 0;
+    for (Sector* S : secs) {
+      const int kw = (int)S->warm.size();
+      double* zr = M->sZ.re + (int64_t)wz * nvals + S->u0;
+      double* zi = M->sZ.im + (int64_t)wz * nvals + S->u0;
+      wz += kw;
+      if (S->full)   // identity rows over the sector's columns
+        set_identity(rnd.re + (int64_t)rz * nvals + S->u0, rnd.im + (int64_t)rz * nvals + S->u0, nvals, S->r, s);
+      rz += S->p - kw;
+      if (kw > 0) {
+        if (w.kind == 1)   // rows conj(Lambda B)^T restricted to the sector's rows of A
+          gather_block(w.sr, w.si, w.ld, w.rs, w.rdiv, M->u_idx + S->ro, S->m, M->u_idx + wpos, kw, 1, zr, zi,
+                       nvals, s);
+        else               // rows of the source restricted to the sector's columns of A
+          gather_block(w.sr, w.si, w.ld, nullptr, 1, M->u_idx + wpos, kw, M->u_idx + S->co, S->n, 0, zr, zi, nvals,
+                       s);
+      }
+      wpos += kw;
+      blocks.push_back(BatchItem{M->sH.re + (int64_t)S->z0 * P + S->z0, M->sH.im + (int64_t)S->z0 * P + S->z0,
+                                 M->sW.re + (int64_t)S->z0 * P + S->z0, M->sW.im + (int64_t)S->z0 * P + S->z0, S->p,
+                                 (int64_t)P});
+    }
+    // Orthonormalise the warm rows on their own, take the random rows out of
+    // their span and orthonormalise those: every product keeps the rows
+    // inside their sectors (the Gram blocks between sectors are zero).
+    bool ortho = KW == 0 || lowdin(M, M->sZ, M->sZ2, KW, nvals, true, true);
+    if (ortho && KW > 0 && nr > 0) {
+      ZGemmArgs c;   // C = R Zw^+  (nr x KW)
+      c.m = nr; c.n = KW; c.k = nvals;
+      c.ar = rnd.re; c.ai = rnd.im; c.lda = nvals;
+      c.br = M->sZ.re; c.bi = M->sZ.im; c.ldb = nvals; c.transB = 1;
+      c.cr = M->sH.re; c.ci = M->sH.im; c.ldc = KW;
+      zgemm(c, 0, s);
+      ZGemmArgs u;   // R <- R - C Zw
+      u.m = nr; u.n = nvals; u.k = KW;
+      u.ar = M->sH.re; u.ai = M->sH.im; u.lda = KW;
+      u.br = M->sZ.re; u.bi = M->sZ.im; u.ldb = nvals;
+      u.cr = rnd.re; u.ci = rnd.im; u.ldc = nvals;
+      u.alpha = -1.0; u.beta = 1;
+      zgemm(u, 0, s);
+    }
+    if (ortho && nr > 0) ortho = lowdin(M, rnd, M->sZ2, nr, nvals, true, true);
+    if (ortho) {   // sector order
+      gather_rows(M->sZ.re, M->sZ.im, nvals, M->u_idx + perm_off, nullptr, P, nvals, M->sZ2.re, M->sZ2.im, nvals,
+                  nullptr, s);
+      std::swap(M->sZ, M->sZ2);
+    }
+    const bool conv =
+        ortho && subspace_topk(M, M->G.re, M->G.im, nvals, P, std::min({M->chi_max, nvals, P}), WarmStart{}, &blocks);
+    // (the iteration swaps its buffers: the Ritz rows are where sZ points now)
+    for (Sector* S : secs) {
+      S->v0 = S->z0;
+      S->vn = S->p;
+      S->vbr = M->sZ.re + (int64_t)S->z0 * nvals + S->u0;
+      S->vbi = M->sZ.im + (int64_t)S->z0 * nvals + S->u0;
+      S->vld = nvals;
+    }
+    if (conv) {
+      // the ledger is charged only once the sectors are known to hold every kept value
+      double* trial = M->info_d + 12;
+      fill_zero(trial, 1, s);
+      select_truncate(M->norms, P, 1, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, trial,
+                      M->info_d + 5, s);
+      k = read_kept();
+      // A sector whose subspace is nearly filled by kept values may miss
+      // values above the cut: fall back to solving every sector in full.
+      done = true;
+      for (Sector* S : secs) {
+        const int guard = std::max(2, (S->p - (int)S->warm.size()) / 2);
+        if (S->p < S->r && (int)S->kept.size() > S->p - guard) done = false;
+      }
+      if (done) accumulate_slots(trial, 1, M->ledger, s);
+    }
+    if (!done && debug_enabled())
+      std::fprintf(stderr, "[ptebd] U(1) subspace %s: solving sectors in full\n", conv ? "too narrow" : "failed");
   }
-  select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
-                  M->ledger, nullptr, s);
-  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
-  PTEBD_HIP(hipStreamSynchronize(s));
-  const int k = M->h_info[0];
-  M->h_perm.resize(k);
-  PTEBD_HIP(hipMemcpyAsync(M->h_perm.data(), M->perm, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-  PTEBD_HIP(hipStreamSynchronize(s));
-  std::vector<int> u0s;
-  for (Sector* S : secs) u0s.push_back(S->u0);
-  for (int i = 0; i < k; ++i) {
-    const int u = M->h_perm[i];
-    const int si = (int)(std::upper_bound(u0s.begin(), u0s.end(), u) - u0s.begin()) - 1;
-    if (si < 0 || u >= secs[si]->u0 + secs[si]->r) throw Error(-3, "U(1) SVD: kept value outside every sector");
-    secs[si]->kept.push_back(i);
+  if (!done) {
+    if (gram) {
+      sector_grams(false);
+      std::vector<BatchItem> items;
+      for (Sector* S : secs) {
+        double* wr = M->W.re + S->goff;
+        double* wi = M->W.im + S->goff;
+        if (S->r > 1)
+          items.push_back(BatchItem{M->G.re + S->goff, M->G.im + S->goff, wr, wi, S->r});
+        else
+          set_identity(wr, wi, 1, 1, s);
+      }
+      // all sector eigenproblems in one batched Jacobi
+      if (!items.empty()) run_herm_jacobi_batched(M, items);
+    }
+    // the union of the sector spectra (after every Jacobi run, which uses
+    // M->norms as its own scratch)
+    for (Sector* S : secs) {
+      double* out = M->norms + S->u0;
+      if (!gram) {
+        if (S->left)
+          row_norms(xbuf.re + S->off, xbuf.im + S->off, S->n, S->m, S->n, out, s);
+        else
+          row_norms(xbuf.re + S->off, xbuf.im + S->off, S->m, S->n, S->m, out, s);
+      } else {
+        herm_diag(M->G.re + S->goff, S->r, S->r, out, s);
+      }
+      S->v0 = S->u0;
+      S->vn = S->r;
+      S->vbr = M->W.re + S->goff;
+      S->vbi = M->W.im + S->goff;
+      S->vld = S->r;
+    }
+    select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
+                    M->ledger, nullptr, s);
+    k = read_kept();
   }
   // output order: by particle number, then by rank
   kept_q.clear();
@@ -1179,12 +1480,13 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       M->h_order.push_back(i);
       kept_q.push_back(S->q);
     }
-  int* d_order = M->u_idx + io;
+  if (idx_end + k > M->u_idx_cap) throw Error(-1, "U(1) SVD: sector lists exceed their buffer");
+  int* d_order = M->u_idx + idx_end;
   PTEBD_HIP(hipMemcpyAsync(d_order, M->h_order.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
   take(lam_out, d_order, k, M->sq, s);
   PTEBD_HIP(hipMemcpyAsync(lam_out, M->sq, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
-  // row-copy table: for the left Gram route the scaled eigenvector rows
-  // S^-1 U^+ of every sector first (into G), then the output rows
+  // row-copy table: for the left Gram blocks the scaled eigenvector rows
+  // S^-1 U^+ of every sector first (into G, free by now), then the output rows
   M->h_tab.clear();
   int nx = 0;
   if (gram) {
@@ -1195,10 +1497,9 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       S->yoff = yo;
       for (size_t t = 0; t < S->kept.size(); ++t) {
         const int i = S->kept[t];
-        const int64_t loc = M->h_perm[i] - S->u0;
-        M->h_tab.push_back(RowCopy{M->W.re + S->goff + loc * S->m, M->W.im + S->goff + loc * S->m,
-                                   M->G.re + xo + (int64_t)t * S->m, M->G.im + xo + (int64_t)t * S->m, nullptr,
-                                   (int64_t)S->m, (int64_t)i});
+        const int64_t loc = M->h_perm[i] - S->v0;
+        M->h_tab.push_back(RowCopy{S->vbr + loc * S->vld, S->vbi + loc * S->vld, M->G.re + xo + (int64_t)t * S->m,
+                                   M->G.im + xo + (int64_t)t * S->m, nullptr, (int64_t)S->m, (int64_t)i});
       }
       xo += (int64_t)S->kept.size() * S->m;
       yo += (int64_t)S->kept.size() * S->n;
@@ -1209,7 +1510,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
   for (Sector* S : secs) {
     for (size_t t = 0; t < S->kept.size(); ++t, ++o) {
       const int i = S->kept[t];
-      const int64_t loc = M->h_perm[i] - S->u0;
+      const int64_t loc = M->h_perm[i] - S->v0;
       const double* sr;
       const double* si;
       int64_t sidx = -1;
@@ -1221,8 +1522,8 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
         sr = M->uv.re + S->yoff + (int64_t)t * S->n;
         si = M->uv.im + S->yoff + (int64_t)t * S->n;
       } else {
-        sr = M->W.re + S->goff + loc * S->n;
-        si = M->W.im + S->goff + loc * S->n;
+        sr = S->vbr + loc * S->vld;
+        si = S->vbi + loc * S->vld;
       }
       M->h_tab.push_back(RowCopy{sr, si, vhr + o * n, vhi + o * n, M->u_idx + S->co, (int64_t)S->n, sidx});
     }
@@ -1325,6 +1626,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   in1.warm.sr = S->Br[j]; in1.warm.si = S->Bi[j]; in1.warm.ld = c1;
   in1.warm.src_rows = m1; in1.warm.src_cols = c1;
   in1.warm.rs = S->lam[j]; in1.warm.rdiv = d;
+  if (S->u1) in1.warm.q = &S->q[j + 1];
   std::vector<int> q1, q2;
   int k1;
   if (S->u1) {
@@ -1359,6 +1661,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   in2.warm.kind = 2;
   in2.warm.sr = S->Br[j + 2]; in2.warm.si = S->Bi[j + 2]; in2.warm.ld = n2;
   in2.warm.src_rows = c2; in2.warm.src_cols = n2;
+  if (S->u1) in2.warm.q = &S->q[j + 2];
   int k2;
   if (S->u1) {
     // rows (a', s2): q1[a'] + s2; columns (s3, b): q_{j+3}[b] - s3
@@ -1423,6 +1726,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
   in.warm.sr = S->Br[K]; in.warm.si = S->Bi[K]; in.warm.ld = cm;
   in.warm.src_rows = m1; in.warm.src_cols = cm;
   in.warm.rs = S->lam[K]; in.warm.rdiv = D;
+  if (S->u1) in.warm.q = &S->q[K + 1];
   // V^+ goes straight to B_{K+1}: psi' no longer needs the old B_{K+1}
   std::vector<int> qk;
   int k;

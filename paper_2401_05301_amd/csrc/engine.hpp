@@ -50,6 +50,8 @@ struct tebd_mps {
   unsigned long long* h_ratio = nullptr;      // pinned host mirror
   double* pwork = nullptr;      // Newton-Schulz scale: row sums and power-iteration vectors (5p + 1)
   int sub_p = 0;                // subspace width reserved (0: not reserved)
+  int sub_r = 0;                // row length reserved for the subspace bases
+  int64_t g_cap = 0;            // entries of the Gram workspaces G and W
   int* flags = nullptr;         // per block pair flags of the Hermitian Jacobi
   Z E, F, F2, F3;
   double* ks = nullptr;
@@ -151,6 +153,8 @@ struct WarmStart {
   int src_rows = 0, src_cols = 0;
   const double* rs = nullptr;
   int rdiv = 1;
+  // particle numbers of the warm rows' bond indices (U(1) SVD), or null
+  const std::vector<int>* q = nullptr;
 };
 
 struct SvdIn {

@@ -172,10 +172,12 @@ void supersite_local(const double* const* br, const double* const* bi, const dou
                      const int* chir, int Ls, int d, double* out, hipStream_t s);
 // Particle-number sectors (U(1) block-sparse SVD).
 // out = the block rows[0..m) x cols[0..n) of diag(rs) A (rs[r / rdiv], may be
-// null): out(i, j) with leading dimension n (trans == 0), or its conjugate
-// transpose out(j, i) with leading dimension m (trans == 1).
+// null): out(i, j) (trans == 0), or its conjugate transpose out(j, i)
+// (trans == 1); ldo is the leading dimension of out.
 void gather_block(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv, const int* rows, int m,
-                  const int* cols, int n, int trans, double* outr, double* outi, hipStream_t s);
+                  const int* cols, int n, int trans, double* outr, double* outi, int64_t ldo, hipStream_t s);
+// Zero every entry of row i of Z (p x r) outside columns [lo[i], hi[i]) (device arrays).
+void mask_rows(double* zr, double* zi, int64_t ldz, int p, int r, const int* lo, const int* hi, hipStream_t s);
 // One row copy: len values from (sr, si) into (dr, di) at positions cols[t]
 // (or t when cols is null), times scale[sidx] when sidx >= 0.
 struct RowCopy {

@@ -242,3 +242,40 @@ def test_supersite_two_site_variant(pt, L, d, chi, steps, svd):
             assert np.abs(g.lam(b) - ores["mps"].lam[b]).max() <= tol, b
         assert abs(g.discarded_weight() - ores["w_total"][-1]) <= 1e-12 + 1e-6 * ores["w_total"][-1]
     g.close()
+
+
+@pytest.mark.parametrize("svd", [0, 1])
+def test_rank_deficient_gram_matrices(pt, svd):
+    """A state with definite particle numbers makes every Gram matrix of the
+    dense route highly rank-deficient (its rank is the sum of the sector
+    ranks).  Identity-gate canonicalisation and two layers against the
+    oracle; the Gram route must not lose weight to a subspace stuck in the
+    null space (it falls back to the direct solve)."""
+    from workloads import random_mps_u1
+    L, d, chi = 12, 5, 96
+    B, lam, _ = random_mps_u1(L, d, chi, L // 2, seed=0, tau=20.0, bias=30.0)
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-12 if svd == 0 else 1e-6)
+    om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    eye = np.eye(d ** 3)
+    for j in range(L - 2):
+        otebd.apply_gate(om, j, eye, tr)
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12, svd=svd), B, lam)
+    g.canonicalize()
+    note(f"rank-deficient svd={svd}: canonical w {om.w_total:.3e} (GPU {g.discarded_weight():.3e})")
+    gates = otebd.GateCache(m)
+    for group, tau in [(0, 0.01), (1, 0.01)]:
+        otebd.apply_layer(om, gates, group, tau, tr)
+        g.layer(group, tau)
+    n, C, D = g.measure()
+    on, oC, oD = otebd.measure(om)
+    tol = bar(ores_like(om), 1e-10 if svd == 0 else 1e-8)
+    assert np.abs(n - on).max() < tol, np.abs(n - on).max()
+    assert np.abs(C - oC).max() < tol
+    assert np.abs(D - oD).max() < tol
+    assert abs(g.discarded_weight() - om.w_total) < 1e-10 + 1e-6 * om.w_total
+    g.close()
+
+
+def ores_like(om):
+    return {"mps": om, "w_total": [om.w_total]}

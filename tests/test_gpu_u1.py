@@ -166,3 +166,29 @@ def test_u1_rejects_state_without_definite_numbers(pt):
         g.charges(0)
     assert e.value.status == pt.TEBD_ESTATE
     g.close()
+
+
+def test_u1_gram_subspace_sectors(pt):
+    """Gram route at a bond cap where each sector is solved by the sector
+    subspace iteration (previous Schmidt vectors of the same particle number
+    plus a few random rows); layers on a random state of N = 8 bosons."""
+    L, d, chi, N = 12, 5, 96, 6
+    B, lam, _ = random_mps_u1(L, d, chi, N, seed=5, tau=20.0, bias=30.0)
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    # the Gram route drops values below 1e-6 s_0: the oracle applies the same floor
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-6)
+    om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12, svd=pt.SVD_GRAM_EIG, u1=True), B, lam)
+    gates = otebd.GateCache(m)
+    for group, tau in [(0, 0.01), (1, 0.01), (2, 0.02), (1, 0.01), (0, 0.01)]:
+        note(f"u1 gram subspace layer group={group}")
+        otebd.apply_layer(om, gates, group, tau, tr)
+        g.layer(group, tau)
+        n, C, D = g.measure()
+        on, oC, oD = otebd.measure(om)
+        tol = bar(om, 1e-8)
+        assert np.abs(n - on).max() < tol, np.abs(n - on).max()
+        assert np.abs(C - oC).max() < tol
+        assert np.abs(D - oD).max() < tol
+    check_bonds(g, om, bar(om, 1e-8))
+    g.close()
