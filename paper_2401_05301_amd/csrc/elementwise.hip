@@ -208,18 +208,6 @@ __global__ void gather_block_kernel(const double* ar, const double* ai, int64_t 
   }
 }
 
-// Row i of Z (r columns) keeps columns [lo[i], hi[i]) and is zero elsewhere.
-__global__ void mask_rows_kernel(double* zr, double* zi, int64_t ldz, int p, int r, const int* lo, const int* hi) {
-  const int64_t tot = (int64_t)p * r;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / r), c = (int)(e % r);
-    if (c < lo[i] || c >= hi[i]) {
-      zr[(int64_t)i * ldz + c] = 0.0;
-      zi[(int64_t)i * ldz + c] = 0.0;
-    }
-  }
-}
-
 // One work-group per entry: copies len values from (sr, si) to (dr, di),
 // to dr[cols[t]] when cols is given, scaled by scale[sidx] when sidx >= 0.
 __global__ __launch_bounds__(256) void rows_copy_kernel(const RowCopy* tab, const double* scale) {
@@ -592,13 +580,6 @@ void gather_block(const double* ar, const double* ai, int64_t lda, const double*
   if (tot <= 0) return;
   gather_block_kernel<<<(int)std::min<int64_t>((tot + 255) / 256, 8192), 256, 0, s>>>(
       ar, ai, lda, rs, rdiv, rows, m, cols, n, trans, outr, outi, ldo);
-  PTEBD_LAUNCH_CHECK();
-}
-
-void mask_rows(double* zr, double* zi, int64_t ldz, int p, int r, const int* lo, const int* hi, hipStream_t s) {
-  const int64_t tot = (int64_t)p * r;
-  if (tot <= 0) return;
-  mask_rows_kernel<<<(int)std::min<int64_t>((tot + 255) / 256, 8192), 256, 0, s>>>(zr, zi, ldz, p, r, lo, hi);
   PTEBD_LAUNCH_CHECK();
 }
 

@@ -80,10 +80,8 @@ size_t Sizes::bytes(int workers, bool u1) const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
   int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
-  // the U(1) subspace reserves 256 more rows (the Gram route only; counted always)
-  const int64_t sp = (u1 && sub_p > 0) ? std::min<int64_t>(sub_p + 256, sub_r) : sub_p;
-  w += 2 * (4 * sp * sub_r + 6 * sp * sp);
-  w += 6 * vec + part + 64 + 5 * sp + 8;
+  w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
+  w += 6 * vec + part + 64 + 5 * sub_p + 8;
   if (u1) w += 2 * uv + (idx + 4 * vec) / 2 + 1 + 2 * vec * (int64_t)(sizeof(RowCopy) / sizeof(double));
   d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
@@ -205,8 +203,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->flags = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
   W->flags_cap = s.vec;
   if (s.sub_p > 0 && W->opts.svd == TEBD_SVD_GRAM_EIG) {
-    // the U(1) subspace gives every particle-number sector a few rows of its own
-    const int64_t sp = W->opts.u1 ? std::min<int64_t>(s.sub_p + 256, s.sub_r) : s.sub_p;
+    const int64_t sp = s.sub_p;
     W->sub_p = (int)sp;
     W->sub_r = (int)s.sub_r;
     W->sZ = zalloc(W, sp * s.sub_r);
@@ -675,14 +672,13 @@ void rayleigh(tebd_mps* M, int p, int r) {
 }
 
 // Independent Hermitian matrices (H n x n in place, eigenvector rows into W,
-// both with leading dimension ld, n when ld is 0) for one batched Jacobi.
+// both with leading dimension n) for one batched Jacobi.
 struct BatchItem {
   double* hr;
   double* hi;
   double* wr;
   double* wi;
   int n;
-  int64_t ld = 0;
 };
 
 // Two-sided block Jacobi on every matrix of the batch at once: each round
@@ -690,9 +686,8 @@ struct BatchItem {
 // the threshold (c u times the summed trace of the batch), so small
 // matrices share the device instead of running their latency-bound rounds
 // one after the other.  Convergence is counted per matrix before every
-// sweep.  With sweep_cap > 0 at most that many sweeps run and unconverged
-// matrices are returned as they stand (partial diagonalisation).
-void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items, int sweep_cap = 0) {
+// sweep.
+void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
   hipStream_t s = M->stream;
   const int count = (int)items.size();
   // device layout in u_batch: HermArgs[count], eig_first[count+1], app_first[count+1],
@@ -720,9 +715,8 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items, i
     int nb = (it.n + 15) / 16;
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
-    const int64_t ld = it.ld > 0 ? it.ld : it.n;
-    a.hr = it.hr; a.hi = it.hi; a.ldh = ld; a.n = it.n; a.nb = nb;
-    a.wr = it.wr; a.wi = it.wi; a.ldw = ld;
+    a.hr = it.hr; a.hi = it.hi; a.ldh = it.n; a.n = it.n; a.nb = nb;
+    a.wr = it.wr; a.wi = it.wi; a.ldw = it.n;
     a.wcols = 128;
     a.wchunks = (it.n + a.wcols - 1) / a.wcols;
     a.qbuf = M->part + qoff;
@@ -735,8 +729,8 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items, i
     first[i + 1] = first[i] + nb / 2;
     first[count + 1 + i + 1] = first[count + 1 + i] + herm_apply_groups(a);
     max_n = std::max(max_n, it.n);
-    herm_tol(it.hr, ld, it.n, herm_tol_units(), d_tol + i, s);
-    set_identity(it.wr, it.wi, ld, it.n, s);
+    herm_tol(it.hr, it.n, it.n, herm_tol_units(), d_tol + i, s);
+    set_identity(it.wr, it.wi, it.n, it.n, s);
   }
   if (qoff > M->part_cap || foff > M->flags_cap) throw Error(-1, "U(1) SVD: batched Jacobi scratch too small");
   // The sector Gram matrices are diagonal blocks of one Gram matrix, whose
@@ -774,11 +768,6 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items, i
       M->total_sweeps += sweep;
       return;
     }
-    if (sweep_cap > 0 && sweep == sweep_cap) {
-      M->last_sweeps = sweep;
-      M->total_sweeps += sweep;
-      return;
-    }
     if (sweep == max_sweeps) {
       M->failed = true;
       throw Error(-4, "batched Hermitian Jacobi did not converge within max_sweeps (" + std::to_string(count) +
@@ -795,53 +784,25 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items, i
 // Rayleigh-Ritz.  On return sZ holds the Ritz vectors as rows (conjugated,
 // as W in run_herm_jacobi), M->norms the Ritz values, and info_d[5] the
 // weight of G outside the subspace (trace minus the Ritz values).
-//
-// With blocks given, G is block diagonal (particle-number sectors) and the
-// caller has filled the p starting rows of sZ, orthonormal, each supported on
-// the columns of one sector, grouped by sector; blocks lists the diagonal blocks of the
-// p x p Rayleigh matrix (one per sector, leading dimension p).  Every GEMM
-// and Newton-Schulz product then keeps the rows inside their sectors, and
-// the Jacobi steps run batched on the diagonal blocks only.
-// Returns false when an orthonormalisation does not converge (a start
-// that is nearly dependent on the null space of a rank-deficient G); the
-// caller then solves G directly.
-bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w,
-                   const std::vector<BatchItem>* blocks = nullptr) {
+// Returns false when the iteration breaks down (an orthonormalisation that
+// does not converge, a Rayleigh matrix that is not positive semi-definite, or
+// kept values still moving at the last iteration: a start nearly inside the
+// null space of a rank-deficient G); the caller then solves G directly.
+bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w) {
   hipStream_t s = M->stream;
-  if (!blocks) {
-    fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
-    fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
-  }
+  fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
+  fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
   // eigenpairs of the Rayleigh matrix (partially with a sweep cap)
-  auto rr_jacobi = [&](int cap) {
-    if (!blocks) {
-      run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, cap);
-      return;
-    }
-    fill_zero(M->sW.re, (int64_t)p * p, s);
-    fill_zero(M->sW.im, (int64_t)p * p, s);
-    std::vector<BatchItem> big;
-    for (const BatchItem& b : *blocks) {
-      if (b.n > 1)
-        big.push_back(b);
-      else
-        set_identity(b.wr, b.wi, b.ld, 1, s);
-    }
-    if (!big.empty()) run_herm_jacobi_batched(M, big, cap);
-  };
+  auto rr_jacobi = [&](int cap) { run_herm_jacobi(M, M->sH.re, M->sH.im, p, p, M->sW.re, M->sW.im, p, cap); };
   int kw = 0;   // warm rows at the top of the basis
-  if (blocks) {
-    // rows prepared by the caller
-  } else if (w.kind == 1 && w.src_cols <= p && w.src_rows == r) {
+  if (w.kind == 1 && w.src_cols <= p && w.src_rows == r) {
     conj_transpose_scaled(w.sr, w.si, w.ld, w.rs, w.rdiv, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
     kw = w.src_cols;
   } else if (w.kind == 2 && w.src_rows <= p && w.src_cols == r) {
     scale_rows_copy(w.sr, w.si, w.ld, nullptr, 1, w.src_rows, w.src_cols, M->sZ.re, M->sZ.im, r, s);
     kw = w.src_rows;
   }
-  if (blocks) {
-    // orthonormal already
-  } else if (kw > 0 && kw < p) {
+  if (kw > 0 && kw < p) {
     // Orthonormalise the warm rows on their own and take the random rows
     // out of their span, so that the basis keeps the warm rows as they are
     // (a joint symmetric orthonormalisation would mix them with noise).
@@ -1150,9 +1111,6 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     int64_t goff = 0;        // r x r Gram / eigenvector rows / rotations in G and W
     int u0 = 0;              // first value of the sector in the union
     int64_t ro = 0, co = 0;  // row and column lists in u_idx
-    std::vector<int> warm;   // warm-start bond indices of this number (subspace path)
-    int p = 0, z0 = 0;       // subspace rows of the sector and the first of them
-    bool full = false;       // the subspace is the whole sector (identity rows)
     int v0 = 0, vn = 0;      // the sector's values in the selection: [v0, v0 + vn)
     const double* vbr = nullptr;   // eigenvector (Ritz) row loc at vbr + loc * vld
     const double* vbi = nullptr;
@@ -1193,80 +1151,9 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     secs.push_back(&S);
   }
   if (secs.empty()) throw Error(-1, "U(1) SVD: no particle-number sector has both rows and columns");
-  // Subspace path of the Gram route: with the bond's previous particle
-  // numbers at hand, each sector gets p_Q rows, its warm rows (the previous
-  // Schmidt vectors of that number) plus a few random ones, and the whole
-  // block-diagonal Gram matrix goes through one subspace iteration.
-  const WarmStart& w = in.warm;
-  int P = 0;
-  bool sub = false;
-  int64_t wo = io;   // warm index lists follow the sector lists in u_idx
-  if (gram && w.q && (w.kind == 1 || w.kind == 2) && M->sub_p > 0) {
-    const std::vector<int>& wq = *w.q;
-    for (Sector* S : secs) {
-      S->warm.clear();
-      // warm rows exist on the side the previous Schmidt vectors live on; a
-      // sector whose Gram matrix lies on the other side is solved whole
-      const bool match = (w.kind == 1) == S->left;
-      if (match)
-        for (int x = 0; x < (int)wq.size(); ++x)
-          if (wq[x] == S->q) S->warm.push_back(x);
-      // A few random rows join the warm ones.  They must leave at least as
-      // much room in the sector again (random rows filling most of the
-      // complement of the warm rows would be ill-conditioned); otherwise the
-      // sector is taken whole, with identity rows.
-      const int kw = (int)S->warm.size();
-      const int extra = std::max(4, kw / 16);
-      S->full = !(match && kw + 2 * extra <= S->r);
-      if (S->full) {
-        S->p = S->r;
-        S->warm.clear();
-      } else {
-        S->p = kw + extra;
-      }
-      S->z0 = P;
-      P += S->p;
-    }
-    static const double frac =
-        std::getenv("PTEBD_U1_SUBSPACE_FRAC") ? std::atof(std::getenv("PTEBD_U1_SUBSPACE_FRAC")) : 0.667;
-    sub = P <= M->sub_p && nvals <= M->sub_r && (double)P < frac * nvals;
-  }
-  if (debug_enabled() && gram)
-    std::fprintf(stderr, "[ptebd] U(1) gram m=%d n=%d sectors=%zu union=%d warm=%d P=%d sub_p=%d sub_r=%d -> %s\n", m,
-                 n, secs.size(), nvals, w.q ? (int)w.q->size() : -1, P, M->sub_p, M->sub_r,
-                 sub ? "subspace" : "direct");
-  // The starting rows are built in stages, as on the dense path: the warm
-  // rows of every sector first (rows [0, KW)), then the random rows of every
-  // sector; then they are permuted into sector order (sector Q at rows
-  // [z0, z0 + p)).
-  int KW = 0;
-  for (Sector* S : secs) KW += (int)S->warm.size();
-  int64_t need_idx = io + std::min(m, n);
-  if (sub) {
-    need_idx += KW + 2 * (int64_t)(P - KW) + P;
-    if (need_idx > M->u_idx_cap) sub = false;
-  }
   if (io + std::min(m, n) > M->u_idx_cap) throw Error(-1, "U(1) SVD: sector lists exceed their buffer");
-  int64_t lo_off = 0, perm_off = 0;
-  if (sub) {
-    for (Sector* S : secs) M->h_idx.insert(M->h_idx.end(), S->warm.begin(), S->warm.end());
-    lo_off = (int64_t)M->h_idx.size();
-    for (Sector* S : secs)
-      for (int t = (int)S->warm.size(); t < S->p; ++t) M->h_idx.push_back(S->u0);
-    for (Sector* S : secs)
-      for (int t = (int)S->warm.size(); t < S->p; ++t) M->h_idx.push_back(S->u0 + S->r);
-    perm_off = (int64_t)M->h_idx.size();
-    int wz = 0, rz = KW;
-    for (Sector* S : secs) {
-      const int kw = (int)S->warm.size();
-      for (int t = 0; t < kw; ++t) M->h_idx.push_back(wz + t);
-      for (int t = kw; t < S->p; ++t) M->h_idx.push_back(rz + (t - kw));
-      wz += kw;
-      rz += S->p - kw;
-    }
-  }
-  PTEBD_HIP(hipMemcpyAsync(M->u_idx, M->h_idx.data(), sizeof(int) * M->h_idx.size(), hipMemcpyHostToDevice, s));
-  const int64_t idx_end = (int64_t)M->h_idx.size();
+  PTEBD_HIP(hipMemcpyAsync(M->u_idx, M->h_idx.data(), sizeof(int) * io, hipMemcpyHostToDevice, s));
+  const int64_t idx_end = io;
   // gather every sector block (Gram: as it stands; Jacobi: rows, or the
   // conjugate transpose for a tall block) and decompose it
   for (Sector* S : secs) {
@@ -1294,13 +1181,8 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, S->n, s);
     }
   }
-  // The Gram matrix of every sector: packed r x r blocks (direct path), or
-  // the diagonal blocks of one nvals x nvals matrix (subspace path).
-  auto sector_grams = [&](bool dense_layout) {
-    if (dense_layout) {
-      fill_zero(M->G.re, (int64_t)nvals * nvals, s);
-      fill_zero(M->G.im, (int64_t)nvals * nvals, s);
-    }
+  // The Gram matrix of every sector, packed r x r blocks.
+  auto sector_grams = [&]() {
     for (Sector* S : secs) {
       const double* br = xbuf.re + S->off;
       const double* bi = xbuf.im + S->off;
@@ -1314,12 +1196,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
         g.ar = br; g.ai = bi; g.lda = S->n; g.transA = 1;
         g.br = br; g.bi = bi; g.ldb = S->n;
       }
-      if (dense_layout) {
-        g.cr = M->G.re + (int64_t)S->u0 * nvals + S->u0; g.ci = M->G.im + (int64_t)S->u0 * nvals + S->u0;
-        g.ldc = nvals;
-      } else {
-        g.cr = M->G.re + S->goff; g.ci = M->G.im + S->goff; g.ldc = S->r;
-      }
+      g.cr = M->G.re + S->goff; g.ci = M->G.im + S->goff; g.ldc = S->r;
       g.herm_out = 1;
       zgemm(g, 0, s);
     }
@@ -1345,99 +1222,9 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     return k;
   };
   int k = 0;
-  bool done = false;
-  if (sub) {
-    sector_grams(true);
-    // warm rows (zero outside their sector), then random rows masked to
-    // their sector's columns
-    const int nr = P - KW;
-    fill_zero(M->sZ.re, (int64_t)KW * nvals, s);
-    fill_zero(M->sZ.im, (int64_t)KW * nvals, s);
-    tebd_mps::Z rnd{M->sZ.re + (int64_t)KW * nvals, M->sZ.im + (int64_t)KW * nvals};
-    fill_random(rnd.re, (int64_t)nr * nvals, 0x5eed1234abcdull, s);
-    fill_random(rnd.im, (int64_t)nr * nvals, 0x0bad5eedfeedull, s);
-    mask_rows(rnd.re, rnd.im, nvals, nr, nvals, M->u_idx + lo_off, M->u_idx + lo_off + nr, s);
-    std::vector<BatchItem> blocks;
-    int64_t wpos = wo;
-    int wz = 0, rz = 0;
-    for (Sector* S : secs) {
-      const int kw = (int)S->warm.size();
-      double* zr = M->sZ.re + (int64_t)wz * nvals + S->u0;
-      double* zi = M->sZ.im + (int64_t)wz * nvals + S->u0;
-      wz += kw;
-      if (S->full)   // identity rows over the sector's columns
-        set_identity(rnd.re + (int64_t)rz * nvals + S->u0, rnd.im + (int64_t)rz * nvals + S->u0, nvals, S->r, s);
-      rz += S->p - kw;
-      if (kw > 0) {
-        if (w.kind == 1)   // rows conj(Lambda B)^T restricted to the sector's rows of A
-          gather_block(w.sr, w.si, w.ld, w.rs, w.rdiv, M->u_idx + S->ro, S->m, M->u_idx + wpos, kw, 1, zr, zi,
-                       nvals, s);
-        else               // rows of the source restricted to the sector's columns of A
-          gather_block(w.sr, w.si, w.ld, nullptr, 1, M->u_idx + wpos, kw, M->u_idx + S->co, S->n, 0, zr, zi, nvals,
-                       s);
-      }
-      wpos += kw;
-      blocks.push_back(BatchItem{M->sH.re + (int64_t)S->z0 * P + S->z0, M->sH.im + (int64_t)S->z0 * P + S->z0,
-                                 M->sW.re + (int64_t)S->z0 * P + S->z0, M->sW.im + (int64_t)S->z0 * P + S->z0, S->p,
-                                 (int64_t)P});
-    }
-    // Orthonormalise the warm rows on their own, take the random rows out of
-    // their span and orthonormalise those: every product keeps the rows
-    // inside their sectors (the Gram blocks between sectors are zero).
-    bool ortho = KW == 0 || lowdin(M, M->sZ, M->sZ2, KW, nvals, true, true);
-    if (ortho && KW > 0 && nr > 0) {
-      ZGemmArgs c;   // C = R Zw^+  (nr x KW)
-      c.m = nr; c.n = KW; c.k = nvals;
-      c.ar = rnd.re; c.ai = rnd.im; c.lda = nvals;
-      c.br = M->sZ.re; c.bi = M->sZ.im; c.ldb = nvals; c.transB = 1;
-      c.cr = M->sH.re; c.ci = M->sH.im; c.ldc = KW;
-      zgemm(c, 0, s);
-      ZGemmArgs u;   // R <- R - C Zw
-      u.m = nr; u.n = nvals; u.k = KW;
-      u.ar = M->sH.re; u.ai = M->sH.im; u.lda = KW;
-      u.br = M->sZ.re; u.bi = M->sZ.im; u.ldb = nvals;
-      u.cr = rnd.re; u.ci = rnd.im; u.ldc = nvals;
-      u.alpha = -1.0; u.beta = 1;
-      zgemm(u, 0, s);
-    }
-    if (ortho && nr > 0) ortho = lowdin(M, rnd, M->sZ2, nr, nvals, true, true);
-    if (ortho) {   // sector order
-      gather_rows(M->sZ.re, M->sZ.im, nvals, M->u_idx + perm_off, nullptr, P, nvals, M->sZ2.re, M->sZ2.im, nvals,
-                  nullptr, s);
-      std::swap(M->sZ, M->sZ2);
-    }
-    const bool conv =
-        ortho && subspace_topk(M, M->G.re, M->G.im, nvals, P, std::min({M->chi_max, nvals, P}), WarmStart{}, &blocks);
-    // (the iteration swaps its buffers: the Ritz rows are where sZ points now)
-    for (Sector* S : secs) {
-      S->v0 = S->z0;
-      S->vn = S->p;
-      S->vbr = M->sZ.re + (int64_t)S->z0 * nvals + S->u0;
-      S->vbi = M->sZ.im + (int64_t)S->z0 * nvals + S->u0;
-      S->vld = nvals;
-    }
-    if (conv) {
-      // the ledger is charged only once the sectors are known to hold every kept value
-      double* trial = M->info_d + 12;
-      fill_zero(trial, 1, s);
-      select_truncate(M->norms, P, 1, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, trial,
-                      M->info_d + 5, s);
-      k = read_kept();
-      // A sector whose subspace is nearly filled by kept values may miss
-      // values above the cut: fall back to solving every sector in full.
-      done = true;
-      for (Sector* S : secs) {
-        const int guard = std::max(2, (S->p - (int)S->warm.size()) / 2);
-        if (S->p < S->r && (int)S->kept.size() > S->p - guard) done = false;
-      }
-      if (done) accumulate_slots(trial, 1, M->ledger, s);
-    }
-    if (!done && debug_enabled())
-      std::fprintf(stderr, "[ptebd] U(1) subspace %s: solving sectors in full\n", conv ? "too narrow" : "failed");
-  }
-  if (!done) {
+  {
     if (gram) {
-      sector_grams(false);
+      sector_grams();
       std::vector<BatchItem> items;
       for (Sector* S : secs) {
         double* wr = M->W.re + S->goff;
@@ -1626,7 +1413,6 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   in1.warm.sr = S->Br[j]; in1.warm.si = S->Bi[j]; in1.warm.ld = c1;
   in1.warm.src_rows = m1; in1.warm.src_cols = c1;
   in1.warm.rs = S->lam[j]; in1.warm.rdiv = d;
-  if (S->u1) in1.warm.q = &S->q[j + 1];
   std::vector<int> q1, q2;
   int k1;
   if (S->u1) {
@@ -1661,7 +1447,6 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   in2.warm.kind = 2;
   in2.warm.sr = S->Br[j + 2]; in2.warm.si = S->Bi[j + 2]; in2.warm.ld = n2;
   in2.warm.src_rows = c2; in2.warm.src_cols = n2;
-  if (S->u1) in2.warm.q = &S->q[j + 2];
   int k2;
   if (S->u1) {
     // rows (a', s2): q1[a'] + s2; columns (s3, b): q_{j+3}[b] - s3
@@ -1726,7 +1511,6 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
   in.warm.sr = S->Br[K]; in.warm.si = S->Bi[K]; in.warm.ld = cm;
   in.warm.src_rows = m1; in.warm.src_cols = cm;
   in.warm.rs = S->lam[K]; in.warm.rdiv = D;
-  if (S->u1) in.warm.q = &S->q[K + 1];
   // V^+ goes straight to B_{K+1}: psi' no longer needs the old B_{K+1}
   std::vector<int> qk;
   int k;

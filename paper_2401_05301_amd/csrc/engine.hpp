@@ -153,8 +153,6 @@ struct WarmStart {
   int src_rows = 0, src_cols = 0;
   const double* rs = nullptr;
   int rdiv = 1;
-  // particle numbers of the warm rows' bond indices (U(1) SVD), or null
-  const std::vector<int>* q = nullptr;
 };
 
 struct SvdIn {

@@ -176,8 +176,6 @@ void supersite_local(const double* const* br, const double* const* bi, const dou
 // (trans == 1); ldo is the leading dimension of out.
 void gather_block(const double* ar, const double* ai, int64_t lda, const double* rs, int rdiv, const int* rows, int m,
                   const int* cols, int n, int trans, double* outr, double* outi, int64_t ldo, hipStream_t s);
-// Zero every entry of row i of Z (p x r) outside columns [lo[i], hi[i]) (device arrays).
-void mask_rows(double* zr, double* zi, int64_t ldz, int p, int r, const int* lo, const int* hi, hipStream_t s);
 // One row copy: len values from (sr, si) into (dr, di) at positions cols[t]
 // (or t when cols is null), times scale[sidx] when sidx >= 0.
 struct RowCopy {

@@ -168,12 +168,12 @@ def test_u1_rejects_state_without_definite_numbers(pt):
     g.close()
 
 
-def test_u1_gram_subspace_sectors(pt):
-    """Gram route at a bond cap where each sector is solved by the sector
-    subspace iteration (previous Schmidt vectors of the same particle number
-    plus a few random rows); layers on a random state of N = 8 bosons."""
-    L, d, chi, N = 12, 5, 96, 6
-    B, lam, _ = random_mps_u1(L, d, chi, N, seed=5, tau=20.0, bias=30.0)
+def test_u1_gram_few_sectors(pt):
+    """Gram route on a random state of N = 6 bosons spread over few particle
+    numbers per bond (sigma = 1), five layers including the second-order
+    pattern, against the oracle with the same singular-value floor."""
+    L, d, chi, N = 12, 5, 40, 6
+    B, lam, _ = random_mps_u1(L, d, chi, N, seed=5, tau=20.0, sigma=1.0, bias=30.0)
     m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
     # the Gram route drops values below 1e-6 s_0: the oracle applies the same floor
     tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-6)
