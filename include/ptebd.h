@@ -247,6 +247,7 @@ typedef struct {
   double trunc_weight, trunc_rel;
   int32_t workers_per_request;  /* gate workers of each request's handle; <= 0 selects 1 */
   int32_t measure_every;      /* measure_local every this many steps as well (0: only at the horizon) */
+  int32_t u1;                 /* tebd_opts.u1 for every request (0 or 1) */
 } tebd_serve_opts;
 
 typedef struct {

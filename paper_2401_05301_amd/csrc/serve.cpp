@@ -58,6 +58,7 @@ extern "C" tebd_status tebd_serve(const tebd_request* req, int32_t n, const tebd
     o.trunc_rel = so->trunc_rel;
     o.prec = so->prec;
     o.svd = so->svd;
+    o.u1 = so->u1;
     o.workers = so->workers_per_request > 0 ? so->workers_per_request : 1;
     tebd_status st = mps_footprint(&r.model, &o, &footprint[i]);
     if (st) return st;   // message set by mps_footprint

@@ -83,3 +83,26 @@ def test_step_many_matches_single_steps(pt):
         assert np.abs(n1 - n2).max() <= 1e-13 and np.abs(C1 - C2).max() <= 1e-13 and np.abs(D1 - D2).max() <= 1e-13
         g.close()
         q.close()
+
+
+def test_serving_u1_matches_alone_and_dense(pt):
+    """Requests served with U(1) sectors give what the same request gives
+    alone with U(1) sectors, and agree with the dense route."""
+    reqs = requests(pt)[:4]
+    note("serving 4 requests with U(1) sectors")
+    res = pt.tebd_serve(reqs, max_active=2, hbm_budget=8e9, u1=True)
+    for r, s in zip(reqs, res):
+        assert s["status"] == pt.TEBD_OK
+        o = pt.make_opts(r["chi_max"], 1e-12, 1e-12, workers=1, u1=True)
+        g = pt.MPS.cdw(r["model"], o)
+        for _ in range(r["steps"]):
+            g.step(r["dt"])
+        n, C, D = g.measure()
+        g.close()
+        assert np.abs(s["n"] - n).max() <= 1e-13
+        assert np.abs(s["c_nn"] - C).max() <= 1e-13
+        nd, Cd, Dd, _ = alone(pt, r)
+        # same truncation rule on the same spectra: equal to the dense route
+        # within the parity bar (the test chains keep gaps at the cut)
+        assert np.abs(n - nd).max() <= 1e-9
+        assert np.abs(C - Cd).max() <= 1e-9
