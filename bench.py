@@ -168,7 +168,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build evolves one chain per GPU and has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library evolves one chain per GPU and has no multi-GPU path "
               "(see the sharding design); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -92,17 +92,17 @@ def main():
         "Commands (repository root, one MI355X; `cd /tmp && export TMPDIR=/tmp && cd /root/repo` first):",
         "",
         "```",
-        "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d gpurun_out/pmc "
+        "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
         "-o bench_fetch -- python -u bench.py --no-cpu-baseline --serve 0",
-        "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d gpurun_out/pmc "
+        "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
         "-o bench_write -- python -u bench.py --no-cpu-baseline --serve 0",
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc -o copy_fetch -- python -u bench.py "
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc -o copy_fetch -- python -u bench.py "
         "--copy-calibration 1024",
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc -o copy_write -- python -u bench.py "
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc -o copy_write -- python -u bench.py "
         "--copy-calibration 1024",
         "python paper_2401_05301_amd/traffic.py --bench-json <bench line of the FETCH run> "
-        "--fetch gpurun_out/pmc/bench_fetch_counter_collection.csv --write gpurun_out/pmc/bench_write_counter_collection.csv "
-        "--copy-fetch gpurun_out/pmc/copy_fetch_counter_collection.csv --copy-write gpurun_out/pmc/copy_write_counter_collection.csv "
+        "--fetch <dir>/pmc/bench_fetch_counter_collection.csv --write <dir>/pmc/bench_write_counter_collection.csv "
+        "--copy-fetch <dir>/pmc/copy_fetch_counter_collection.csv --copy-write <dir>/pmc/copy_write_counter_collection.csv "
         "--copy-bytes 1073741824 --out profiles/zgemm_traffic_bulk_L64_chi1024",
         "```",
         "",
