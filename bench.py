@@ -83,6 +83,49 @@ def measured_gemm_peak(pt, torch, n: int = 4096):
     return {"n": n, "zgemm_kernel_TFLOPs": ours, "rocblas_zgemm_TFLOPs": lib}
 
 
+def quench_run(pt, torch, args):
+    """The growing-chi quench: CDW start of the L = 64, d = 5 chain (U = 3,
+    J_NNN = 0.1, K = 0.002 centred at 32.5), truncation 1e-10, chi <= 512,
+    dt = 0.01; every step is timed and measured."""
+    import numpy as np
+    from workloads import CONFIGS
+    cfg = CONFIGS["batched_L64_chi512"]
+    m, tr, dt = cfg["model"], cfg["trunc"], cfg["dt"]
+    svd = {"gram": pt.SVD_GRAM_EIG, "jacobi": pt.SVD_JACOBI}[args.svd]
+    stream = torch.cuda.Stream()
+    opts = pt.make_opts(tr.chi_max, tr.w_max, tr.eps, svd=svd, stream=stream.cuda_stream, workers=args.workers,
+                        u1=args.u1)
+    g = pt.MPS.cdw(pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), opts)
+    g.prepare(dt)
+    per_step = gate_updates_per_step(m.L)
+    times, chis = [], []
+    t_all = time.perf_counter()
+    for k in range(args.steps):
+        t0 = time.perf_counter()
+        g.step(dt)
+        n, C, D = g.measure()
+        times.append(time.perf_counter() - t0)
+        chis.append(max(g.bond_dims()))
+        if (k + 1) % 10 == 0 or k + 1 == args.steps:
+            log(f"quench step {k + 1}/{args.steps}: max bond {chis[-1]}, {times[-1]:.3f} s")
+    wall = time.perf_counter() - t_all
+    out = {
+        "metric": "gate-updates/s of the growing-chi quench (CDW start)",
+        "value": per_step * args.steps / wall, "unit": "gate-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 0, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched_L64_chi512", "L": m.L, "d": m.d, "U": m.U, "Jnnn": m.Jnnn, "K": m.K,
+                   "jc": m.centre(), "chi_max": tr.chi_max, "w_max": tr.w_max, "dt": dt, "svd": args.svd,
+                   "u1": bool(args.u1)},
+        "max_bond_per_step": chis,
+        "seconds_per_step": [round(t, 4) for t in times],
+        "discarded_weight": g.discarded_weight(),
+        "n_total": float(np.sum(n)),
+    }
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
 def measured_traffic():
     """HBM bytes per launch of the FP64 GEMM from the committed rocprofv3
     counter summary, or None when it is missing or the kernel source has
@@ -147,6 +190,8 @@ def main():
     ap.add_argument("--serve", type=int, default=16, help="requests in the serving sample (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference for the HBM counters) and exit")
+    ap.add_argument("--quench", action="store_true",
+                    help="time the growing-chi CDW quench (L=64, chi<=512, truncation 1e-10) instead")
     ap.add_argument("--u1", action="store_true",
                     help="U(1) block-sparse SVDs on a random state of L/2 bosons with definite numbers per bond index")
     ap.add_argument("--sigma", type=float, default=2.0,
@@ -179,6 +224,9 @@ def main():
     from workloads import CONFIGS, random_mps, random_mps_u1
 
     torch.cuda.set_device(0)
+    if args.quench:
+        quench_run(pt, torch, args)
+        return
     stream = torch.cuda.Stream()
     cfg = CONFIGS["bulk_L64_chi1024"]
     mdl = cfg["model"]
