@@ -126,6 +126,40 @@ def quench_run(pt, torch, args):
     print(json.dumps(out), flush=True)
 
 
+def u1_sample(pt, torch, args):
+    """One timed Strang step of the same chain (L, d = 5, chi) with U(1)
+    sectors: a random state of L/2 bosons (sector width sigma), canonicalised,
+    tebd_opts.u1 = 1, Gram route."""
+    from workloads import CONFIGS, random_mps_u1
+    cfg = CONFIGS["bulk_L64_chi1024"]
+    mdl, dt = cfg["model"], cfg["dt"]
+    L, d, chi = args.L, mdl.d, args.chi
+    B, lam, _ = random_mps_u1(L, d, chi, L // 2, seed=args.seed, tau=args.tau, sigma=args.sigma, bias=args.bias)
+    stream = torch.cuda.Stream()
+    opts = pt.make_opts(chi, 1e-12, 1e-12, svd=pt.SVD_GRAM_EIG, stream=stream.cuda_stream, workers=args.workers,
+                        u1=True)
+    g = pt.MPS.from_tensors(pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre()), opts, B, lam)
+    del B, lam
+    g.canonicalize()
+    g.prepare(dt)
+    g.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.step(dt)
+    g.measure()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"value": gate_updates_per_step(L) / (ms / 1e3), "unit": "gate-updates/s", "ms_per_step": ms,
+           "input": f"random right-orthonormal MPS of {L // 2} bosons (seed {args.seed}, sector width sigma "
+                    f"{args.sigma:g}, right-index weight exp(-b/{args.bias:g})), canonicalised",
+           "max_bond": max(g.bond_dims())}
+    g.close()
+    return out
+
+
 def measured_traffic():
     """HBM bytes per launch of the FP64 GEMM from the committed rocprofv3
     counter summary, or None when it is missing or the kernel source has
@@ -194,6 +228,10 @@ def main():
                     help="time the growing-chi CDW quench (L=64, chi<=512, truncation 1e-10) instead")
     ap.add_argument("--u1", action="store_true",
                     help="U(1) block-sparse SVDs on a random state of L/2 bosons with definite numbers per bond index")
+    ap.add_argument("--no-square-gemm", action="store_true",
+                    help="skip the square-GEMM reference (it launches this library's GEMM after the timed step)")
+    ap.add_argument("--no-u1-sample", action="store_true",
+                    help="skip the U(1) step reported under u1_sample in the default run")
     ap.add_argument("--sigma", type=float, default=2.0,
                     help="--u1: width of the particle-number distribution over each bond's indices")
     ap.add_argument("--serve-scale", type=float, default=0.1,
@@ -322,7 +360,7 @@ def main():
                           # with --u1 the sector SVDs do far less than the dense count F_GU: the
                           # figure is then a dense-equivalent rate, not work done
                           "dense_equivalent": bool(args.u1)},
-        "measured_square_gemm": measured_gemm_peak(pt, torch),
+        "measured_square_gemm": None if args.no_square_gemm else measured_gemm_peak(pt, torch),
         "wall_s": wall,
         "kernel_ms": {k: v[0] for k, v in prof.items()},
         "dominant_kernel_class": dom[0],
@@ -331,6 +369,9 @@ def main():
         "max_bond": max(chis),
     }
     g.close()
+    if not args.u1 and not args.no_u1_sample:
+        log("U(1) sample: one step of the same chain with particle-number sectors")
+        out["u1_sample"] = u1_sample(pt, torch, args)
     if args.serve > 0:
         log(f"serving sample: {args.serve} requests")
         out["serving"] = serving_sample(pt, args.serve, args.serve_scale)

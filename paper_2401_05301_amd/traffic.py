@@ -11,8 +11,8 @@ FETCH_SIZE and WRITE_SIZE report KiB per dispatch; each is scaled by the
 ratio of the known copy size to what the same counter reads for the copy.
 The GEMM figures average the last N dispatches of ``zgemm_kernel<0, ...>``,
 N being the number of GEMM launches of bench.py's timed region (so the
-bench must be run without the serving sample, which launches GEMMs after
-it).  Writes <out>.json (read by bench.py) and <out>.md (the summary).
+bench must be run without the square-GEMM reference, the U(1) sample and the
+serving sample, which launch GEMMs after it).  Writes <out>.json (read by bench.py) and <out>.md (the summary).
 """
 from __future__ import annotations
 
@@ -93,9 +93,9 @@ def main():
         "",
         "```",
         "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_fetch -- python -u bench.py --no-cpu-baseline --serve 0",
+        "-o bench_fetch -- python -u bench.py --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm",
         "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_write -- python -u bench.py --no-cpu-baseline --serve 0",
+        "-o bench_write -- python -u bench.py --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm",
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc -o copy_fetch -- python -u bench.py "
         "--copy-calibration 1024",
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc -o copy_write -- python -u bench.py "
