@@ -192,3 +192,21 @@ def test_u1_gram_few_sectors(pt):
         assert np.abs(D - oD).max() < tol
     check_bonds(g, om, bar(om, 1e-8))
     g.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_u1_fp32_theta_gate(pt, prec):
+    """U(1) sectors with the FP32 / split-FP32 theta and gate GEMMs: the
+    sectors are found from the particle numbers, not from the values, so the
+    FP32 path keeps its 1e-6 bar against the FP64 oracle."""
+    m = Model(L=10, d=3, U=2.0, J=1.0, Jnnn=0.1, K=0.01)
+    tr = Trunc(chi_max=24, w_max=1e-12, eps=1e-12)
+    ores = otebd.run(m, tr, 0.02, 8)
+    g = pt.MPS.cdw(gpu_model(pt, m), pt.make_opts(tr.chi_max, tr.w_max, tr.eps, prec=prec, u1=True))
+    for _ in range(8):
+        g.step(0.02)
+    n, C, D = g.measure()
+    err = max(np.abs(n - ores["n"][-1]).max(), np.abs(C - ores["C"][-1]).max(), np.abs(D - ores["D"][-1]).max())
+    note(f"u1 prec={prec} max observable error {err:.3e}")
+    assert err <= 1e-6
+    g.close()
