@@ -1111,10 +1111,6 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
     int64_t goff = 0;        // r x r Gram / eigenvector rows / rotations in G and W
     int u0 = 0;              // first value of the sector in the union
     int64_t ro = 0, co = 0;  // row and column lists in u_idx
-    int v0 = 0, vn = 0;      // the sector's values in the selection: [v0, v0 + vn)
-    const double* vbr = nullptr;   // eigenvector (Ritz) row loc at vbr + loc * vld
-    const double* vbi = nullptr;
-    int64_t vld = 0;
     std::vector<int> kept;   // ranks (by decreasing value) of the kept values
     int64_t xoff = 0, yoff = 0;
   };
@@ -1201,63 +1197,50 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       zgemm(g, 0, s);
     }
   };
-  auto read_kept = [&]() {
-    PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    const int k = M->h_info[0];
-    M->h_perm.resize(k);
-    PTEBD_HIP(hipMemcpyAsync(M->h_perm.data(), M->perm, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    std::vector<int> v0s;
+  if (gram) {
+    sector_grams();
+    std::vector<BatchItem> items;
     for (Sector* S : secs) {
-      v0s.push_back(S->v0);
-      S->kept.clear();
+      double* wr = M->W.re + S->goff;
+      double* wi = M->W.im + S->goff;
+      if (S->r > 1)
+        items.push_back(BatchItem{M->G.re + S->goff, M->G.im + S->goff, wr, wi, S->r});
+      else
+        set_identity(wr, wi, 1, 1, s);
     }
+    // all sector eigenproblems in one batched Jacobi
+    if (!items.empty()) run_herm_jacobi_batched(M, items);
+  }
+  // the union of the sector spectra (after every Jacobi run, which uses
+  // M->norms as its own scratch)
+  for (Sector* S : secs) {
+    double* out = M->norms + S->u0;
+    if (!gram) {
+      if (S->left)
+        row_norms(xbuf.re + S->off, xbuf.im + S->off, S->n, S->m, S->n, out, s);
+      else
+        row_norms(xbuf.re + S->off, xbuf.im + S->off, S->m, S->n, S->m, out, s);
+    } else {
+      herm_diag(M->G.re + S->goff, S->r, S->r, out, s);
+    }
+  }
+  select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
+                  M->ledger, nullptr, s);
+  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  const int k = M->h_info[0];
+  M->h_perm.resize(k);
+  PTEBD_HIP(hipMemcpyAsync(M->h_perm.data(), M->perm, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int> u0s;
+    for (Sector* S : secs) u0s.push_back(S->u0);
     for (int i = 0; i < k; ++i) {
       const int v = M->h_perm[i];
-      const int si = (int)(std::upper_bound(v0s.begin(), v0s.end(), v) - v0s.begin()) - 1;
-      if (si < 0 || v >= secs[si]->v0 + secs[si]->vn) throw Error(-3, "U(1) SVD: kept value outside every sector");
+      const int si = (int)(std::upper_bound(u0s.begin(), u0s.end(), v) - u0s.begin()) - 1;
+      if (si < 0 || v >= secs[si]->u0 + secs[si]->r) throw Error(-3, "U(1) SVD: kept value outside every sector");
       secs[si]->kept.push_back(i);
     }
-    return k;
-  };
-  int k = 0;
-  {
-    if (gram) {
-      sector_grams();
-      std::vector<BatchItem> items;
-      for (Sector* S : secs) {
-        double* wr = M->W.re + S->goff;
-        double* wi = M->W.im + S->goff;
-        if (S->r > 1)
-          items.push_back(BatchItem{M->G.re + S->goff, M->G.im + S->goff, wr, wi, S->r});
-        else
-          set_identity(wr, wi, 1, 1, s);
-      }
-      // all sector eigenproblems in one batched Jacobi
-      if (!items.empty()) run_herm_jacobi_batched(M, items);
-    }
-    // the union of the sector spectra (after every Jacobi run, which uses
-    // M->norms as its own scratch)
-    for (Sector* S : secs) {
-      double* out = M->norms + S->u0;
-      if (!gram) {
-        if (S->left)
-          row_norms(xbuf.re + S->off, xbuf.im + S->off, S->n, S->m, S->n, out, s);
-        else
-          row_norms(xbuf.re + S->off, xbuf.im + S->off, S->m, S->n, S->m, out, s);
-      } else {
-        herm_diag(M->G.re + S->goff, S->r, S->r, out, s);
-      }
-      S->v0 = S->u0;
-      S->vn = S->r;
-      S->vbr = M->W.re + S->goff;
-      S->vbi = M->W.im + S->goff;
-      S->vld = S->r;
-    }
-    select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
-                    M->ledger, nullptr, s);
-    k = read_kept();
   }
   // output order: by particle number, then by rank
   kept_q.clear();
@@ -1284,9 +1267,10 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       S->yoff = yo;
       for (size_t t = 0; t < S->kept.size(); ++t) {
         const int i = S->kept[t];
-        const int64_t loc = M->h_perm[i] - S->v0;
-        M->h_tab.push_back(RowCopy{S->vbr + loc * S->vld, S->vbi + loc * S->vld, M->G.re + xo + (int64_t)t * S->m,
-                                   M->G.im + xo + (int64_t)t * S->m, nullptr, (int64_t)S->m, (int64_t)i});
+        const int64_t loc = M->h_perm[i] - S->u0;
+        M->h_tab.push_back(RowCopy{M->W.re + S->goff + loc * S->r, M->W.im + S->goff + loc * S->r,
+                                   M->G.re + xo + (int64_t)t * S->m, M->G.im + xo + (int64_t)t * S->m, nullptr,
+                                   (int64_t)S->m, (int64_t)i});
       }
       xo += (int64_t)S->kept.size() * S->m;
       yo += (int64_t)S->kept.size() * S->n;
@@ -1297,7 +1281,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
   for (Sector* S : secs) {
     for (size_t t = 0; t < S->kept.size(); ++t, ++o) {
       const int i = S->kept[t];
-      const int64_t loc = M->h_perm[i] - S->v0;
+      const int64_t loc = M->h_perm[i] - S->u0;
       const double* sr;
       const double* si;
       int64_t sidx = -1;
@@ -1308,9 +1292,9 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       } else if (gram && S->left) {
         sr = M->uv.re + S->yoff + (int64_t)t * S->n;
         si = M->uv.im + S->yoff + (int64_t)t * S->n;
-      } else {
-        sr = S->vbr + loc * S->vld;
-        si = S->vbi + loc * S->vld;
+      } else {   // rows of W: eigenvector rows (right Gram) or accumulated rotations (tall Jacobi block)
+        sr = M->W.re + S->goff + loc * S->r;
+        si = M->W.im + S->goff + loc * S->r;
       }
       M->h_tab.push_back(RowCopy{sr, si, vhr + o * n, vhi + o * n, M->u_idx + S->co, (int64_t)S->n, sidx});
     }
