@@ -33,6 +33,9 @@ constexpr double kDiagCoupling = 0.05;     // subspace iteration: largest relati
 // blocks of a particle-number sector) can spend 30-40 sweeps in its linear
 // phase before the quadratic one.
 constexpr int kDefaultSweeps = 80;
+// Gram matrices with fewer rows are solved directly (the subspace iteration
+// pays only above about this size).
+constexpr int kSubspaceMinRows = 1024;
 
 int64_t ipow_cap(int d, int e, int cap) {
   int64_t v = 1;
@@ -95,13 +98,15 @@ int auto_workers(int L, int requested, bool super) {
   return std::max(1, std::min(w, per_layer));
 }
 
-int subspace_width(int r, int chi_max) {
-  const int keep = std::min(chi_max, r);
+int subspace_width(int r, int chi_max) { return subspace_width_keep(r, std::min(chi_max, r)); }
+
+int subspace_width_keep(int r, int keep) {
   // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 16)
   static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 16;
   const int p = ((keep + std::max(64, keep / den)) + 15) / 16 * 16;
-  // below ~1.5 p the whole Gram matrix is cheaper to diagonalise directly
-  return (3 * p < 2 * r) ? p : 0;
+  // below ~1.5 p, or below kSubspaceMinRows rows, the whole Gram matrix is
+  // cheaper to diagonalise directly (measured on the quench workload)
+  return (3 * p < 2 * r && r >= kSubspaceMinRows) ? p : 0;
 }
 
 Sizes plan_sizes(int L, int d, int chi_max) {
@@ -890,12 +895,14 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     // The sum of the largest `keep` Rayleigh quotients is the weight the
     // kept subspace captures; it grows monotonically towards the optimum.
     // Stop once an iteration gains less than 1e-4 of the weight still
-    // outside (or less than the rounding level of G) and no kept value moved
-    // by more than 1e-10 of the largest.
+    // outside (or less than the rounding level of G, or 1% of the
+    // truncation tolerance) and no kept value moved by more than 1e-10 of
+    // the largest.
     const double gain = kept - prev_kept;
+    // (a gain below 1% of the truncation tolerance no longer moves the ledger)
     const bool stable = delta <= 1e-10 * h_vals[0];
-    const bool done = (it >= 1 && gain <= std::max(1e-4 * (trace - kept), 64 * u * trace) && stable) ||
-                      it == max_it - 1;
+    const double gain_tol = std::max({1e-4 * (trace - kept), 64 * u * trace, 1e-2 * M->opts.trunc_weight * trace});
+    const bool done = (it >= 1 && gain <= gain_tol && stable) || it == max_it - 1;
     if (it == max_it - 1 && !stable) {
       // kept values still moving at the last iteration: the subspace has
       // not found the leading eigenvectors (a start nearly inside the null
@@ -1045,27 +1052,48 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   // eigenvectors (conjugated, as rows) and eigenvalues of G
   const double* rows_r;
   const double* rows_i;
-  int nvals;
-  const double* extra = nullptr;
   static const bool no_sub = std::getenv("PTEBD_NO_SUBSPACE") != nullptr;   // debugging aid
-  const int p = (M->sub_p > 0 && !no_sub) ? subspace_width(r, M->chi_max) : 0;
-  if (p > 0 && p <= M->sub_p && subspace_topk(M, M->G.re, M->G.im, r, p, std::min(M->chi_max, r), in.warm)) {
-    rows_r = M->sZ.re;
-    rows_i = M->sZ.im;
-    nvals = p;
-    extra = M->info_d + 5;
-  } else {
-    run_herm_jacobi(M, M->G.re, M->G.im, r, r, M->W.re, M->W.im, r);
-    herm_diag(M->G.re, r, r, M->norms, s);
-    rows_r = M->W.re;
-    rows_i = M->W.im;
-    nvals = r;
+  // The kept count follows the bond dimension before the gate, which the
+  // warm rows carry: the subspace is sized for that count with a margin
+  // rather than for chi_max (a subspace far wider than the kept values
+  // spends its iterations on rounding-level eigenvalues without a gap), and
+  // widened to chi_max when more values turn out to be kept.
+  const int keep_full = std::min(M->chi_max, r);
+  int kw = 0;
+  if (in.warm.kind == 1 && in.warm.src_rows == r) kw = in.warm.src_cols;
+  if (in.warm.kind == 2 && in.warm.src_cols == r) kw = in.warm.src_rows;
+  int keep = kw > 0 ? std::min(keep_full, kw + std::max(16, kw / 8)) : keep_full;
+  int k = -1;
+  while (k < 0) {
+    const int p = (M->sub_p > 0 && !no_sub) ? subspace_width_keep(r, keep) : 0;
+    if (p > 0 && p <= M->sub_p && subspace_topk(M, M->G.re, M->G.im, r, p, keep, in.warm)) {
+      // the ledger is charged once the width is known to be enough
+      double* trial = M->info_d + 12;
+      fill_zero(trial, 1, s);
+      select_truncate(M->norms, p, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, trial,
+                      M->info_d + 5, s);
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipStreamSynchronize(s));
+      if (M->h_info[0] > keep && keep < keep_full) {
+        keep = keep_full;
+        continue;
+      }
+      accumulate_slots(trial, 1, M->ledger, s);
+      k = M->h_info[0];
+      rows_r = M->sZ.re;
+      rows_i = M->sZ.im;
+    } else {
+      run_herm_jacobi(M, M->G.re, M->G.im, r, r, M->W.re, M->W.im, r);
+      herm_diag(M->G.re, r, r, M->norms, s);
+      select_truncate(M->norms, r, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger,
+                      nullptr, s);
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipStreamSynchronize(s));
+      k = M->h_info[0];
+      rows_r = M->W.re;
+      rows_i = M->W.im;
+    }
   }
-  select_truncate(M->norms, nvals, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger,
-                  extra, s);
-  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
-  PTEBD_HIP(hipStreamSynchronize(s));
-  const int k = M->h_info[0];
   if (left) {
     // V^+ = S^-1 U_k^+ diag(rs) A
     gather_rows(rows_r, rows_i, r, M->perm, M->inv_sig, k, m, xbuf.re, xbuf.im, m, kdev, s);

@@ -128,6 +128,8 @@ Sizes plan_sizes2(int Ls, int D, int chi_max);
 // Width of the subspace used for the top-k eigenpairs of an r x r Gram
 // matrix when keeping at most chi_max values (0: solve the whole matrix).
 int subspace_width(int r, int chi_max);
+// The same for a given number of values to keep.
+int subspace_width_keep(int r, int keep);
 void mps_allocate(tebd_mps* M);
 void mps_release(tebd_mps* M);
 void upload_product(tebd_mps* M, const int* occ);

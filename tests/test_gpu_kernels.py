@@ -126,9 +126,10 @@ def test_svd_rank_deficient_and_chi_cap(pt):
     assert abs(w2 - np.sum(sr[2:] ** 2) / np.sum(sr ** 2)) < 1e-13
 
 
-@pytest.mark.parametrize("m,n,chi", [(400, 900, 64), (900, 400, 48), (640, 3000, 128)])
+@pytest.mark.parametrize("m,n,chi", [(1100, 1800, 64), (1800, 1100, 48), (1280, 3000, 128), (400, 900, 64)])
 def test_gram_subspace_topk(pt, m, n, chi):
-    """Gram route with subspace iteration (chi_max well below min(m, n))."""
+    """Gram route with subspace iteration (chi_max well below min(m, n),
+    at least 1024 rows), and the direct solve below that size."""
     rng = np.random.default_rng(m + n + chi)
     A, s_true = graded_matrix(rng, m, n, decay=chi / 4.0)
     note(f"gram subspace m={m} n={n} chi={chi}")
@@ -144,7 +145,7 @@ def test_gram_subspace_topk(pt, m, n, chi):
     assert np.abs(P - Pr).max() < 1e-6
 
 
-@pytest.mark.parametrize("m,n,rank,chi", [(700, 900, 150, 128), (900, 700, 1, 64), (1100, 2600, 300, 256)])
+@pytest.mark.parametrize("m,n,rank,chi", [(1100, 1300, 150, 128), (1300, 1100, 1, 64), (1100, 2600, 300, 256)])
 def test_gram_subspace_rank_deficient(pt, m, n, rank, chi):
     """Subspace route on a Gram matrix whose rank lies below the subspace
     width (as for an identity gate on a state of exact bond dimension), with

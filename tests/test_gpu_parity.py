@@ -135,8 +135,8 @@ def test_single_layers_and_random_state(pt):
 
 @pytest.mark.parametrize("svd", [0, 1])
 def test_random_state_layers_chi48(pt, svd):
-    """Random right-orthonormal input at chi = 48, d = 5: with the Gram route
-    the top-chi eigenpairs come from subspace iteration (r = 240 > 1.5 p)."""
+    """Random right-orthonormal input at chi = 48, d = 5 (Gram matrices of
+    at most 240 rows: solved directly on the Gram route)."""
     L, d, chi = 12, 5, 48
     B, lam = random_mps(L, d, chi, seed=7, tau=10.0)
     m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
@@ -279,3 +279,28 @@ def test_rank_deficient_gram_matrices(pt, svd):
 
 def ores_like(om):
     return {"mps": om, "w_total": [om.w_total]}
+
+
+def test_random_state_layer_gram_subspace_chi256(pt):
+    """Gram route where SVD #1 of the central gate has a 1280 x 1280 Gram
+    matrix and chi_max = 256: the kept eigenpairs come from the warm-started
+    subspace iteration.  One layer on a random right-orthonormal state,
+    against the oracle with the same singular-value floor."""
+    L, d, chi = 10, 5, 256
+    B, lam = random_mps(L, d, chi, seed=3, tau=40.0)
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    tr = Trunc(chi_max=chi, w_max=1e-12, eps=1e-6)
+    om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, 1e-12, svd=1), B, lam)
+    note("gram subspace chi=256 layer group=1")
+    otebd.apply_layer(om, otebd.GateCache(m), 1, 0.01, tr)
+    g.layer(1, 0.01)
+    n, C, D = g.measure()
+    on, oC, oD = otebd.measure(om)
+    tol = 1e-8 if om.min_gap >= 1e-8 else max(1e-8, 2 * om.w_total)
+    assert np.abs(n - on).max() < tol, np.abs(n - on).max()
+    assert np.abs(C - oC).max() < tol
+    assert np.abs(D - oD).max() < tol
+    assert g.bond_dims() == om.bond_dims()
+    assert abs(g.discarded_weight() - om.w_total) < 1e-10 + 1e-6 * om.w_total
+    g.close()
