@@ -94,3 +94,20 @@ def test_serve_validation_without_gpu():
     with pytest.raises(pt.TebdError) as e:
         pt.tebd_serve(big, hbm_budget=1024.0)
     assert e.value.status == pt.TEBD_ENOMEM
+
+
+def test_headers_compile_as_c(tmp_path):
+    """The C-ABI headers are plain C99: no torch or C++ types in the signatures."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(ROOT, "include")
+    src = tmp_path / "hdr.c"
+    src.write_text('#include "ptebd.h"\n#include "ptebd_diag.h"\n'
+                   "int main(void) { tebd_opts o; tebd_opts_default(&o); o.u1 = 1; o.supersite = 0;\n"
+                   "  tebd_serve_opts s; s.u1 = 0; (void)s; return 0; }\n")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I", inc,
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
