@@ -45,3 +45,37 @@ def test_bulk_gate_chi1024_sampled():
     assert np.abs(n[win] - on[win]).max() < 1e-8, np.abs(n[win] - on[win]).max()
     assert np.abs(C[j:j + 2] - oC[j:j + 2]).max() < 1e-8
     assert abs(D[j] - oD[j]) < 1e-8
+
+
+@pytest.mark.timeout(1200)
+def test_bulk_gate_chi1024_sampled_u1():
+    """The same check with particle-number sectors (tebd_opts.u1 = 1) on a
+    random state of 16 bosons (one per site, so that the central bonds
+    reach chi = 1024): the sector SVDs against the oracle's dense
+    SVDs of the same gate (spectra compared after sorting, since the
+    library groups each bond by particle number)."""
+    import paper_2401_05301_amd as pt
+    from workloads import random_mps_u1
+    L, d, chi, j, tau = 16, 5, 1024, 6, 0.01
+    B, lam, _ = random_mps_u1(L, d, chi, L, seed=0, tau=110.0, sigma=2.0, bias=150.0)
+    assert all(B[i].shape[0] == chi for i in range(j, j + 4))
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    note(f"full size U(1): bonds {[b.shape[0] for b in B]}")
+    g = pt.MPS.from_tensors(pt.make_model(L, d, m.U, m.J, m.Jnnn, m.K, m.centre()),
+                            pt.make_opts(chi, 1e-12, 1e-12, svd=pt.SVD_GRAM_EIG, workers=4, u1=True), B, lam)
+    g.layer(j % 3, tau)
+    n, C, D = g.measure()
+    lam_g = [np.sort(g.lam(j + 1))[::-1], np.sort(g.lam(j + 2))[::-1]]
+    g.close()
+    note("full size U(1): oracle gate j=6 (dense SVDs)")
+    om = otebd.MPS(B, lam)
+    otebd.apply_gate(om, j, otebd.GateCache(m)(j, tau), Trunc(chi, 1e-12, 1e-6))
+    on, oC, oD = otebd.measure(om)
+    for b, lg in zip((j + 1, j + 2), lam_g):
+        lo = om.lam[b]
+        assert len(lg) == len(lo), (b, len(lg), len(lo))
+        assert np.abs(lg - lo).max() < 1e-8, (b, np.abs(lg - lo).max())
+    win = slice(j, j + 3)
+    assert np.abs(n[win] - on[win]).max() < 1e-8, np.abs(n[win] - on[win]).max()
+    assert np.abs(C[j:j + 2] - oC[j:j + 2]).max() < 1e-8
+    assert abs(D[j] - oD[j]) < 1e-8
