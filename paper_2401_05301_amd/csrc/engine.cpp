@@ -85,7 +85,12 @@ size_t Sizes::bytes(int workers, bool u1) const {
   int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
   w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
   w += 6 * vec + part + 64 + 5 * sub_p + 8;
-  if (u1) w += 2 * uv + (idx + 4 * vec) / 2 + 1 + 2 * vec * (int64_t)(sizeof(RowCopy) / sizeof(double));
+  if (u1) {
+    w += 2 * uv + (idx + 4 * vec) / 2 + 1 + 2 * vec * (int64_t)(sizeof(RowCopy) / sizeof(double));
+    // batched Jacobi tables
+    w += ((int64_t)(std::max(sizeof(HermArgs), sizeof(JacobiArgs)) + 2 * sizeof(int64_t) + 2 * sizeof(int) +
+                    sizeof(double)) * (vec / 2 + 1) + 128 + 7) / 8;
+  }
   d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
 }
@@ -235,7 +240,9 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
     W->uv = zalloc(W, s.uv);
     // at most one batched matrix per two values of the union (each has n >= 2)
     const int64_t cnt = s.vec / 2 + 1;
-    W->u_batch_cap = (int64_t)(sizeof(HermArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) * cnt + 128;
+    W->u_batch_cap =
+        (int64_t)(std::max(sizeof(HermArgs), sizeof(JacobiArgs)) + 2 * sizeof(int64_t) + 2 * sizeof(int) +
+                  sizeof(double)) * cnt + 128;
     W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
   }
   W->info_i = static_cast<int*>(dev_alloc(W, sizeof(int) * 8));
@@ -413,10 +420,11 @@ bool debug_enabled() {
   return on;
 }
 
-// One-sided block Jacobi on the rows of X; returns the number of sweeps.
-int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, double* wi, int64_t ldw, int r, int c,
-               double tol_rel, double tol_abs) {
-  hipStream_t s = M->stream;
+// Launch shape of the one-sided Jacobi on the r rows (length c) of X, with
+// the rotations accumulated into W when wr is set: 16-row blocks, column
+// splits of the pair Grams, column chunks of the update.
+JacobiArgs jacobi_args(double* xr, double* xi, int64_t ldx, double* wr, double* wi, int64_t ldw, int r, int c,
+                       double tol_rel, double tol_abs) {
   int nb = (r + 15) / 16;
   if (nb < 2) nb = 2;
   if (nb & 1) ++nb;
@@ -426,14 +434,25 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
   a.wr = wr; a.wi = wi; a.ldw = ldw;
   a.r = r; a.c = c; a.nb = nb;
   a.nsplit = std::max(1, std::min({kNsplitMax, (c + 63) / 64, (1024 + npairs - 1) / npairs}));
-  if ((int64_t)npairs * a.nsplit * 1536 > M->part_cap) throw Error(-1, "Jacobi scratch too small");
   const int total = c + (wr ? r : 0);
   int nu = std::max(1, std::min((total + 63) / 64, (1024 + npairs - 1) / npairs));
   a.ucols = ((total + nu - 1) / nu + 15) / 16 * 16;
   a.nuchunks = (total + a.ucols - 1) / a.ucols;
-  a.part = M->part;
   a.tol_rel = tol_rel;
   a.tol_abs = tol_abs;
+  return a;
+}
+
+int64_t jacobi_part(const JacobiArgs& a) { return (int64_t)(a.nb / 2) * a.nsplit * 1536; }
+
+// One-sided block Jacobi on the rows of X; returns the number of sweeps.
+int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, double* wi, int64_t ldw, int r, int c,
+               double tol_rel, double tol_abs) {
+  hipStream_t s = M->stream;
+  JacobiArgs a = jacobi_args(xr, xi, ldx, wr, wi, ldw, r, c, tol_rel, tol_abs);
+  const int nb = a.nb;
+  if (jacobi_part(a) > M->part_cap) throw Error(-1, "Jacobi scratch too small");
+  a.part = M->part;
   a.rotated = M->counter;
   row_norms(xr, xi, ldx, r, c, M->norms, s);
   negligible_norm2(M->norms, r, M->info_d + 6, s);
@@ -482,6 +501,109 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
   M->failed = true;
   throw Error(-4, "Jacobi SVD did not converge within max_sweeps (rows " + std::to_string(r) + ", columns " +
                       std::to_string(c) + ")");
+}
+
+// run_jacobi on a group of independent matrices at once (each JacobiArgs
+// with its own part scratch): every round launches the pair Grams and the
+// rotations of all matrices still rotating, so that small matrices share the
+// device instead of running their latency-bound rounds one after the other.
+// Every matrix takes the launch shape, tolerances and sweeps it would take
+// alone, so its result is the same bit for bit.
+void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab) {
+  hipStream_t s = M->stream;
+  const int count = (int)tab.size();
+  // device layout in u_batch: JacobiArgs[count], gram_first[count+1], rot_first[count+1],
+  // active[count], counts[count], tiny2[count]
+  const size_t need = sizeof(JacobiArgs) * count + 2 * sizeof(int64_t) * (count + 1) + 2 * sizeof(int) * count +
+                      sizeof(double) * count + 64;
+  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "U(1) SVD: batched Jacobi tables exceed their buffer");
+  char* base = static_cast<char*>(M->u_batch);
+  JacobiArgs* d_tab = reinterpret_cast<JacobiArgs*>(base);
+  int64_t* d_gram = reinterpret_cast<int64_t*>(d_tab + count);
+  int64_t* d_rot = d_gram + (count + 1);
+  int* d_active = reinterpret_cast<int*>(d_rot + (count + 1));
+  unsigned int* d_counts = reinterpret_cast<unsigned int*>(d_active + count);
+  double* d_tiny2 = reinterpret_cast<double*>(reinterpret_cast<char*>(d_counts + count) +
+                                              ((8 - (reinterpret_cast<uintptr_t>(d_counts + count) & 7)) & 7));
+  std::vector<int64_t>& first = M->h_first;
+  first.assign(2 * (count + 1), 0);
+  int max_nb = 0;
+  for (int i = 0; i < count; ++i) {
+    JacobiArgs& a = tab[i];
+    row_norms(a.xr, a.xi, a.ldx, a.r, a.c, M->norms, s);
+    negligible_norm2(M->norms, a.r, d_tiny2 + i, s);
+    a.tiny2 = d_tiny2 + i;
+    a.rotated = d_counts + i;
+    if (a.wr) set_identity(a.wr, a.wi, a.ldw, a.r, s);
+    first[i + 1] = first[i] + (int64_t)(a.nb / 2) * a.nsplit;
+    first[count + 1 + i + 1] = first[count + 1 + i] + (int64_t)(a.nb / 2) * a.nuchunks;
+    max_nb = std::max(max_nb, a.nb);
+  }
+  {
+    // the absolute floor of run_jacobi, per matrix
+    std::vector<double> t2(count);
+    PTEBD_HIP(hipMemcpyAsync(t2.data(), d_tiny2, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) tab[i].tol_abs = std::max(tab[i].tol_abs, 256.0 * t2[i]);
+  }
+  PTEBD_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(JacobiArgs) * count, hipMemcpyHostToDevice, s));
+  PTEBD_HIP(hipMemcpyAsync(d_gram, first.data(), sizeof(int64_t) * 2 * (count + 1), hipMemcpyHostToDevice, s));
+  std::vector<int>& act = M->h_active;
+  act.assign(count, 1);
+  std::vector<unsigned int>& cnt = M->h_counts;
+  cnt.assign(count, 0);
+  const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : kDefaultSweeps;
+  int rounds = max_nb - 1;
+  for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+    PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    PTEBD_HIP(hipMemsetAsync(d_counts, 0, sizeof(unsigned int) * count, s));
+    for (int t = 0; t < rounds; ++t)
+      jacobi_round_batched(d_tab, d_gram, first[count], d_rot, first[2 * (count + 1) - 1], count, d_active, t, s);
+    PTEBD_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    rounds = 0;
+    for (int i = 0; i < count; ++i) {
+      if (act[i] && cnt[i] == 0) act[i] = 0;
+      if (act[i]) rounds = std::max(rounds, tab[i].nb - 1);
+    }
+    if (debug_enabled()) {
+      std::string line;
+      for (int i = 0; i < count; ++i)
+        if (act[i]) line += " " + std::to_string(tab[i].r) + "x" + std::to_string(tab[i].c) + ":" +
+                            std::to_string(cnt[i]);
+      std::fprintf(stderr, "[ptebd] batched one-sided jacobi sweep=%d rotating(r x c:pairs)%s\n", sweep,
+                   line.c_str());
+    }
+    if (rounds == 0) {
+      M->last_sweeps = sweep;
+      M->total_sweeps += sweep;
+      return;
+    }
+  }
+  M->failed = true;
+  throw Error(-4, "batched Jacobi SVD did not converge within max_sweeps (" + std::to_string(count) + " sectors)");
+}
+
+// run_jacobi on every matrix of tab, in groups whose pair Grams fit the
+// scratch together.
+void run_jacobi_batched(tebd_mps* M, std::vector<JacobiArgs>& tab) {
+  size_t i0 = 0;
+  while (i0 < tab.size()) {
+    std::vector<JacobiArgs> group;
+    int64_t poff = 0;
+    size_t i1 = i0;
+    while (i1 < tab.size()) {
+      const int64_t need = jacobi_part(tab[i1]);
+      if (need > M->part_cap) throw Error(-1, "Jacobi scratch too small");
+      if (poff + need > M->part_cap) break;
+      group.push_back(tab[i1]);
+      group.back().part = M->part + poff;
+      poff += need;
+      ++i1;
+    }
+    run_jacobi_group(M, group);
+    i0 = i1;
+  }
 }
 
 // Truncated SVD of diag(rs) A.  Writes the kept normalised singular values
@@ -1179,7 +1301,9 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
   PTEBD_HIP(hipMemcpyAsync(M->u_idx, M->h_idx.data(), sizeof(int) * io, hipMemcpyHostToDevice, s));
   const int64_t idx_end = io;
   // gather every sector block (Gram: as it stands; Jacobi: rows, or the
-  // conjugate transpose for a tall block) and decompose it
+  // conjugate transpose for a tall block); the Jacobi route decomposes all
+  // sectors in one batched run
+  std::vector<JacobiArgs> jac;
   for (Sector* S : secs) {
     const int* rows = M->u_idx + S->ro;
     const int* cols = M->u_idx + S->co;
@@ -1191,13 +1315,14 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       if (S->left) {
         // rows of the block become sigma_i v_i^+
         gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, S->n, s);
-        if (S->m > 1) run_jacobi(M, br, bi, S->n, nullptr, nullptr, 0, S->m, S->n, jacobi_tol(S->n), 0.0);
+        if (S->m > 1)
+          jac.push_back(jacobi_args(br, bi, S->n, nullptr, nullptr, 0, S->m, S->n, jacobi_tol(S->n), 0.0));
       } else {
         // rows of the conjugate transpose (n x m) become sigma_i u_i^+; the
         // accumulated rotations are the rows v_i^+
         gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 1, br, bi, S->m, s);
         if (S->n > 1)
-          run_jacobi(M, br, bi, S->m, wr, wi, S->n, S->n, S->m, jacobi_tol(S->m), 0.0);
+          jac.push_back(jacobi_args(br, bi, S->m, wr, wi, S->n, S->n, S->m, jacobi_tol(S->m), 0.0));
         else
           set_identity(wr, wi, 1, 1, s);
       }
@@ -1205,6 +1330,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       gather_block(in.ar, in.ai, in.lda, in.rs, in.rdiv, rows, S->m, cols, S->n, 0, br, bi, S->n, s);
     }
   }
+  if (!jac.empty()) run_jacobi_batched(M, jac);
   // The Gram matrix of every sector, packed r x r blocks.
   auto sector_grams = [&]() {
     for (Sector* S : secs) {

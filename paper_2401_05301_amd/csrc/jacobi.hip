@@ -40,14 +40,15 @@ __device__ __forceinline__ void round_pair(int nb, int t, int p, int& I, int& J)
 __device__ __forceinline__ int pair_row(int I, int J, int k) { return k < JB ? I * JB + k : J * JB + (k - JB); }
 
 // ------------------------------------------------------------ partial Grams
-// grid (nb/2, nsplit); part layout per (pair, split): [tile aa, ab, bb][re, im][16*16]
-__global__ __launch_bounds__(256) void jac_gram(JacobiArgs a, int round) {
-  __shared__ double red[4][3][2][256];
+// One work-group per (pair, column split); part layout per (pair, split):
+// [tile aa, ab, bb][re, im][16*16]
+__device__ __forceinline__ void jac_gram_body(const JacobiArgs& a, int round, int pair, int split,
+                                              double (*red)[3][2][256]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int I, J;
-  round_pair(a.nb, round, blockIdx.x, I, J);
+  round_pair(a.nb, round, pair, I, J);
   const int chunk = ((a.c + a.nsplit - 1) / a.nsplit + 15) / 16 * 16;
-  const int cb = blockIdx.y * chunk;
+  const int cb = split * chunk;
   const int ce = min(a.c, cb + chunk);
   const int ra = I * JB + (lane & 15), rb = J * JB + (lane & 15);
   const bool va = ra < a.r, vb = rb < a.r;
@@ -97,23 +98,38 @@ __global__ __launch_bounds__(256) void jac_gram(JacobiArgs a, int round) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) red[wave][t][ri][acc_row(lane, e) * 16 + (lane & 15)] = g[t][ri][e];
   __syncthreads();
-  double* out = a.part + ((int64_t)blockIdx.x * a.nsplit + blockIdx.y) * 1536;
+  double* out = a.part + ((int64_t)pair * a.nsplit + split) * 1536;
   for (int idx = threadIdx.x; idx < 1536; idx += 256) {
     const int t = idx / 512, ri = (idx / 256) & 1, el = idx & 255;
     out[idx] = ((red[0][t][ri][el] + red[1][t][ri][el]) + red[2][t][ri][el]) + red[3][t][ri][el];
   }
 }
 
+// grid (nb/2, nsplit)
+__global__ __launch_bounds__(256) void jac_gram(JacobiArgs a, int round) {
+  __shared__ double red[4][3][2][256];
+  jac_gram_body(a, round, blockIdx.x, blockIdx.y, red);
+}
+
 // ------------------------------------------------- pair eigensolve + update
-__global__ __launch_bounds__(256) void jac_rotate(JacobiArgs a, int round) {
-  __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
-  __shared__ double rot[16][4];
+struct RotLds {
+  double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];
+  double rot[16][4];
+};
+
+// One work-group per (pair, column chunk of the update).
+__device__ __forceinline__ void jac_rotate_body(const JacobiArgs& a, int round, int pair, int chunk_id, RotLds& L) {
+  auto& Cr = L.Cr;
+  auto& Ci = L.Ci;
+  auto& Qr = L.Qr;
+  auto& Qi = L.Qi;
+  auto& rot = L.rot;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int I, J;
-  round_pair(a.nb, round, blockIdx.x, I, J);
+  round_pair(a.nb, round, pair, I, J);
 
   // 1. sum the partial Grams in a fixed order
-  const double* part = a.part + (int64_t)blockIdx.x * a.nsplit * 1536;
+  const double* part = a.part + (int64_t)pair * a.nsplit * 1536;
   for (int idx = tid; idx < PR * PR; idx += 256) {
     const int p = idx / PR, q = idx % PR;
     int t, pp, qq;
@@ -150,7 +166,7 @@ __global__ __launch_bounds__(256) void jac_rotate(JacobiArgs a, int round) {
     }
   }
   if (!__syncthreads_or(need)) return;
-  if (blockIdx.y == 0 && tid == 0) atomicAdd(a.rotated, 1u);
+  if (chunk_id == 0 && tid == 0) atomicAdd(a.rotated, 1u);
 
   // 3. cyclic Jacobi on the 32 x 32 Hermitian pair matrix
   for (int sweep = 0; sweep < 12; ++sweep) {
@@ -237,7 +253,7 @@ __global__ __launch_bounds__(256) void jac_rotate(JacobiArgs a, int round) {
       qai[t][ks] = -Qi[k][p];
     }
   const int total = a.c + (a.wr ? a.r : 0);
-  const int cb = blockIdx.y * a.ucols;
+  const int cb = chunk_id * a.ucols;
   const int ce = min(total, cb + a.ucols);
   for (int j0 = cb + wave * 16; j0 < ce; j0 += 64) {
     const int j = j0 + (lane & 15);
@@ -283,6 +299,47 @@ __global__ __launch_bounds__(256) void jac_rotate(JacobiArgs a, int round) {
         }
       }
   }
+}
+
+// grid (nb/2, nuchunks)
+__global__ __launch_bounds__(256) void jac_rotate(JacobiArgs a, int round) {
+  __shared__ RotLds L;
+  jac_rotate_body(a, round, blockIdx.x, blockIdx.y, L);
+}
+
+// Batched form over independent matrices (one JacobiArgs each in the device
+// table tab): first[i] is the first work-group of matrix i (first[count] the
+// total); a matrix takes part while active[i] != 0 and round < nb_i - 1.
+__device__ __forceinline__ int jac_owner(const int64_t* first, int count, int64_t bid) {
+  int lo = 0, hi = count;   // first[lo] <= bid < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void jac_gram_batched(const JacobiArgs* tab, const int64_t* first, int count,
+                                                        const int* active, int round) {
+  __shared__ double red[4][3][2][256];
+  const int i = jac_owner(first, count, blockIdx.x);
+  const JacobiArgs a = tab[i];
+  if (!active[i] || round >= a.nb - 1) return;
+  const int local = (int)(blockIdx.x - first[i]);
+  jac_gram_body(a, round, local / a.nsplit, local % a.nsplit, red);
+}
+
+__global__ __launch_bounds__(256) void jac_rotate_batched(const JacobiArgs* tab, const int64_t* first, int count,
+                                                          const int* active, int round) {
+  __shared__ RotLds L;
+  const int i = jac_owner(first, count, blockIdx.x);
+  const JacobiArgs a = tab[i];
+  if (!active[i] || round >= a.nb - 1) return;
+  const int local = (int)(blockIdx.x - first[i]);
+  jac_rotate_body(a, round, local / a.nuchunks, local % a.nuchunks, L);
 }
 
 __global__ __launch_bounds__(256) void row_norms_kernel(const double* xr, const double* xi, int64_t ldx,
@@ -437,6 +494,21 @@ void jacobi_round(const JacobiArgs& a, int round, hipStream_t s) {
   {
     ProfScope ps(K_JAC_ROTATE, 0.0, s);
     jac_rotate<<<g2, 256, 0, s>>>(a, round);
+    PTEBD_LAUNCH_CHECK();
+  }
+}
+
+void jacobi_round_batched(const JacobiArgs* tab, const int64_t* gram_first, int64_t gram_total,
+                          const int64_t* rot_first, int64_t rot_total, int count, const int* active, int round,
+                          hipStream_t s) {
+  {
+    ProfScope ps(K_JAC_GRAM, 0.0, s);
+    jac_gram_batched<<<(unsigned)gram_total, 256, 0, s>>>(tab, gram_first, count, active, round);
+    PTEBD_LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps(K_JAC_ROTATE, 0.0, s);
+    jac_rotate_batched<<<(unsigned)rot_total, 256, 0, s>>>(tab, rot_first, count, active, round);
     PTEBD_LAUNCH_CHECK();
   }
 }

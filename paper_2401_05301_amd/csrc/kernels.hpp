@@ -50,6 +50,13 @@ struct JacobiArgs {
   int nuchunks;                             // update work-groups per pair
 };
 void jacobi_round(const JacobiArgs& a, int round, hipStream_t s);
+// One round on each of `count` independent matrices (device table tab;
+// gram_first / rot_first: prefix sums of nb/2 * nsplit and nb/2 * nuchunks,
+// count + 1 entries, totals their last entries).  Matrices with
+// active[i] == 0, or whose sweep has fewer rounds, sit the round out.
+void jacobi_round_batched(const JacobiArgs* tab, const int64_t* gram_first, int64_t gram_total,
+                          const int64_t* rot_first, int64_t rot_total, int count, const int* active, int round,
+                          hipStream_t s);
 
 // ------------------------------------------------- two-sided Hermitian Jacobi
 struct HermArgs {
