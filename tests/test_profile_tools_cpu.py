@@ -40,7 +40,7 @@ def test_mfma_util_summary(tmp_path):
     assert s["launches"] == 2
     assert abs(s["mfma_util_percent_mean"] - 40.0) < 1e-12
     assert abs(s["mfma_util_percent_time_weighted"] - (20.0 * 100 + 60.0 * 300) / 400) < 1e-12
-    assert abs(s["mfma_flops_f64_per_launch"] - 4e9) < 1e-3
+    assert abs(s["mfma_flops_fp64_per_launch"] - 4e9) < 1e-3
     assert abs(s["executed_over_algorithmic"] - 1.0) < 1e-12
     assert abs(s["serialised_rate_TFLOPs"] - 8e9 / 400 / 1e3) < 1e-12
     assert "MfmaUtil" in (tmp_path / "summary.md").read_text()
