@@ -65,22 +65,29 @@ def cpu_baseline(chi: int, L_ref: int, steps_scale: float):
 
 
 def measured_gemm_peak(pt, torch, n: int = 4096):
-    """Square complex FP64 GEMM rate on this device: this library's kernel and
-    torch's complex128 matmul (rocBLAS), n x n x n, 8 n^3 flops each."""
+    """Square complex GEMM rates on this device, n x n x n, 8 n^3 flops each:
+    this library's kernel and torch's matmul (rocBLAS), in complex128 (FP64
+    matrix cores) and complex64 (FP32 matrix cores)."""
     fl = 8.0 * n ** 3
-    ours = fl / (pt.tebd_diag_zgemm_time(n, n, n, pt.FP64, 5) / 1e3) / 1e12
-    a = torch.randn(n, n, dtype=torch.complex128, device="cuda")
-    b = torch.randn(n, n, dtype=torch.complex128, device="cuda")
-    torch.matmul(a, b)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
+
+    def torch_rate(dtype):
+        a = torch.randn(n, n, dtype=dtype, device="cuda")
+        b = torch.randn(n, n, dtype=dtype, device="cuda")
         torch.matmul(a, b)
-    e1.record()
-    torch.cuda.synchronize()
-    lib = fl / (e0.elapsed_time(e1) / 5 / 1e3) / 1e12
-    return {"n": n, "zgemm_kernel_TFLOPs": ours, "rocblas_zgemm_TFLOPs": lib}
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            torch.matmul(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        return fl / (e0.elapsed_time(e1) / 5 / 1e3) / 1e12
+
+    return {"n": n,
+            "zgemm_kernel_TFLOPs": fl / (pt.tebd_diag_zgemm_time(n, n, n, pt.FP64, 5) / 1e3) / 1e12,
+            "rocblas_zgemm_TFLOPs": torch_rate(torch.complex128),
+            "zgemm_kernel_fp32_TFLOPs": fl / (pt.tebd_diag_zgemm_time(n, n, n, pt.FP32, 5) / 1e3) / 1e12,
+            "rocblas_cgemm_TFLOPs": torch_rate(torch.complex64)}
 
 
 def quench_run(pt, torch, args):
