@@ -32,8 +32,9 @@
  * Error behaviour: every call returns a tebd_status; no exception crosses
  * the ABI.  tebd_last_error() returns a thread-local message for the last
  * failing call on the calling thread.  EINVAL leaves the handle untouched.
- * ENOCONV (SVD did not converge within max_sweeps) marks the handle ESTATE:
- * later evolution and measurement calls refuse it.
+ * ENOCONV (SVD did not converge within max_sweeps), and any other error
+ * raised while gates are being applied (the layer is then half applied),
+ * marks the handle ESTATE: later evolution and measurement calls refuse it.
  *
  * Ownership: the library owns all device memory behind an opaque handle
  * (allocated through opts.dev_alloc if given, else hipMalloc).  The caller

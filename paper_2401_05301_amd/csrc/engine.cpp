@@ -1697,11 +1697,18 @@ void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::p
                bool parallel) {
   fill_zero(M->wslots, M->L, M->stream);
   const int nw = parallel ? std::min<int>((int)M->workers.size(), (int)js.size()) : 1;
+  // A gate that fails leaves the layer half applied: the handle is marked
+  // failed whatever the error, so that later calls refuse the state.
   if (nw <= 1) {
     tebd_mps* W = M->workers[0];
-    for (size_t x = 0; x < js.size(); ++x) {
-      W->ledger = M->wslots + js[x];
-      update_gate(M, W, js[x], G[x]);
+    try {
+      for (size_t x = 0; x < js.size(); ++x) {
+        W->ledger = M->wslots + js[x];
+        update_gate(M, W, js[x], G[x]);
+      }
+    } catch (...) {
+      M->failed = true;
+      throw;
     }
   } else {
     // workers start after everything enqueued so far on the handle's stream
@@ -1740,7 +1747,7 @@ void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::p
     PTEBD_HIP(hipEventDestroy(start));
     for (int w = 0; w < nw; ++w)
       if (err[w]) {
-        for (tebd_mps* W : M->workers) M->failed = M->failed || W->failed;
+        M->failed = true;
         std::rethrow_exception(err[w]);
       }
   }
@@ -1767,12 +1774,7 @@ void layer(tebd_mps* M, int group, double tau) {
     js.push_back(j);
     G.push_back(device_gate(M, j, tau));
   }
-  try {
-    run_gates(M, js, G, true);
-  } catch (...) {
-    for (tebd_mps* W : M->workers) M->failed = M->failed || W->failed;
-    throw;
-  }
+  run_gates(M, js, G, true);
 }
 
 void canonicalize(tebd_mps* M) {
@@ -1784,12 +1786,7 @@ void canonicalize(tebd_mps* M) {
     js.push_back(j);
     G.push_back(device_gate(M, j, 0.0));
   }
-  try {
-    run_gates(M, js, G, false);
-  } catch (...) {
-    for (tebd_mps* W : M->workers) M->failed = M->failed || W->failed;
-    throw;
-  }
+  run_gates(M, js, G, false);
 }
 
 void sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
