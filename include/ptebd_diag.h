@@ -43,6 +43,15 @@ tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, const double* A
  * finite), C = A B. */
 tebd_status tebd_diag_zgemm_time(int32_t prec, int32_t m, int32_t n, int32_t k, int32_t reps, double* ms);
 
+/* The gate G = exp(-i h tau) as the library builds it on the host in FP64
+ * (Eq. (1) split into three-site terms h_j, or with supersite = 1 into the
+ * two-super-site terms of super sites (j, j + 1), each diagonalised and
+ * exponentiated).  Host only: no device call is made.  G (planar, n x n
+ * row-major, output index first) must hold 2 n^2 values, n = d^3, or d^4 for
+ * super sites.  EINVAL for an invalid model, j outside 0..L-3 (0..L/2-2 on
+ * the super-site chain of even L >= 4) or a non-finite tau. */
+tebd_status tebd_diag_gate(const tebd_model* m, int32_t supersite, int32_t j, double tau, double* G);
+
 #ifdef __cplusplus
 }
 #endif

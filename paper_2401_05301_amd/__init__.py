@@ -437,10 +437,21 @@ def _load_diag():
 
     _lib.tebd_diag_zgemm_time.restype = ctypes.c_int
     _lib.tebd_diag_zgemm_time.argtypes = [ctypes.c_int32] * 5 + [P(ctypes.c_double)]
+    _lib.tebd_diag_gate.restype = ctypes.c_int
+    _lib.tebd_diag_gate.argtypes = [P(Model), ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P(ctypes.c_double)]
 
 
 _load_diag()
-EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time"]
+EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time", "tebd_diag_gate"]
+
+
+def tebd_diag_gate(model: Model, j: int, tau: float, supersite: bool = False) -> np.ndarray:
+    """The library's host-built gate exp(-i h tau) of window j (super sites
+    (j, j+1) with supersite=True) as a complex n x n array."""
+    n = model.d ** (4 if supersite else 3)
+    g = np.zeros(2 * n * n)
+    _check(_lib.tebd_diag_gate(ctypes.byref(model), int(bool(supersite)), j, tau, _dptr(g)))
+    return (g[:n * n] + 1j * g[n * n:]).reshape(n, n)
 
 
 def tebd_diag_zgemm_time(m: int, n: int, k: int, prec: int = FP64, reps: int = 5) -> float:

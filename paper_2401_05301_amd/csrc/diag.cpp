@@ -1,4 +1,5 @@
 // Diagnostic entry points (include/ptebd_diag.h): one kernel family at a time.
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -176,5 +177,29 @@ extern "C" tebd_status tebd_diag_zgemm_time(int32_t prec, int32_t m, int32_t n, 
   } catch (const ptebd::Error& e) {
     ptebd::set_last_error(e.what());
     return (tebd_status)e.code;
+  }
+}
+
+extern "C" tebd_status tebd_diag_gate(const tebd_model* m, int32_t supersite, int32_t j, double tau, double* G) {
+  if (!m || !G || (supersite != 0 && supersite != 1) || !std::isfinite(tau)) return TEBD_EINVAL;
+  if (m->L < 3 || m->d < 2 || m->d > 8 || !std::isfinite(m->U) || !std::isfinite(m->J) ||
+      !std::isfinite(m->Jnnn) || !std::isfinite(m->K) || !std::isfinite(m->jc))
+    return TEBD_EINVAL;
+  if (supersite ? (m->L % 2 != 0 || m->L < 4 || j < 0 || j + 1 >= m->L / 2) : (j < 0 || j + 2 >= m->L))
+    return TEBD_EINVAL;
+  try {
+    const ptebd::ModelP mp{m->L, m->d, m->U, m->J, m->Jnnn, m->K, m->jc};
+    const ptebd::SpectralGate g = supersite ? ptebd::eig_supersite(mp, j) : ptebd::eig_three_site(mp, j);
+    std::vector<double> re, im;
+    ptebd::gate_matrix(g, tau, re, im);
+    std::memcpy(G, re.data(), sizeof(double) * re.size());
+    std::memcpy(G + re.size(), im.data(), sizeof(double) * im.size());
+    return TEBD_OK;
+  } catch (const ptebd::Error& e) {
+    ptebd::set_last_error(e.what());
+    return (tebd_status)e.code;
+  } catch (const std::bad_alloc&) {
+    ptebd::set_last_error("host allocation failed");
+    return TEBD_ENOMEM;
   }
 }
