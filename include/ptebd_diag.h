@@ -52,6 +52,14 @@ tebd_status tebd_diag_zgemm_time(int32_t prec, int32_t m, int32_t n, int32_t k, 
  * the super-site chain of even L >= 4) or a non-finite tau. */
 tebd_status tebd_diag_gate(const tebd_model* m, int32_t supersite, int32_t j, double tau, double* G);
 
+/* Particle number of every bond index (bosons to the left of the bond) as
+ * mps_init_state infers it with tebd_opts.u1 on a three-site chain of L
+ * sites of dimension d: chi[L + 1] bond dimensions (chi[0] = chi[L] = 1) and
+ * the tensors B in mps_init_state's layout.  q receives chi[0] + ... + chi[L]
+ * integers, bond by bond.  Host only: no device call is made.  EINVAL when an
+ * index is reached by non-zero entries of two particle numbers or by none. */
+tebd_status tebd_diag_bond_charges(int32_t L, int32_t d, const int32_t* chi, const double* B, int32_t* q);
+
 #ifdef __cplusplus
 }
 #endif

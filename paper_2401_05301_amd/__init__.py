@@ -439,10 +439,13 @@ def _load_diag():
     _lib.tebd_diag_zgemm_time.argtypes = [ctypes.c_int32] * 5 + [P(ctypes.c_double)]
     _lib.tebd_diag_gate.restype = ctypes.c_int
     _lib.tebd_diag_gate.argtypes = [P(Model), ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P(ctypes.c_double)]
+    _lib.tebd_diag_bond_charges.restype = ctypes.c_int
+    _lib.tebd_diag_bond_charges.argtypes = [ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double),
+                                            P(ctypes.c_int32)]
 
 
 _load_diag()
-EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time", "tebd_diag_gate"]
+EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time", "tebd_diag_gate", "tebd_diag_bond_charges"]
 
 
 def tebd_diag_gate(model: Model, j: int, tau: float, supersite: bool = False) -> np.ndarray:
@@ -452,6 +455,23 @@ def tebd_diag_gate(model: Model, j: int, tau: float, supersite: bool = False) ->
     g = np.zeros(2 * n * n)
     _check(_lib.tebd_diag_gate(ctypes.byref(model), int(bool(supersite)), j, tau, _dptr(g)))
     return (g[:n * n] + 1j * g[n * n:]).reshape(n, n)
+
+
+def tebd_diag_bond_charges(B: Sequence[np.ndarray]):
+    """Particle numbers of every bond index as the library infers them from
+    the tensors B[i] (chi_i, d, chi_{i+1}) of a three-site chain."""
+    L, d = len(B), B[0].shape[1]
+    chi = np.array([1] + [b.shape[2] for b in B], dtype=np.int32)
+    flat = []
+    for b in B:
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        flat.append(b.real.ravel())
+        flat.append(b.imag.ravel())
+    Bf = np.ascontiguousarray(np.concatenate(flat), dtype=np.float64)
+    q = np.zeros(int(chi.sum()), dtype=np.int32)
+    _check(_lib.tebd_diag_bond_charges(L, d, chi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(Bf),
+                                       q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return np.split(q.astype(np.int64), np.cumsum(chi)[:-1])
 
 
 def tebd_diag_zgemm_time(m: int, n: int, k: int, prec: int = FP64, reps: int = 5) -> float:

@@ -203,3 +203,29 @@ extern "C" tebd_status tebd_diag_gate(const tebd_model* m, int32_t supersite, in
     return TEBD_ENOMEM;
   }
 }
+
+extern "C" tebd_status tebd_diag_bond_charges(int32_t L, int32_t d, const int32_t* chi, const double* B,
+                                              int32_t* q) {
+  if (L < 1 || d < 2 || d > 8 || !chi || !B || !q) return TEBD_EINVAL;
+  if (chi[0] != 1 || chi[L] != 1) return TEBD_EINVAL;
+  for (int b = 0; b <= L; ++b)
+    if (chi[b] < 1) return TEBD_EINVAL;
+  try {
+    tebd_mps M;   // host fields only: no device memory is touched
+    M.L = L;
+    M.d = d;
+    M.qs.resize(d);
+    for (int t = 0; t < d; ++t) M.qs[t] = t;
+    const std::vector<std::vector<int>> Q = ptebd::infer_charges(&M, chi, B);
+    int64_t o = 0;
+    for (const auto& qb : Q)
+      for (int v : qb) q[o++] = v;
+    return TEBD_OK;
+  } catch (const ptebd::Error& e) {
+    ptebd::set_last_error(e.what());
+    return (tebd_status)e.code;
+  } catch (const std::bad_alloc&) {
+    ptebd::set_last_error("host allocation failed");
+    return TEBD_ENOMEM;
+  }
+}
