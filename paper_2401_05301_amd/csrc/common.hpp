@@ -35,6 +35,21 @@ struct ZMat {
   int64_t ld;
 };
 
+// Batched launches over independent matrices: the matrix that owns
+// work-group bid, given first[i], the first work-group of matrix i
+// (first[count] the total; every matrix has at least one work-group).
+__device__ __forceinline__ int batch_owner(const int64_t* first, int count, int64_t bid) {
+  int lo = 0, hi = count;   // first[lo] <= bid < first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 // Sets the thread-local message returned by tebd_last_error().
 void set_last_error(const std::string& msg);
 

@@ -383,18 +383,6 @@ __global__ __launch_bounds__(256) void herm_apply(HermArgs a) {
 // of one SVD.  first[i] is the first work-group of matrix i (first[count] the
 // total); a matrix takes part while active[i] != 0 and round < nb_i - 1 (its
 // own sweep may be shorter than the longest one).
-__device__ __forceinline__ int batch_owner(const int64_t* first, int count, int64_t bid) {
-  int lo = 0, hi = count;   // first[lo] <= bid < first[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= bid)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(kEigThreads) void herm_eig_batched(const HermArgs* tab, const int64_t* first, int count,
                                                                 const int* active, int round) {
   __shared__ double Cr[PR][PR + 1], Ci[PR][PR + 1], Qr[PR][PR + 1], Qi[PR][PR + 1];

@@ -310,22 +310,11 @@ __global__ __launch_bounds__(256) void jac_rotate(JacobiArgs a, int round) {
 // Batched form over independent matrices (one JacobiArgs each in the device
 // table tab): first[i] is the first work-group of matrix i (first[count] the
 // total); a matrix takes part while active[i] != 0 and round < nb_i - 1.
-__device__ __forceinline__ int jac_owner(const int64_t* first, int count, int64_t bid) {
-  int lo = 0, hi = count;   // first[lo] <= bid < first[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= bid)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 __global__ __launch_bounds__(256) void jac_gram_batched(const JacobiArgs* tab, const int64_t* first, int count,
                                                         const int* active, int round) {
   __shared__ double red[4][3][2][256];
-  const int i = jac_owner(first, count, blockIdx.x);
+  const int i = batch_owner(first, count, blockIdx.x);
   const JacobiArgs a = tab[i];
   if (!active[i] || round >= a.nb - 1) return;
   const int local = (int)(blockIdx.x - first[i]);
@@ -335,7 +324,7 @@ __global__ __launch_bounds__(256) void jac_gram_batched(const JacobiArgs* tab, c
 __global__ __launch_bounds__(256) void jac_rotate_batched(const JacobiArgs* tab, const int64_t* first, int count,
                                                           const int* active, int round) {
   __shared__ RotLds L;
-  const int i = jac_owner(first, count, blockIdx.x);
+  const int i = batch_owner(first, count, blockIdx.x);
   const JacobiArgs a = tab[i];
   if (!active[i] || round >= a.nb - 1) return;
   const int local = (int)(blockIdx.x - first[i]);
