@@ -77,6 +77,18 @@ def test_footprint_scales_with_chi():
     # the sector SVD adds its projected-row buffer per worker
     assert pt.mps_footprint(m, pt.make_opts(chi_max=1024, u1=True)) > big
 
+def test_footprint_counts_workers_and_supersites():
+    import paper_2401_05301_amd as pt
+    m = pt.make_model(L=32, d=3, U=2.0, Jnnn=0.1)
+    one = pt.mps_footprint(m, pt.make_opts(chi_max=256, workers=1))
+    four = pt.mps_footprint(m, pt.make_opts(chi_max=256, workers=4))
+    assert one < four
+    # each worker holds one gate workspace on top of the shared state
+    state = one - (four - one) / 3
+    assert 0 < state < one
+    sup = pt.mps_footprint(m, pt.make_opts(chi_max=256, workers=1, supersite=True))
+    assert sup > 0 and sup != one
+
 
 def test_serve_validation_without_gpu():
     import paper_2401_05301_amd as pt
