@@ -12,7 +12,8 @@ model      Eq. (1) Hamiltonian, its exact split into three-site terms and
            the gates exp(-i h_j tau).
 tebd       MPS in (B = Gamma Lambda, Lambda) form, the three-site gate update
            with two truncated SVDs, the second-order (Strang) step over the
-           three commuting gate groups, and local measurement of n_j,
+           three commuting gate groups, the fourth-order step composed of
+           five Strang steps (Suzuki's weights), and local measurement of n_j,
            C_j = <b_j^+ b_{j+1}> and D_j = <b_j^+ b_{j+2}> (Eqs. (4), (7)).
 reference  Independent checks of the above: dense state vectors evolved by
            the same gate layers or by exp(-iHt), the single-particle

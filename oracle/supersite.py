@@ -25,7 +25,7 @@ import numpy as np
 
 from workloads import Model, Trunc
 from . import model as mdl
-from .tebd import MPS, _truncate
+from .tebd import MPS, _truncate, suzuki4_weights
 
 
 def _kron(*ops):
@@ -125,6 +125,13 @@ def step2(mps: MPS, gates: SupersiteGates, dt: float, tr: Trunc) -> None:
             apply_gate2(mps, K, gates(K, tau), tr)
 
 
+def step4_2(mps: MPS, gates: SupersiteGates, dt: float, tr: Trunc) -> None:
+    """Fourth-order step of the super-site chain: five second-order steps
+    with the Suzuki weights of ``oracle.tebd.suzuki4_weights`` (reading C21)."""
+    for w in suzuki4_weights():
+        step2(mps, gates, w * dt, tr)
+
+
 def measure2(mps: MPS, d: int):
     """Physical n_i, C_i = <b_i^+ b_{i+1}>, D_i = <b_i^+ b_{i+2}> of the
     super-site MPS (right-orthonormal gauge, as the three-site oracle)."""
@@ -163,13 +170,16 @@ def measure2(mps: MPS, d: int):
     return n, C, Dd
 
 
-def run2(m: Model, tr: Trunc, dt: float, steps: int, occ):
-    """Evolve the Fock state ``occ`` (even length) and measure after every step."""
+def run2(m: Model, tr: Trunc, dt: float, steps: int, occ, order: int = 2):
+    """Evolve the Fock state ``occ`` (even length) and measure after every
+    step; ``order`` 4 takes fourth-order steps."""
+    if order not in (2, 4):
+        raise ValueError("order must be 2 or 4")
     mps = supersite_product(m.d, occ)
     gates = SupersiteGates(m)
     out = {"n": [], "C": [], "D": [], "w_total": []}
     for _ in range(steps):
-        step2(mps, gates, dt, tr)
+        (step2 if order == 2 else step4_2)(mps, gates, dt, tr)
         n, C, D = measure2(mps, m.d)
         out["n"].append(n)
         out["C"].append(C)

@@ -23,6 +23,7 @@ SVD_JACOBI, SVD_GRAM_EIG = 0, 1
 
 EXPORTS = [
     "tebd_opts_default", "mps_init_cdw", "mps_init_product", "mps_init_state", "tebd_layer", "tebd_step",
+    "tebd_step4",
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
     "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve", "measure_quasi_local",
@@ -84,6 +85,7 @@ def _load():
         "mps_init_state": (st, [P(Model), P(Opts), P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double), P(H)]),
         "tebd_layer": (st, [H, ctypes.c_int32, ctypes.c_double]),
         "tebd_step": (st, [H, ctypes.c_double]),
+        "tebd_step4": (st, [H, ctypes.c_double]),
         "tebd_step_many": (st, [P(H), ctypes.c_int32, P(ctypes.c_double)]),
         "measure_local": (st, [H, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double)]),
         "mps_set_model": (st, [H, P(Model)]),
@@ -199,6 +201,10 @@ def tebd_layer(h, group: int, tau: float):
 
 def tebd_step(h, dt: float):
     _check(_lib.tebd_step(h, dt))
+
+
+def tebd_step4(h, dt: float):
+    _check(_lib.tebd_step4(h, dt))
 
 
 def tebd_step_many(handles, dts):
@@ -366,6 +372,9 @@ class MPS:
 
     def step(self, dt: float):
         tebd_step(self.h, dt)
+
+    def step4(self, dt: float):
+        tebd_step4(self.h, dt)
 
     def measure(self):
         return measure_local(self.h, self.L)

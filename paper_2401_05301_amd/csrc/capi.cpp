@@ -123,6 +123,22 @@ tebd_status usable(const tebd_mps* M) {
   return TEBD_OK;
 }
 
+// One second-order (Strang) step of the handle's chain.
+void strang(tebd_mps* M, double dt) {
+  const double h = 0.5 * dt;
+  if (M->super) {   // A(dt/2) B(dt) A(dt/2), A = even K, B = odd K
+    ptebd::layer(M, 0, h);
+    ptebd::layer(M, 1, dt);
+    ptebd::layer(M, 0, h);
+    return;
+  }
+  ptebd::layer(M, 0, h);
+  ptebd::layer(M, 1, h);
+  ptebd::layer(M, 2, dt);
+  ptebd::layer(M, 1, h);
+  ptebd::layer(M, 0, h);
+}
+
 }  // namespace
 
 extern "C" {
@@ -204,19 +220,19 @@ tebd_status tebd_step(tebd_mps* M, double dt) {
   if (st) return st;
   if (!std::isfinite(dt)) return fail(TEBD_EINVAL, "dt must be finite");
   ProfBind pb(M);
+  return guard([&] { strang(M, dt); });
+}
+
+tebd_status tebd_step4(tebd_mps* M, double dt) {
+  tebd_status st = usable(M);
+  if (st) return st;
+  if (!std::isfinite(dt)) return fail(TEBD_EINVAL, "dt must be finite");
+  ProfBind pb(M);
   return guard([&] {
-    const double h = 0.5 * dt;
-    if (M->super) {   // A(dt/2) B(dt) A(dt/2), A = even K, B = odd K
-      ptebd::layer(M, 0, h);
-      ptebd::layer(M, 1, dt);
-      ptebd::layer(M, 0, h);
-      return;
-    }
-    ptebd::layer(M, 0, h);
-    ptebd::layer(M, 1, h);
-    ptebd::layer(M, 2, dt);
-    ptebd::layer(M, 1, h);
-    ptebd::layer(M, 0, h);
+    // Suzuki's fractal weights: 4p + (1 - 4p) = 1 and 4p^3 + (1 - 4p)^3 = 0
+    const double p = 1.0 / (4.0 - std::cbrt(4.0));
+    const double w[5] = {p, p, 1.0 - 4.0 * p, p, p};
+    for (double x : w) strang(M, x * dt);
   });
 }
 

@@ -304,3 +304,45 @@ def test_random_state_layer_gram_subspace_chi256(pt):
     assert g.bond_dims() == om.bond_dims()
     assert abs(g.discarded_weight() - om.w_total) < 1e-10 + 1e-6 * om.w_total
     g.close()
+
+
+def test_fourth_order_step(pt):
+    """tebd_step4 (five Strang steps of Suzuki's weights, reading C21) against
+    the oracle's step4 on the exact-chi L=8 chain with NNN hopping and trap,
+    and on a truncating chi=20 chain."""
+    for m, tr, steps in [
+        (Model(L=8, d=3, U=2.0, J=1.0, Jnnn=0.1, K=0.02), Trunc(chi_max=81, w_max=0.0, eps=1e-14), 6),
+        (Model(L=10, d=3, U=3.0, J=1.0, Jnnn=-0.1, K=0.01), Trunc(chi_max=20, w_max=1e-12, eps=1e-12), 4),
+    ]:
+        note(f"fourth order L={m.L} chi={tr.chi_max} steps={steps}")
+        ores = otebd.run(m, tr, 0.05, steps, order=4)
+        g = pt.MPS.cdw(gpu_model(pt, m), pt.make_opts(tr.chi_max, tr.w_max, tr.eps))
+        for _ in range(steps):
+            g.step4(0.05)
+        n, C, D = g.measure()
+        tol = bar(ores)
+        assert np.abs(n - ores["n"][-1]).max() <= tol
+        assert np.abs(C - ores["C"][-1]).max() <= tol
+        assert np.abs(D - ores["D"][-1]).max() <= tol
+        if tr.w_max > 0:   # exact chi: the eps cut sits among rounding-level values
+            assert g.bond_dims() == ores["mps"].bond_dims()
+        g.close()
+
+
+def test_fourth_order_step_supersite(pt):
+    from oracle import supersite as oss
+    from workloads import cdw_occupations
+    m = Model(L=8, d=2, U=2.0, J=1.0, Jnnn=0.1, K=0.01)
+    tr = Trunc(chi_max=16, w_max=0.0, eps=1e-14)
+    occ = cdw_occupations(m.L, 1)
+    note("fourth order super-site L=8 d=2")
+    ores = oss.run2(m, tr, 0.05, 5, occ, order=4)
+    g = pt.MPS.product(gpu_model(pt, m), pt.make_opts(tr.chi_max, tr.w_max, tr.eps, supersite=True), occ)
+    for _ in range(5):
+        g.step4(0.05)
+    n, C, D = g.measure()
+    tol = bar(ores)
+    assert np.abs(n - ores["n"][-1]).max() <= tol
+    assert np.abs(C - ores["C"][-1]).max() <= tol
+    assert np.abs(D - ores["D"][-1]).max() <= tol
+    g.close()

@@ -73,6 +73,22 @@ def test_supersite_and_three_site_agree_to_trotter_order():
     assert abs(np.sum(r2["n"][-1]) - L / 2) < 1e-12
 
 
+def test_supersite_fourth_order_step():
+    """Fourth-order super-site steps converge as dt^4 to exp(-iHt)."""
+    L, d, t = 6, 3, 0.6
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.02)
+    occ = cdw_occupations(L, 1)
+    from oracle import reference as ref
+    ex = ref.exact_evolve(m, ref.cdw_vector(m, 1), t)
+    n_ex, C_ex, _ = ref.observables(ex, L, d)
+    e = []
+    for dt in (0.1, 0.05):
+        r = ss.run2(m, EXACT, dt, int(round(t / dt)), occ, order=4)
+        e.append(max(np.abs(r["n"][-1] - n_ex).max(), np.abs(r["C"][-1] - C_ex).max()))
+    assert e[1] < 1e-7
+    assert 13.0 < e[0] / e[1] < 19.0, e[0] / e[1]
+
+
 def test_supersite_truncation_conserves_norm_and_number():
     L, d = 12, 3
     m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)

@@ -91,6 +91,35 @@ def test_trotter_error_with_nnn_and_trap():
     assert 3.3 < e[0] / e[1] < 4.7
 
 
+def test_suzuki_weights_closed_form():
+    """The fourth-order weights sum to one and their cubes to zero (the
+    condition that removes the third-order term of a symmetric step)."""
+    w = tebd.suzuki4_weights()
+    assert len(w) == 5 and w == w[::-1]
+    assert abs(sum(w) - 1.0) < 1e-15
+    assert abs(sum(x ** 3 for x in w)) < 1e-15
+    assert w[2] < 0 < w[0]
+
+
+def test_trotter_error_is_fourth_order():
+    """Fourth-order steps against exp(-iHt): halving dt divides the error by
+    about 16 (a wrong weight would leave the second-order factor 4)."""
+    m = Model(L=6, d=3, U=2.0, J=1.0, Jnnn=-0.12, K=0.05, jc=3.5)
+    t = 0.6
+    psi_ex = ref.exact_evolve(m, ref.cdw_vector(m), t)
+    n_ex, C_ex, D_ex = ref.observables(psi_ex, m.L, m.d)
+    e = []
+    for dt in (0.1, 0.05):
+        res = tebd.run(m, EXACT, dt, int(round(t / dt)), order=4)
+        e.append(max(max_err(res["n"][-1], n_ex), max_err(res["C"][-1], C_ex),
+                     max_err(res["D"][-1], D_ex)))
+    assert e[1] < 1e-7
+    assert 13.0 < e[0] / e[1] < 19.0, e[0] / e[1]
+    # the second-order step at the same dt is orders of magnitude worse
+    r2 = tebd.run(m, EXACT, 0.05, int(round(t / 0.05)))
+    assert max_err(r2["n"][-1], n_ex) > 100 * e[1]
+
+
 # --------------------------------------------------- P3: free fermions (d = 2)
 def test_hard_core_matches_free_fermion_propagator():
     m = Model(L=12, d=2, U=7.0, J=1.0, Jnnn=0.0, K=0.005)
