@@ -5,10 +5,18 @@ One timed "step" is one second-order Trotter step of the whole chain (five
 commuting layers, 104 three-site gate updates at L = 64) followed by the local
 measurement of n_i, <b+_i b_{i+1}> and <b+_i b_{i+2}>, on a synthetic state of
 the bulk chi = 1024 workload (L = 64, d = 5, U = 2, J_NNN = 0.1, K = 0,
-dt = 0.01).  The state, the gates and all workspace are resident in HBM before
-the timed region starts.  Prints one JSON line on stdout; progress on stderr.
+dt = 0.01, w_max = 1e-12).  The state, the gates and all workspace are
+resident in HBM before the timed region starts.  Prints one JSON line on
+stdout; progress on stderr.
 
-    python bench.py [--steps K] [--warmup W] [--svd gram|jacobi] [--prec fp64|fp32|split]
+A step takes tens of seconds at chi = 1024, so the run is bounded by wall
+clock: at most one warmup step, then timed steps while they fit in
+--budget seconds (at least one); the JSON reports the steps actually run and
+the ones requested.  Kernel timing (HIP events per launch) is switched on
+only for one extra step after the timed region, which supplies the roofline
+and the per-kernel breakdown.
+
+    python bench.py [--steps K] [--warmup W] [--budget S] [--svd gram|jacobi] [--prec fp64|fp32|split]
 """
 from __future__ import annotations
 
@@ -24,7 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "3-site TEBD gate-updates/s at χ=1024,d=5 (MFMA roofline %); quench p50/p99"
 PEAK_FP64 = 78.6      # TFLOP/s, MI355X dense FP64 matrix
-F_GU = 7.79e12        # algorithmic flops of one bulk gate update at chi = 1024, d = 5
+PEAK_FP32 = 157.3     # TFLOP/s, MI355X dense FP32 matrix
 
 
 def log(msg: str):
@@ -36,10 +44,32 @@ def gate_updates_per_step(L: int) -> int:
     return sum(len(range(g, L - 2, 3)) for g, _ in layers)
 
 
-def cpu_baseline(chi: int, L_ref: int, steps_scale: float):
+def unit_flops(chi: int = 1024, d: int = 5):
+    """Algorithmic flops of one bulk gate update (all four bonds at chi), by
+    term: theta assembly, gate, and per SVD the Gram product, the
+    tridiagonal reduction, the back-transformation of the kept k = chi
+    eigenvectors and the projection onto them (complex 8 flop per
+    multiply-add, Hermitian products 4 m^2 n).  The GEMM-shaped terms are
+    what the GEMM kernel's roofline is credited with."""
+    m1, n1 = chi * d, d * d * chi
+    m2 = n2 = chi * d
+    k = chi
+    t = {
+        "theta": 8.0 * chi ** 3 * (d ** 2 + d ** 3),
+        "gate": 8.0 * d ** 6 * chi ** 2,
+        "svd1_gram": 4.0 * m1 * m1 * n1, "svd1_tri": 16.0 / 3.0 * m1 ** 3,
+        "svd1_back": 8.0 * m1 * m1 * k, "svd1_project": 8.0 * k * m1 * n1,
+        "svd2_gram": 4.0 * m2 * m2 * n2, "svd2_tri": 16.0 / 3.0 * m2 ** 3,
+        "svd2_back": 8.0 * m2 * m2 * k, "svd2_project": 8.0 * k * m2 * n2,
+    }
+    total = sum(t.values())
+    gemm = total - t["svd1_tri"] - t["svd2_tri"]
+    return total, gemm, t
+
+
+def cpu_baseline(chi: int):
     """Time the FP64 CPU oracle on one bulk gate update at bond dimension chi
     and scale its rate by (chi / 1024)^3 to the chi = 1024 unit."""
-    import numpy as np
     from oracle import model as mdl
     from oracle import tebd as otebd
     from workloads import Model, Trunc, random_mps
@@ -60,8 +90,9 @@ def cpu_baseline(chi: int, L_ref: int, steps_scale: float):
     rate = (1.0 / dt) * (chi / 1024.0) ** 3
     return {"value": rate, "unit": "gate-updates/s", "cores": threads or os.cpu_count(), "kind": "oracle",
             "sample": (f"one bulk gate update (bonds {chi},{chi},{chi},{chi}, d=5) of the same Hamiltonian on a "
-                       f"random right-orthonormal L=14 chain took {dt:.1f} s; rate scaled by ({chi}/1024)^3 "
-                       f"to the chi=1024 unit")}
+                       f"random right-orthonormal L=14 chain took {dt:.1f} s; its rate is scaled by "
+                       f"({chi}/1024)^3 to the chi=1024 unit (the oracle's cost is cubic in chi), since one "
+                       f"chi=1024 gate update takes minutes in the oracle")}
 
 
 def measured_gemm_peak(pt, torch, n: int = 4096):
@@ -99,8 +130,9 @@ def quench_run(pt, torch, args):
     cfg = CONFIGS["batched_L64_chi512"]
     m, tr, dt = cfg["model"], cfg["trunc"], cfg["dt"]
     svd = {"gram": pt.SVD_GRAM_EIG, "jacobi": pt.SVD_JACOBI}[args.svd]
+    eps = max(tr.eps, pt.GRAM_EPS_MIN) if svd == pt.SVD_GRAM_EIG else tr.eps
     stream = torch.cuda.Stream()
-    opts = pt.make_opts(tr.chi_max, tr.w_max, tr.eps, svd=svd, stream=stream.cuda_stream, workers=args.workers,
+    opts = pt.make_opts(tr.chi_max, tr.w_max, eps, svd=svd, stream=stream.cuda_stream, workers=args.workers,
                         u1=args.u1)
     g = pt.MPS.cdw(pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), opts)
     g.prepare(dt)
@@ -122,18 +154,19 @@ def quench_run(pt, torch, args):
         "warmup": 0, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batched_L64_chi512", "L": m.L, "d": m.d, "U": m.U, "Jnnn": m.Jnnn, "K": m.K,
-                   "jc": m.centre(), "chi_max": tr.chi_max, "w_max": tr.w_max, "dt": dt, "svd": args.svd,
-                   "u1": bool(args.u1)},
+                   "jc": m.centre(), "chi_max": tr.chi_max, "w_max": tr.w_max, "eps": eps, "dt": dt,
+                   "svd": args.svd, "u1": bool(args.u1)},
         "max_bond_per_step": chis,
         "seconds_per_step": [round(t, 4) for t in times],
         "discarded_weight": g.discarded_weight(),
+        "trunc_rule_counts": g.trunc_stats(),
         "n_total": float(np.sum(n)),
     }
     g.close()
     print(json.dumps(out), flush=True)
 
 
-def u1_sample(pt, torch, args):
+def u1_sample(pt, torch, args, eps):
     """One timed Strang step of the same chain (L, d = 5, chi) with U(1)
     sectors: a random state of L/2 bosons (sector width sigma), canonicalised,
     tebd_opts.u1 = 1, Gram route."""
@@ -143,7 +176,7 @@ def u1_sample(pt, torch, args):
     L, d, chi = args.L, mdl.d, args.chi
     B, lam, _ = random_mps_u1(L, d, chi, L // 2, seed=args.seed, tau=args.tau, sigma=args.sigma, bias=args.bias)
     stream = torch.cuda.Stream()
-    opts = pt.make_opts(chi, 1e-12, 1e-12, svd=pt.SVD_GRAM_EIG, stream=stream.cuda_stream, workers=args.workers,
+    opts = pt.make_opts(chi, 1e-12, eps, svd=pt.SVD_GRAM_EIG, stream=stream.cuda_stream, workers=args.workers,
                         u1=True)
     g = pt.MPS.from_tensors(pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre()), opts, B, lam)
     del B, lam
@@ -182,7 +215,7 @@ def measured_traffic():
     return t["traffic_bytes_per_launch"]
 
 
-def serving_sample(pt, n: int, scale: float):
+def serving_sample(pt, n: int, scale: float, eps: float):
     """Quench requests of the serving workload (Poisson arrivals, L in
     {16..64}, U in [2, 10], K in [0, 0.01], J_NNN = 0.1, dt = 0.01), with the
     small bond caps {16, 32, 64} and each horizon scaled by `scale`, served
@@ -197,7 +230,7 @@ def serving_sample(pt, n: int, scale: float):
         reqs.append(dict(model=pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), chi_max=r["chi_max"],
                          dt=r["dt"], steps=steps, arrival=r["arrival"]))
     t0 = time.perf_counter()
-    res = pt.tebd_serve(reqs, max_active=8, svd=pt.SVD_GRAM_EIG)
+    res = pt.tebd_serve(reqs, max_active=8, svd=pt.SVD_GRAM_EIG, eps=eps)
     wall = time.perf_counter() - t0
     if any(x["status"] != 0 for x in res):
         raise RuntimeError("a served request failed: " + str([x["status"] for x in res]))
@@ -212,10 +245,16 @@ def serving_sample(pt, n: int, scale: float):
 
 
 def main():
+    T_START = time.perf_counter()
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3, help="timed steps requested (capped by --budget)")
+    ap.add_argument("--warmup", type=int, default=1, help="warmup steps requested (at most one is run)")
+    ap.add_argument("--budget", type=float, default=100.0,
+                    help="seconds of timed steps: no further step starts once the next would end past it")
+    ap.add_argument("--aux-budget", type=float, default=420.0,
+                    help="auxiliary legs (profiled step, U(1), serving, square GEMM, CPU oracle) start only "
+                         "while the whole run is below this many seconds")
     ap.add_argument("--L", type=int, default=64)
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--svd", choices=["gram", "jacobi"], default="gram")
@@ -224,11 +263,14 @@ def main():
     ap.add_argument("--bias", type=float, default=150.0,
                     help="decay length of the right-index weighting that shapes the canonical Schmidt spectra")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-input", action="store_true",
+                    help="draw the input with numpy on the host (slow at chi=1024) instead of torch on the GPU")
     ap.add_argument("--no-canonicalize", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-chi", type=int, default=512)
     ap.add_argument("--workers", type=int, default=0, help="concurrent gate workers per layer (0: library default)")
     ap.add_argument("--serve", type=int, default=16, help="requests in the serving sample (0: skip it)")
+    ap.add_argument("--no-profile-step", action="store_true", help="skip the profiled step (no roofline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the reference for the HBM counters) and exit")
     ap.add_argument("--quench", action="store_true",
@@ -266,7 +308,7 @@ def main():
     import torch
 
     import paper_2401_05301_amd as pt
-    from workloads import CONFIGS, random_mps, random_mps_u1
+    from workloads import CONFIGS, random_mps, random_mps_device, random_mps_u1
 
     torch.cuda.set_device(0)
     if args.quench:
@@ -279,15 +321,27 @@ def main():
     L, d, chi = args.L, mdl.d, args.chi
     prec = {"fp64": pt.FP64, "fp32": pt.FP32, "split": pt.FP32_SPLIT}[args.prec]
     svd = {"gram": pt.SVD_GRAM_EIG, "jacobi": pt.SVD_JACOBI}[args.svd]
+    w_max = cfg["trunc"].w_max
+    # The Gram route refuses eps below TEBD_GRAM_EPS_MIN; at chi = 1024 the
+    # bond cap sets every cut of this workload (trunc_rule_counts shows it),
+    # so the result is the one eps = 1e-12 would give.
+    eps = pt.GRAM_EPS_MIN if svd == pt.SVD_GRAM_EIG else cfg["trunc"].eps
 
     t0 = time.perf_counter()
     if args.u1:
         B, lam, _ = random_mps_u1(L, d, chi, L // 2, seed=args.seed, tau=args.tau, sigma=args.sigma, bias=args.bias)
-    else:
+        recipe = "random_mps_u1 (numpy)"
+    elif args.cpu_input:
         B, lam = random_mps(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
-    log(f"synthetic input L={L} d={d} chi={chi} u1={args.u1} generated in {time.perf_counter() - t0:.1f} s")
+        recipe = "random_mps (numpy)"
+    else:
+        B, lam = random_mps_device(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        recipe = "random_mps_device (torch on the GPU)"
+    log(f"synthetic input L={L} d={d} chi={chi} u1={args.u1} ({recipe}) generated in {time.perf_counter() - t0:.1f} s")
     model = pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, mdl.centre())
-    opts = pt.make_opts(chi, 1e-12, 1e-12, prec=prec, svd=svd, stream=stream.cuda_stream, workers=args.workers,
+    opts = pt.make_opts(chi, w_max, eps, prec=prec, svd=svd, stream=stream.cuda_stream, workers=args.workers,
                         u1=args.u1)
     keep = pt.torch_allocator(opts, stream=stream)
     g = pt.MPS.from_tensors(model, opts, B, lam)
@@ -297,94 +351,146 @@ def main():
         t0 = time.perf_counter()
         g.canonicalize()
         g.sync()
-        log(f"canonicalised by an identity sweep in {time.perf_counter() - t0:.1f} s, bonds {g.bond_dims()}")
+        log(f"canonicalised by an identity sweep in {time.perf_counter() - t0:.1f} s, max bond {max(g.bond_dims())}")
     g.prepare(dt)
     nsteps_gu = gate_updates_per_step(L)
 
-    for w in range(args.warmup):
+    warm_run, t_warm = 0, None
+    for w in range(min(args.warmup, 1)):
+        t0 = time.perf_counter()
         g.step(dt)
         g.measure()
-        log(f"warmup step {w + 1}/{args.warmup} done")
+        t_warm = time.perf_counter() - t0
+        warm_run += 1
+        log(f"warmup step {w + 1} done in {t_warm:.1f} s")
 
     w0 = g.discarded_weight()
     sweeps0 = pt.mps_sweep_stats(g.h)[1]
-    g.profile(True)
+    rules0 = g.trunc_stats()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for k in range(args.steps):
+    steps_run = 0
+    est = t_warm
+    for k in range(max(1, args.steps)):
+        if steps_run >= 1 and est is not None and (time.perf_counter() - t0) + est > args.budget:
+            break
+        ts = time.perf_counter()
         g.step(dt)
         n, C, D = g.measure()
+        steps_run += 1
+        est = time.perf_counter() - ts
         log(f"timed step {k + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)")
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     dev_ms = e0.elapsed_time(e1)
-    prof = g.profile_read()
-    g.profile(False)
     w1 = g.discarded_weight()
     sweeps1 = pt.mps_sweep_stats(g.h)[1]
+    rules1 = g.trunc_stats()
     chis = g.bond_dims()
+    lam_min = min(float(np.min(g.lam(b))) / float(np.max(g.lam(b))) for b in range(1, L) if chis[b] > 1)
 
     secs = dev_ms / 1e3
-    value = nsteps_gu * args.steps / secs
-    # dominant kernel by device time
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    gemm_ms, gemm_n, gemm_fl = prof["gemm_fp64"] if prec == pt.FP64 else prof["gemm_fp32"]
-    achieved = gemm_fl / (gemm_ms / 1e3) / 1e12 if gemm_ms > 0 else 0.0
-    peak = PEAK_FP64 if prec == pt.FP64 else 157.3
-    roof = {"bound": "mfma", "kernel": "zgemm_kernel<0>" if prec == pt.FP64 else "zgemm_kernel<fp32>",
-            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-            "launches": gemm_n, "avg_launch_ms": gemm_ms / max(gemm_n, 1),
-            "flops_per_launch": gemm_fl / max(gemm_n, 1)}
-    if prec == pt.FP64 and L == 64 and chi == 1024 and args.svd == "gram" and not args.u1:
-        roof["traffic"] = measured_traffic()
+    value = nsteps_gu * steps_run / secs
+    F_GU, F_GEMM, terms = unit_flops(1024, 5)
+    peak = PEAK_FP64 if prec == pt.FP64 else PEAK_FP32
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "gate-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dev_ms / args.steps,
+        "steps": steps_run,
+        "warmup": warm_run,
+        "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget},
+        "ms_per_step": dev_ms / steps_run,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == pt.FP64 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "bulk_L64_chi1024" + ("_u1" if args.u1 else ""), "L": L, "d": d, "chi_max": chi, "U": mdl.U, "J": mdl.J,
-                   "Jnnn": mdl.Jnnn, "K": mdl.K, "dt": dt, "svd": args.svd, "theta_gate_prec": args.prec,
-                   "gate_updates_per_step": nsteps_gu, "w_max": 1e-12, "eps": 1e-12,
+        "config": {"workload": "bulk_L64_chi1024" + ("_u1" if args.u1 else ""), "L": L, "d": d, "chi_max": chi,
+                   "U": mdl.U, "J": mdl.J, "Jnnn": mdl.Jnnn, "K": mdl.K, "dt": dt, "svd": args.svd,
+                   "theta_gate_prec": args.prec, "gate_updates_per_step": nsteps_gu, "w_max": w_max, "eps": eps,
                    "u1": bool(args.u1),
-                   "input": (f"random right-orthonormal MPS (seed {args.seed}, right-index weight exp(-b/{args.bias:g})"
+                   "input": (f"{recipe}: random right-orthonormal MPS (seed {args.seed}, right-index weight "
+                             f"exp(-b/{args.bias:g})"
                              + (f", {L // 2} bosons, sector width sigma {args.sigma:g}" if args.u1 else "") + "), "
                              + ("canonicalised by an identity sweep" if not args.no_canonicalize else "as generated"))},
-        "roofline": roof,
         "path_roofline": {"unit_flops": F_GU, "achieved_TFLOPs": F_GU * value / 1e12, "peak": PEAK_FP64,
                           "frac": F_GU * value / 1e12 / PEAK_FP64,
                           # with --u1 the sector SVDs do far less than the dense count F_GU: the
                           # figure is then a dense-equivalent rate, not work done
                           "dense_equivalent": bool(args.u1)},
-        "measured_square_gemm": None if args.no_square_gemm else measured_gemm_peak(pt, torch),
         "wall_s": wall,
-        "kernel_ms": {k: v[0] for k, v in prof.items()},
-        "dominant_kernel_class": dom[0],
-        "discarded_weight_per_step": (w1 - w0) / args.steps,
-        "jacobi_sweeps_per_gate_update": (sweeps1 - sweeps0) / (nsteps_gu * args.steps),
+        "discarded_weight_per_step": (w1 - w0) / steps_run,
+        "trunc_rule_counts": {k: rules1[k] - rules0[k] for k in rules1},
+        "smallest_kept_lambda_ratio": lam_min,
+        "jacobi_sweeps_per_gate_update": (sweeps1 - sweeps0) / (nsteps_gu * steps_run),
         "max_bond": max(chis),
     }
+
+    def time_left():
+        return time.perf_counter() - T_START < args.aux_budget
+
+    # one more step with per-launch HIP events: kernel breakdown and roofline
+    if not args.no_profile_step and time_left():
+        g.profile(True)
+        tp = time.perf_counter()
+        g.step(dt)
+        g.measure()
+        g.sync()
+        prof = g.profile_read()
+        busy = g.profile_busy()
+        g.profile(False)
+        log(f"profiled step done in {time.perf_counter() - tp:.1f} s")
+        key = "gemm_fp64" if prec == pt.FP64 else "gemm_fp32"
+        gemm_ms, gemm_n, gemm_fl = prof["gemm_fp64"]
+        gemm_busy = busy["gemm_fp64"]
+        # credited: the GEMM-shaped terms of the unit (theta, gate, Gram products,
+        # back-transformation, projections) for the step's gate updates; in the
+        # FP32 theta/gate path those two terms run on the FP32 GEMM instead
+        credited = F_GEMM * nsteps_gu
+        if prec != pt.FP64:
+            credited -= (terms["theta"] + terms["gate"]) * nsteps_gu
+        roof = {"bound": "mfma", "kernel": "zgemm_kernel<FP64>", "achieved": credited / (gemm_ms / 1e3) / 1e12,
+                "peak": PEAK_FP64, "unit": "TFLOP/s", "frac": credited / (gemm_ms / 1e3) / 1e12 / PEAK_FP64,
+                "traffic": None, "launches": gemm_n, "avg_launch_ms": gemm_ms / max(gemm_n, 1),
+                "credited_flops_per_launch": credited / max(gemm_n, 1),
+                "issued_flops_per_launch": gemm_fl / max(gemm_n, 1),
+                "issued_over_credited": gemm_fl / credited,
+                "issued_TFLOPs": gemm_fl / (gemm_ms / 1e3) / 1e12,
+                "busy_ms": gemm_busy, "summed_launch_ms": gemm_ms,
+                "achieved_over_busy_TFLOPs": credited / (gemm_busy / 1e3) / 1e12,
+                "frac_over_busy": credited / (gemm_busy / 1e3) / 1e12 / PEAK_FP64,
+                "note": ("achieved = credited GEMM flops of the profiled step (SURVEY unit terms x gate "
+                         "updates) / summed HIP-event launch time; gate workers run concurrently, so "
+                         "launches overlap: busy_ms is the union of the launch intervals")}
+        if prec == pt.FP64 and L == 64 and chi == 1024 and args.svd == "gram" and not args.u1:
+            roof["traffic"] = measured_traffic()
+        out["roofline"] = roof
+        out["kernel_ms"] = {k: v[0] for k, v in prof.items()}
+        out["kernel_launches"] = {k: v[1] for k, v in prof.items()}
+        out["kernel_busy_ms"] = busy
+        out["dominant_kernel_class"] = max(prof.items(), key=lambda kv: kv[1][0])[0]
+        if key != "gemm_fp64":
+            out["roofline_fp32_gemm"] = {"achieved": (terms["theta"] + terms["gate"]) * nsteps_gu
+                                         / (prof[key][0] / 1e3) / 1e12, "peak": PEAK_FP32}
     g.close()
-    if not args.u1 and not args.no_u1_sample:
+    if not args.no_square_gemm and time_left():
+        out["measured_square_gemm"] = measured_gemm_peak(pt, torch)
+    if not args.u1 and not args.no_u1_sample and time_left():
         log("U(1) sample: one step of the same chain with particle-number sectors")
-        out["u1_sample"] = u1_sample(pt, torch, args)
-    if args.serve > 0:
+        out["u1_sample"] = u1_sample(pt, torch, args, pt.GRAM_EPS_MIN)
+    if args.serve > 0 and time_left():
         log(f"serving sample: {args.serve} requests")
-        out["serving"] = serving_sample(pt, args.serve, args.serve_scale)
-    if not args.no_cpu_baseline:
+        out["serving"] = serving_sample(pt, args.serve, args.serve_scale, pt.GRAM_EPS_MIN)
+    if not args.no_cpu_baseline and time_left():
         log(f"timing the CPU oracle on one chi={args.cpu_chi} gate update")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_chi, L, 1.0)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_chi)
+    out["bench_wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out), flush=True)
 
 

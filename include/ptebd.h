@@ -74,6 +74,15 @@ typedef enum {
   TEBD_SVD_GRAM_EIG = 1  /* Hermitian Gram matrix + block Jacobi eigensolver; faster, squares the condition number */
 } tebd_svd;
 
+/* Smallest relative tolerance eps (tebd_opts.trunc_rel) the Gram route
+ * accepts.  The Gram matrix squares the singular values, so values below
+ * about sqrt(u) s_0 (u = 2^-53) sit at its rounding level and cannot be told
+ * apart from zero; eps >= 1e-6 keeps every cut the rule k_eps makes well
+ * above that level.  With TEBD_SVD_GRAM_EIG a smaller trunc_rel is refused
+ * with TEBD_EINVAL (mps_init_*, mps_footprint, tebd_serve); the one-sided
+ * Jacobi route takes any eps >= 0. */
+#define TEBD_GRAM_EPS_MIN 1e-6
+
 /* Eq. (1): U/2 sum n(n-1) - J sum (b+_j b_{j+1} + h.c.) + K/2 sum (x-jc)^2 n
  *          - Jnnn sum (b+_j b_{j+2} + h.c.);  d = n_max + 1 levels per site. */
 typedef struct {
@@ -84,7 +93,7 @@ typedef struct {
 typedef struct {
   int32_t chi_max;        /* bond cap (>= 1) */
   double trunc_weight;    /* w_max (>= 0) */
-  double trunc_rel;       /* eps (>= 0) */
+  double trunc_rel;       /* eps (>= 0; >= TEBD_GRAM_EPS_MIN with TEBD_SVD_GRAM_EIG) */
   int32_t prec;           /* tebd_precision */
   int32_t svd;            /* tebd_svd */
   int32_t max_sweeps;     /* Jacobi sweep limit; <= 0 selects the default (80) */
@@ -137,11 +146,15 @@ tebd_status mps_init_state(const tebd_model* model, const tebd_opts* opts,
                            const int32_t* chi, const double* B, const double* lam,
                            tebd_mps** out);
 
-/* One commuting layer: every gate g_j with j mod 3 == group, for a time slice
- * tau (exp(-i h_j tau)).  Enqueued on the handle's stream. */
+/* One commuting layer (Sec. I: the gates of a layer act on disjoint sites and
+ * are applied concurrently, as in pTEBD): every gate g_j with j mod 3 ==
+ * group, for a time slice tau (exp(-i h_j tau)).  Enqueued on the handle's
+ * stream. */
 tebd_status tebd_layer(tebd_mps* mps, int32_t group, double tau);
 
-/* One second-order Trotter step: layers (0, dt/2) (1, dt/2) (2, dt) (1, dt/2) (0, dt/2). */
+/* One second-order Trotter step (the appendix on numerical convergence: second-order
+ * pTEBD), as the symmetric splitting over the three commuting groups:
+ * layers (0, dt/2) (1, dt/2) (2, dt) (1, dt/2) (0, dt/2). */
 tebd_status tebd_step(tebd_mps* mps, double dt);
 
 /* One fourth-order step (the appendix on numerical convergence compares
@@ -199,6 +212,12 @@ tebd_status mps_discarded_weight(const tebd_mps* mps, double* w_total);
 /* Number of Jacobi sweeps used by the last SVD and their running total. */
 tebd_status mps_sweep_stats(const tebd_mps* mps, int64_t* last, int64_t* total);
 
+/* Which part of the truncation rule set k, counted over every truncation so
+ * far: counts[0] the bond cap chi_max, counts[1] the weight tolerance k_w,
+ * counts[2] the relative tolerance k_eps, counts[3] none (every value kept).
+ * Ties are counted in that order of precedence. */
+tebd_status mps_trunc_stats(const tebd_mps* mps, int64_t* counts);
+
 /* Device bytes a handle of this model/opts reserves (state + workspace at the bond cap). */
 tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t* bytes);
 
@@ -223,13 +242,20 @@ typedef enum {
 } tebd_kernel_class;
 
 /* enable != 0: clear previous records and time every later kernel launch of
- * the handle with a pair of HIP events on its stream; 0: stop recording. */
+ * the handle with a pair of HIP events on the stream it runs on; 0: stop
+ * recording (the totals stay readable until the next enable). */
 tebd_status mps_profile(tebd_mps* mps, int32_t enable);
 
 /* Totals over the recorded launches of one kernel class (synchronises):
  * device milliseconds, number of launches and algorithmic flops (complex
  * GEMM 8 m n k, Hermitian Gram products 4 m^2 k; 0 for the Jacobi kernels). */
 tebd_status mps_profile_read(tebd_mps* mps, int32_t kclass, double* ms, int64_t* launches, double* flops);
+
+/* Wall milliseconds, since profiling was enabled, during which at least one
+ * recorded launch of the class was running (the union of the launches'
+ * intervals; launches on concurrent gate workers overlap, so this can be
+ * less than the summed device time of mps_profile_read).  Synchronises. */
+tebd_status mps_profile_busy(tebd_mps* mps, int32_t kclass, double* busy_ms);
 
 /* ------------------------------------------------------------------ serving
  * A stream of quench requests (CDW start, Sec. II B; Eq. (1) couplings of

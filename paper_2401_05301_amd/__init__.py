@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libptebd.so")
 TEBD_OK, TEBD_EINVAL, TEBD_ENOMEM, TEBD_EDEVICE, TEBD_ENOCONV, TEBD_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP32_SPLIT = 0, 1, 2
 SVD_JACOBI, SVD_GRAM_EIG = 0, 1
+GRAM_EPS_MIN = 1e-6   # TEBD_GRAM_EPS_MIN: smallest trunc_rel the Gram route accepts
 
 EXPORTS = [
     "tebd_opts_default", "mps_init_cdw", "mps_init_product", "mps_init_state", "tebd_layer", "tebd_step",
@@ -27,7 +28,7 @@ EXPORTS = [
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
     "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve", "measure_quasi_local",
-    "mps_bond_charges",
+    "mps_bond_charges", "mps_trunc_stats", "mps_profile_busy",
 ]
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "herm_eig": 2, "herm_apply": 3, "jac_gram": 4, "jac_rotate": 5}
 
@@ -95,6 +96,7 @@ def _load():
         "mps_site": (st, [H, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int64]),
         "mps_discarded_weight": (st, [H, P(ctypes.c_double)]),
         "mps_sweep_stats": (st, [H, P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "mps_trunc_stats": (st, [H, P(ctypes.c_int64)]),
         "mps_footprint": (st, [P(Model), P(Opts), P(ctypes.c_size_t)]),
         "mps_sync": (st, [H]),
         "mps_free": (st, [H]),
@@ -103,6 +105,7 @@ def _load():
         "mps_canonicalize": (st, [H]),
         "mps_profile": (st, [H, ctypes.c_int32]),
         "mps_profile_read": (st, [H, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_double)]),
+        "mps_profile_busy": (st, [H, ctypes.c_int32, P(ctypes.c_double)]),
         "tebd_serve": (st, [P(Request), ctypes.c_int32, P(ServeOpts), P(ServeResult), P(ctypes.c_double),
                             P(ctypes.c_double), P(ctypes.c_double)]),
         "measure_quasi_local": (st, [H, ctypes.c_int32, P(ctypes.c_double)]),
@@ -277,6 +280,14 @@ def mps_sweep_stats(h):
     return a.value, b.value
 
 
+def mps_trunc_stats(h):
+    """Truncations so far by the part of the rule that set k:
+    {"chi_max": .., "w_max": .., "eps": .., "none": ..}."""
+    a = (ctypes.c_int64 * 4)()
+    _check(_lib.mps_trunc_stats(h, a))
+    return {"chi_max": a[0], "w_max": a[1], "eps": a[2], "none": a[3]}
+
+
 def mps_footprint(model: Model, opts: Opts) -> int:
     b = ctypes.c_size_t()
     _check(_lib.mps_footprint(ctypes.byref(model), ctypes.byref(opts), ctypes.byref(b)))
@@ -300,6 +311,13 @@ def mps_profile_read(h, kclass: int):
     ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
     _check(_lib.mps_profile_read(h, kclass, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
     return ms.value, n.value, fl.value
+
+
+def mps_profile_busy(h, kclass: int) -> float:
+    """Wall ms during which at least one launch of the class ran."""
+    b = ctypes.c_double()
+    _check(_lib.mps_profile_busy(h, kclass, ctypes.byref(b)))
+    return b.value
 
 
 def mps_sync(h):
@@ -405,6 +423,9 @@ class MPS:
     def sweeps(self):
         return mps_sweep_stats(self.h)
 
+    def trunc_stats(self):
+        return mps_trunc_stats(self.h)
+
     def sync(self):
         mps_sync(self.h)
 
@@ -419,6 +440,9 @@ class MPS:
 
     def profile_read(self):
         return {name: mps_profile_read(self.h, k) for name, k in KERNEL_CLASSES.items()}
+
+    def profile_busy(self):
+        return {name: mps_profile_busy(self.h, k) for name, k in KERNEL_CLASSES.items()}
 
     def close(self):
         if self.h is not None and self.h.value:
@@ -437,11 +461,12 @@ def _load_diag():
     P = ctypes.POINTER
     _lib.tebd_diag_zgemm.restype = ctypes.c_int
     _lib.tebd_diag_zgemm.argtypes = [ctypes.c_int32] * 6 + [P(ctypes.c_double)] * 5 + [ctypes.c_int32, P(ctypes.c_double)]
-    _lib.tebd_diag_svd.restype = ctypes.c_int
-    _lib.tebd_diag_svd.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double),
-                                   ctypes.c_int32, ctypes.c_double, ctypes.c_double, P(ctypes.c_int32),
-                                   P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
-                                   P(ctypes.c_double), P(ctypes.c_int32)]
+    for name in ("tebd_diag_svd",):
+        f = getattr(_lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
+                      ctypes.c_double, ctypes.c_double, P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double),
+                      P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
 
 
     _lib.tebd_diag_zgemm_time.restype = ctypes.c_int
@@ -528,7 +553,7 @@ def tebd_diag_svd(A: np.ndarray, variant: int = SVD_JACOBI, chi_max: int = 1 << 
     nrm, w = ctypes.c_double(), ctypes.c_double()
     sw = ctypes.c_int32()
     _check(_lib.tebd_diag_svd(variant, m, n, _dptr(pa), min(chi_max, 2 ** 31 - 1), w_max, eps, ctypes.byref(k),
-                              _dptr(s), _dptr(vh), ctypes.byref(nrm), ctypes.byref(w), ctypes.byref(sw)))
+              _dptr(s), _dptr(vh), ctypes.byref(nrm), ctypes.byref(w), ctypes.byref(sw)))
     kk = k.value
     V = (vh[:kk * n] + 1j * vh[kk * n:2 * kk * n]).reshape(kk, n)
     return s[:kk].copy(), V, nrm.value, w.value, sw.value

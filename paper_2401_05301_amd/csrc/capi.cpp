@@ -68,6 +68,10 @@ tebd_status check_opts(const tebd_opts* o, int d) {
   if (!finite(o->trunc_rel) || o->trunc_rel < 0) return fail(TEBD_EINVAL, "trunc_rel must be >= 0");
   if (o->prec < TEBD_FP64 || o->prec > TEBD_FP32_SPLIT) return fail(TEBD_EINVAL, "bad precision");
   if (o->svd < TEBD_SVD_JACOBI || o->svd > TEBD_SVD_GRAM_EIG) return fail(TEBD_EINVAL, "bad svd variant");
+  if (o->svd == TEBD_SVD_GRAM_EIG && !(o->trunc_rel >= TEBD_GRAM_EPS_MIN))
+    return fail(TEBD_EINVAL,
+                "the Gram route resolves singular values down to 1e-6 of the largest: trunc_rel must be >= "
+                "TEBD_GRAM_EPS_MIN (1e-6); use TEBD_SVD_JACOBI for a smaller eps");
   if (o->workers < 0) return fail(TEBD_EINVAL, "workers must be >= 0");
   if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr))
     return fail(TEBD_EINVAL, "dev_alloc and dev_free must be given together");
@@ -378,6 +382,12 @@ tebd_status mps_sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
   return TEBD_OK;
 }
 
+tebd_status mps_trunc_stats(const tebd_mps* M, int64_t* counts) {
+  if (!M || !counts) return fail(TEBD_EINVAL, "NULL argument");
+  ptebd::trunc_stats(M, counts);
+  return TEBD_OK;
+}
+
 tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t* bytes) {
   if (!bytes) return fail(TEBD_EINVAL, "bytes is NULL");
   tebd_status st = check_model(model);
@@ -423,7 +433,10 @@ tebd_status mps_profile(tebd_mps* M, int32_t enable) {
   if (!M) return fail(TEBD_EINVAL, "handle is NULL");
   return guard([&] {
     PTEBD_HIP(hipStreamSynchronize(M->stream));
-    M->prof.clear();
+    if (enable)
+      M->prof.start(M->stream);
+    else
+      M->prof.fold(true);
     M->prof_on = enable != 0;
   });
 }
@@ -432,20 +445,22 @@ tebd_status mps_profile_read(tebd_mps* M, int32_t kclass, double* ms, int64_t* l
   if (!M || !ms || !launches || !flops) return fail(TEBD_EINVAL, "NULL argument");
   if (kclass < 0 || kclass >= ptebd::K_NCLASS) return fail(TEBD_EINVAL, "unknown kernel class");
   return guard([&] {
+    // the handle's stream follows every worker stream at the end of a call
     PTEBD_HIP(hipStreamSynchronize(M->stream));
-    double t = 0.0, f = 0.0;
-    int64_t n = 0;
-    for (auto& r : M->prof.recs) {
-      if (r.cls != kclass) continue;
-      float e = 0.f;
-      PTEBD_HIP(hipEventElapsedTime(&e, r.a, r.b));
-      t += e;
-      f += r.flops;
-      ++n;
-    }
-    *ms = t;
-    *launches = n;
-    *flops = f;
+    M->prof.fold(true);
+    *ms = M->prof.ms[kclass];
+    *launches = M->prof.launches[kclass];
+    *flops = M->prof.flops[kclass];
+  });
+}
+
+tebd_status mps_profile_busy(tebd_mps* M, int32_t kclass, double* busy_ms) {
+  if (!M || !busy_ms) return fail(TEBD_EINVAL, "NULL argument");
+  if (kclass < 0 || kclass >= ptebd::K_NCLASS) return fail(TEBD_EINVAL, "unknown kernel class");
+  return guard([&] {
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+    M->prof.fold(true);
+    *busy_ms = M->prof.busy_ms(kclass);
   });
 }
 

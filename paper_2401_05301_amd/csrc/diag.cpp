@@ -66,6 +66,11 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
   if (m < 1 || n < 1 || !A || !k || !s || !vh || !nrm || !w || !sweeps || chi_max < 1) return TEBD_EINVAL;
   if (variant != TEBD_SVD_JACOBI && variant != TEBD_SVD_GRAM_EIG) return TEBD_EINVAL;
   if (std::min(m, n) > 8192) return TEBD_EINVAL;
+  if (!(eps >= 0.0) || !(w_max >= 0.0)) return TEBD_EINVAL;
+  if (variant == TEBD_SVD_GRAM_EIG && !(eps >= TEBD_GRAM_EPS_MIN)) {
+    ptebd::set_last_error("the Gram route needs eps >= TEBD_GRAM_EPS_MIN (1e-6)");
+    return TEBD_EINVAL;
+  }
   tebd_mps M;
   try {
     PTEBD_HIP(hipStreamCreateWithFlags(&M.stream, hipStreamNonBlocking));

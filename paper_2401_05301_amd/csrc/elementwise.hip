@@ -62,6 +62,11 @@ __global__ void fill_zero_kernel(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
+__global__ void fill_zero_words_kernel(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // Fixed-order block reduction of one double per thread (256 threads).
 __device__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -550,6 +555,13 @@ void square_expand(const double* x, int div, int n, double* y, hipStream_t s) {
 void fill_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   fill_zero_kernel<<<std::min<int64_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, n);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void fill_zero_words(void* p, int64_t words, hipStream_t s) {
+  if (words <= 0) return;
+  fill_zero_words_kernel<<<std::min<int64_t>((words + 255) / 256, 4096), 256, 0, s>>>(static_cast<uint32_t*>(p),
+                                                                                   words);
   PTEBD_LAUNCH_CHECK();
 }
 

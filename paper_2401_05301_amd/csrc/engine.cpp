@@ -25,7 +25,9 @@ namespace ptebd {
 namespace {
 
 constexpr int kNsplitMax = 16;
-constexpr double kGramSigmaFloor = 1e-6;   // Gram route: singular values below this (relative) are noise
+// Gram route: singular values below this (relative) sit at the Gram
+// matrix's rounding level; the subspace iteration does not chase them.
+constexpr double kGramSigmaFloor = TEBD_GRAM_EPS_MIN;
 constexpr double kDampRel = 1e-10;         // subspace iteration: power-step scale floor (relative to the top value)
 constexpr double kDiagCoupling = 0.05;     // subspace iteration: largest relative coupling treated as diagonal
 // Jacobi sweep limit when opts.max_sweeps <= 0.  Cyclic Jacobi on a matrix
@@ -152,7 +154,7 @@ Sizes plan_sizes(int L, int d, int chi_max) {
   s.vec = std::max<int64_t>(s.vec, (int64_t)chi * d);
   const int64_t nb = (maxr + 15) / 16 + 2;
   s.part = (nb / 2 + 1) * kNsplitMax * 1536;
-  s.gates = (int64_t)std::max(L - 2, 0) * 3 * 2 * (int64_t)d * d * d * d * d * d;
+  s.gates = (int64_t)std::max(L - 2, 0) * kGateSlots * 2 * (int64_t)d * d * d * d * d * d;
   return s;
 }
 
@@ -189,7 +191,7 @@ Sizes plan_sizes2(int Ls, int D, int chi_max) {
   s.vec = std::max<int64_t>(s.vec, (int64_t)chi * D);
   const int64_t nb = (maxr + 15) / 16 + 2;
   s.part = (nb / 2 + 1) * kNsplitMax * 1536;
-  s.gates = (int64_t)std::max(Ls - 1, 0) * 2 * 2 * (int64_t)D * D * D * D;
+  s.gates = (int64_t)std::max(Ls - 1, 0) * kGateSlots * 2 * (int64_t)D * D * D * D;
   return s;
 }
 
@@ -286,7 +288,7 @@ void mps_allocate(tebd_mps* M) {
   PTEBD_HIP(hipMemcpyAsync(M->d_br, M->Br.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
-  PTEBD_HIP(hipMemsetAsync(M->ledger, 0, sizeof(double), M->stream));
+  fill_zero(M->ledger, 1, M->stream);
   const int nw = auto_workers(L, M->opts.workers, M->super);
   for (int w = 0; w < nw; ++w) {
     tebd_mps* W = new tebd_mps();
@@ -392,27 +394,45 @@ void set_model(tebd_mps* M, const ModelP& m) {
     for (int K = 0; K + 1 < M->L; ++K) M->spectra.push_back(eig_supersite(m, K));
   else
     for (int j = 0; j + 2 < M->L; ++j) M->spectra.push_back(eig_three_site(m, j));
-  // device gates are rebuilt lazily; keep their memory for reuse
-  for (auto& kv : M->gates) {
-    (void)kv;
+  // device gates are rebuilt lazily into the same buffers (the caller has
+  // synchronised the handle, so no launch still reads them)
+  M->gates.resize(M->spectra.size());
+  for (auto& slots : M->gates) {
+    slots.resize(kGateSlots);
+    for (auto& g : slots) g.valid = false;
   }
-  M->gates.clear();
 }
 
 namespace {
 
+// G_j(tau) on the device: a resident slot of window j if one holds this tau,
+// else the least recently used slot is rebuilt (allocated on first use; a
+// slot that held another gate is overwritten only after the handle's stream
+// has drained, so no launch still reads it).
 std::pair<double*, double*> device_gate(tebd_mps* M, int j, double tau) {
-  auto key = std::make_pair(j, tau);
-  auto it = M->gates.find(key);
-  if (it != M->gates.end()) return it->second;
+  auto& slots = M->gates[j];
+  tebd_mps::GateSlot* pick = nullptr;
+  for (auto& g : slots)
+    if (g.valid && g.tau == tau) {
+      g.used = ++M->gate_clock;
+      return {g.re, g.im};
+    }
+  for (auto& g : slots)
+    if (!pick || (!g.valid && pick->valid) || (g.valid == pick->valid && g.used < pick->used)) pick = &g;
   std::vector<double> re, im;
   gate_matrix(M->spectra[j], tau, re, im);
-  double* dr = dalloc(M, (int64_t)re.size());
-  double* di = dalloc(M, (int64_t)im.size());
-  PTEBD_HIP(hipMemcpy(dr, re.data(), sizeof(double) * re.size(), hipMemcpyHostToDevice));
-  PTEBD_HIP(hipMemcpy(di, im.data(), sizeof(double) * im.size(), hipMemcpyHostToDevice));
-  M->gates[key] = {dr, di};
-  return {dr, di};
+  if (!pick->re) {
+    pick->re = dalloc(M, (int64_t)re.size());
+    pick->im = dalloc(M, (int64_t)im.size());
+  } else if (pick->valid) {
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+  }
+  PTEBD_HIP(hipMemcpy(pick->re, re.data(), sizeof(double) * re.size(), hipMemcpyHostToDevice));
+  PTEBD_HIP(hipMemcpy(pick->im, im.data(), sizeof(double) * im.size(), hipMemcpyHostToDevice));
+  pick->tau = tau;
+  pick->valid = true;
+  pick->used = ++M->gate_clock;
+  return {pick->re, pick->im};
 }
 
 bool debug_enabled() {
@@ -485,7 +505,7 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
   }
   const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : kDefaultSweeps;
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
-    PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
+    fill_zero_words(M->counter, 1, s);
     for (int t = 0; t < nb - 1; ++t) jacobi_round(a, t, s);
     PTEBD_HIP(hipMemcpyAsync(M->h_counter, M->counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     PTEBD_HIP(hipStreamSynchronize(s));
@@ -556,7 +576,7 @@ void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab) {
   int rounds = max_nb - 1;
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
     PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
-    PTEBD_HIP(hipMemsetAsync(d_counts, 0, sizeof(unsigned int) * count, s));
+    fill_zero_words(d_counts, count, s);
     for (int t = 0; t < rounds; ++t)
       jacobi_round_batched(d_tab, d_gram, first[count], d_rot, first[2 * (count + 1) - 1], count, d_active, t, s);
     PTEBD_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
@@ -675,7 +695,7 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
       M->total_sweeps += sweep - 1;
       return sweep - 1;
     }
-    PTEBD_HIP(hipMemsetAsync(M->counter, 0, sizeof(unsigned int), s));
+    fill_zero_words(M->counter, 1, s);
     for (int t = 0; t < nb - 1; ++t) herm_round(a, t, s);
     if (debug_enabled()) {
       PTEBD_HIP(hipMemcpyAsync(M->h_counter, M->counter, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
@@ -875,7 +895,7 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
   const int max_sweeps = M->opts.max_sweeps > 0 ? M->opts.max_sweeps : kDefaultSweeps;
   PTEBD_HIP(hipMemcpyAsync(d_active, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
   for (int sweep = 0;; ++sweep) {
-    PTEBD_HIP(hipMemsetAsync(d_counts, 0, sizeof(unsigned int) * count, s));
+    fill_zero_words(d_counts, count, s);
     count_above_batched(d_tab, count, d_active, max_n, d_counts, s);
     PTEBD_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
     PTEBD_HIP(hipStreamSynchronize(s));
@@ -1098,6 +1118,13 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
 // a few times the rounding error of a length-c dot product.
 double jacobi_tol(int c) { return std::max(2e-15, 2.0 * std::sqrt((double)c) * 1.11e-16); }
 
+// Counts the part of the truncation rule that set the k just read back
+// (h_info[4], written by select_truncate).
+void count_rule(tebd_mps* M) {
+  const int rule = M->h_info[4];
+  if (rule >= 0 && rule < 4) ++M->rule_counts[rule];
+}
+
 }  // namespace
 
 int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf) {
@@ -1115,9 +1142,10 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
                  0.0);
       row_norms(xbuf.re, xbuf.im, n, m, n, M->norms, s);
       select_truncate(M->norms, m, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, nullptr, s);
-      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       const int k = M->h_info[0];
+      count_rule(M);
       gather_rows(xbuf.re, xbuf.im, n, M->perm, M->inv_sig, k, n, vhr, vhi, n, kdev, s);
       return k;
     } else {
@@ -1126,15 +1154,19 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
                  0.0);
       row_norms(xbuf.re, xbuf.im, m, n, m, M->norms, s);
       select_truncate(M->norms, n, 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger, nullptr, s);
-      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       const int k = M->h_info[0];
+      count_rule(M);
       gather_rows(M->W.re, M->W.im, n, M->perm, nullptr, k, n, vhr, vhi, n, kdev, s);
       return k;
     }
   }
-  // Gram route: G = A_s A_s^+ (m <= n) or A_s^+ A_s (m > n), r x r
-  const double eps_g = std::max(eps, kGramSigmaFloor);
+  // Gram route: G = A_s A_s^+ (m <= n) or A_s^+ A_s (m > n), r x r.  The
+  // caller's eps is used as given: the handle refuses eps below
+  // TEBD_GRAM_EPS_MIN on this route, so every cut of the rule lies well
+  // above the Gram matrix's rounding level.
+  const double eps_g = eps;
   // The smaller Gram matrix, except that the right one is kept where the
   // warm start lives on that side and the subspace iteration will run on
   // it, unless it is clearly the larger one (and while it fits the Gram
@@ -1194,7 +1226,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       fill_zero(trial, 1, s);
       select_truncate(M->norms, p, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, trial,
                       M->info_d + 5, s);
-      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       if (M->h_info[0] > keep && keep < keep_full) {
         keep = keep_full;
@@ -1202,6 +1234,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       }
       accumulate_slots(trial, 1, M->ledger, s);
       k = M->h_info[0];
+      count_rule(M);
       rows_r = M->sZ.re;
       rows_i = M->sZ.im;
     } else {
@@ -1209,9 +1242,10 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       herm_diag(M->G.re, r, r, M->norms, s);
       select_truncate(M->norms, r, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger,
                       nullptr, s);
-      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       k = M->h_info[0];
+      count_rule(M);
       rows_r = M->W.re;
       rows_i = M->W.im;
     }
@@ -1250,7 +1284,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
   const bool gram = M->opts.svd == TEBD_SVD_GRAM_EIG;
   double* nrm = M->info_d + 2 * slot;
   int* kdev = M->info_i + slot;
-  const double eps = gram ? std::max(M->opts.trunc_rel, kGramSigmaFloor) : M->opts.trunc_rel;
+  const double eps = M->opts.trunc_rel;   // >= TEBD_GRAM_EPS_MIN on the Gram route (checked at creation)
   const double w_max = M->opts.trunc_weight;
   struct Sector {
     int q = 0;
@@ -1380,9 +1414,10 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
   }
   select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
                   M->ledger, nullptr, s);
-  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
   const int k = M->h_info[0];
+  count_rule(M);
   M->h_perm.resize(k);
   PTEBD_HIP(hipMemcpyAsync(M->h_perm.data(), M->perm, sizeof(int) * k, hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
@@ -1796,6 +1831,12 @@ void sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {
     *last = std::max<int64_t>(*last, W->last_sweeps);
     *total += W->total_sweeps;
   }
+}
+
+void trunc_stats(const tebd_mps* M, int64_t* counts) {
+  for (int i = 0; i < 4; ++i) counts[i] = 0;
+  for (const tebd_mps* W : M->workers)
+    for (int i = 0; i < 4; ++i) counts[i] += W->rule_counts[i];
 }
 
 void prepare_gates(tebd_mps* M, int group, double tau) {

@@ -71,10 +71,21 @@ struct tebd_mps {
 
   std::vector<void*> allocs;
   std::vector<ptebd::SpectralGate> spectra;          // per j
-  std::map<std::pair<int, double>, std::pair<double*, double*>> gates;  // (j, tau) -> device G
+  // Device gates: kGateSlots buffers per window j, each holding G_j(tau) for
+  // one tau, reused least recently used first (set_model invalidates them).
+  struct GateSlot {
+    double tau = 0.0;
+    bool valid = false;
+    uint64_t used = 0;
+    double* re = nullptr;
+    double* im = nullptr;
+  };
+  std::vector<std::vector<GateSlot>> gates;
+  uint64_t gate_clock = 0;
 
   bool failed = false;
   int64_t last_sweeps = 0, total_sweeps = 0;
+  int64_t rule_counts[4] = {0, 0, 0, 0};   // truncations set by chi_max, k_w, k_eps, none (this workspace)
 
   ptebd::Profiler prof;   // kernel timings while profiling is enabled
   bool prof_on = false;
@@ -106,6 +117,10 @@ struct tebd_mps {
 };
 
 namespace ptebd {
+
+// Time slices whose gates stay resident per window (a Strang step needs
+// one per window, a fourth-order step two, canonicalisation one more).
+constexpr int kGateSlots = 4;
 
 struct Sizes {
   std::vector<int> cap;
@@ -141,6 +156,8 @@ void layer(tebd_mps* M, int group, double tau);
 void canonicalize(tebd_mps* M);
 // Sweeps of the last SVD (max over workers) and their running total.
 void sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total);
+// Truncations of the handle by the part of the rule that set k (summed over workers).
+void trunc_stats(const tebd_mps* M, int64_t* counts);
 // Build and upload the gates of the given group and time slice (no state change).
 void prepare_gates(tebd_mps* M, int group, double tau);
 void measure(tebd_mps* M, double* n, double* cnn, double* cnnn);

@@ -569,7 +569,7 @@ void herm_diag(const double* hr, int64_t ldh, int n, double* out, hipStream_t s)
 
 double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, const double* tol, double floor,
                      unsigned long long* ratio_bits, unsigned long long* h_ratio, hipStream_t s) {
-  PTEBD_HIP(hipMemsetAsync(ratio_bits, 0, sizeof(unsigned long long), s));
+  fill_zero_words(ratio_bits, 2, s);
   const int64_t n = (int64_t)p * p;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
   offdiag_ratio_kernel<<<grid, 256, 0, s>>>(hr, hi, ldh, p, tol, floor, ratio_bits);
@@ -588,7 +588,7 @@ void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s) {
 
 unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n, const double* tol,
                          unsigned int* count, unsigned int* h_count, hipStream_t s) {
-  PTEBD_HIP(hipMemsetAsync(count, 0, sizeof(unsigned int), s));
+  fill_zero_words(count, 1, s);
   const int64_t total = (int64_t)n * n;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 2048);
   count_above_kernel<<<grid, 256, 0, s>>>(hr, hi, ldh, n, tol, count);

@@ -11,6 +11,8 @@
 //   3. X_R <- Q^+ X_R (and W_R <- Q^+ W_R) with FP64 MFMA (jac_rotate).
 // At convergence the row norms of X are the singular values (or, when X is a
 // Gram matrix G, its eigenvalues) and W holds the accumulated unitary.
+#include <mutex>
+
 #include "kernels.hpp"
 #include "profile.hpp"
 
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
     const double extra = extra_tail ? fmax(extra_tail[0], 0.0) : 0.0;
     double total = extra;
     for (int i = 0; i < r; ++i) total += key[i] * key[i];
-    int k;
+    int k, rule = 3;
     double tail_k = 0.0;
     if (total <= 0.0) {
       k = 1;
@@ -417,6 +419,8 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
       k = min(min(chi_max, kw), ke);
       if (k < 1) k = 1;
       if (k > r) k = r;
+      // the part of the rule that set k (precedence chi_max, k_w, k_eps)
+      if (k < r) rule = (k == chi_max) ? 0 : (k == kw) ? 1 : (k == ke) ? 2 : 3;
       tail_k = extra;
       for (int i = r - 1; i >= k; --i) tail_k += key[i] * key[i];
     }
@@ -426,6 +430,7 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
     if (!(nrm > 0.0)) nrm = 1.0;
     const double w = total > 0.0 ? tail_k / total : 0.0;
     info_i[0] = k;
+    info_i[4] = rule;
     info_d[0] = nrm;
     info_d[1] = w;
     *ledger += w;
@@ -520,11 +525,15 @@ void select_truncate(const double* vals, int r, int is_gram, int chi_max, double
   const size_t shm = (size_t)np2 * (sizeof(double) + sizeof(int));
   constexpr size_t kMaxShm = 96 * 1024 + 1024;   // 8192 keys + indices
   if (shm > kMaxShm) throw Error(-1, "select: too many singular values for the on-chip sort");
-  static bool attr = false;
-  if (!attr && shm > 48 * 1024) {
-    PTEBD_HIP(hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kMaxShm));
-    attr = true;
+  if (shm > 48 * 1024) {
+    // set once per process, whichever thread gets here first
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] {
+      attr_err = hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kMaxShm);
+    });
+    PTEBD_HIP(attr_err);
   }
   select_kernel<<<1, 256, shm, s>>>(vals, r, np2, is_gram, chi_max, w_max, eps, lam_out, perm, inv_sig, info_i,
                                     info_d, ledger, extra_tail);

@@ -200,6 +200,10 @@ void rows_copy(const RowCopy* tab, int count, const double* scale, hipStream_t s
 // dst[o] = src[idx[o]], o < k (dst must not alias src).
 void take(const double* src, const int* idx, int k, double* dst, hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
+// Zeroes `words` 32-bit words at p with a kernel (counters and flags: a fill
+// kernel rather than hipMemsetAsync, so that the work stays plain kernel
+// launches on the stream).
+void fill_zero_words(void* p, int64_t words, hipStream_t s);
 // *acc += sum_{i<n} slots[i], summed in index order by one thread.
 void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s);
 

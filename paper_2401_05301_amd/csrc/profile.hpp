@@ -11,16 +11,35 @@ namespace ptebd {
 enum KernelClass { K_GEMM_FP64 = 0, K_GEMM_FP32 = 1, K_HERM_EIG = 2, K_HERM_APPLY = 3, K_JAC_GRAM = 4,
                    K_JAC_ROTATE = 5, K_NCLASS = 6 };
 
+// Launch records are folded into per-class totals as soon as their end
+// event has completed, and the events go back to a pool, so a long profiled
+// run holds a bounded number of events.
 struct Profiler {
   struct Rec {
     int cls;
     double flops;
     hipEvent_t a, b;
   };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
+  std::vector<Rec> recs;            // launches not folded yet
+  std::vector<hipEvent_t> pool;     // idle events
+  double ms[K_NCLASS] = {};
+  double flops[K_NCLASS] = {};
+  int64_t launches[K_NCLASS] = {};
+  // Start and end of every folded launch (ms after origin, an event recorded
+  // on the handle's stream when profiling was enabled, before any launch).
+  hipEvent_t origin = nullptr;
+  std::vector<std::pair<float, float>> spans[K_NCLASS];
+  // Starts recording: clears the totals and records the origin on s.
+  void start(hipStream_t s);
+  // Milliseconds during which at least one launch of class cls ran (the
+  // union of its folded spans).
+  double busy_ms(int cls);
   std::mutex mu;   // launchers of several worker threads report here
   hipEvent_t get();
+  void put(int cls, double flops, hipEvent_t a, hipEvent_t b);
+  // Folds the finished records (every record when all_done: the caller has
+  // synchronised every stream the records were made on).
+  void fold(bool all_done);
   void clear();
   ~Profiler();
 };

@@ -66,6 +66,30 @@ def test_validation_without_gpu():
     assert e.value.status == pt.TEBD_EINVAL
 
 
+def test_gram_route_refuses_eps_below_its_floor():
+    """The Gram route cannot resolve singular values below about sqrt(u) s_0:
+    a relative tolerance below TEBD_GRAM_EPS_MIN is refused before any device
+    call (no silent override), the Jacobi route takes it."""
+    import paper_2401_05301_amd as pt
+    m = pt.make_model(L=8, d=3, U=1.0)
+    for eps in (0.0, 1e-12, 0.99e-6):
+        o = pt.make_opts(chi_max=16, w_max=1e-12, eps=eps, svd=pt.SVD_GRAM_EIG)
+        with pytest.raises(pt.TebdError) as e:
+            pt.mps_footprint(m, o)
+        assert e.value.status == pt.TEBD_EINVAL and "TEBD_GRAM_EPS_MIN" in str(e.value)
+        with pytest.raises(pt.TebdError) as e:
+            pt.mps_init_cdw(m, o)
+        assert e.value.status == pt.TEBD_EINVAL
+        with pytest.raises(pt.TebdError) as e:
+            pt.tebd_serve([dict(model=m, chi_max=8, dt=0.01, steps=1, arrival=0.0)], svd=pt.SVD_GRAM_EIG, eps=eps,
+                          hbm_budget=1e9)
+        assert e.value.status == pt.TEBD_EINVAL
+    assert pt.mps_footprint(m, pt.make_opts(chi_max=16, eps=pt.GRAM_EPS_MIN, svd=pt.SVD_GRAM_EIG)) > 0
+    assert pt.mps_footprint(m, pt.make_opts(chi_max=16, eps=1e-14, svd=pt.SVD_JACOBI)) > 0
+    txt = open(os.path.join(ROOT, "include", "ptebd.h")).read()
+    assert re.search(r"#define TEBD_GRAM_EPS_MIN 1e-6\b", txt)
+
+
 def test_footprint_scales_with_chi():
     import paper_2401_05301_amd as pt
     m = pt.make_model(L=64, d=5, U=2.0, Jnnn=0.1)

@@ -32,7 +32,7 @@ def test_unconverged_svd_marks_handle(pt, svd, u1, workers):
     else:
         B, lam = random_mps(L, d, chi, seed=4)
     m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.01)
-    opts = pt.make_opts(chi, 1e-12, 1e-12, svd=svd, max_sweeps=1, workers=workers, u1=u1)
+    opts = pt.make_opts(chi, 1e-12, 1e-12 if svd == 0 else 1e-6, svd=svd, max_sweeps=1, workers=workers, u1=u1)
     g = pt.MPS.from_tensors(pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), opts, B, lam)
     with pytest.raises(pt.TebdError) as e:
         g.layer(0, 0.05)
