@@ -357,8 +357,14 @@ def main():
 
     warm_run, t_warm = 0, None
     for w in range(min(args.warmup, 1)):
+        # the warmup step runs its five layers one call at a time (the same
+        # work as tebd_step), reporting each
         t0 = time.perf_counter()
-        g.step(dt)
+        for grp, tau in [(0, 0.5 * dt), (1, 0.5 * dt), (2, dt), (1, 0.5 * dt), (0, 0.5 * dt)]:
+            tl = time.perf_counter()
+            g.layer(grp, tau)
+            g.sync()
+            log(f"warmup layer {grp} ({tau:g}) done in {time.perf_counter() - tl:.1f} s")
         g.measure()
         t_warm = time.perf_counter() - t0
         warm_run += 1
@@ -444,6 +450,7 @@ def main():
         g.sync()
         prof = g.profile_read()
         busy = g.profile_busy()
+        sites = g.profile_sites()
         g.profile(False)
         log(f"profiled step done in {time.perf_counter() - tp:.1f} s")
         key = "gemm_fp64" if prec == pt.FP64 else "gemm_fp32"
@@ -474,6 +481,7 @@ def main():
         out["kernel_ms"] = {k: v[0] for k, v in prof.items()}
         out["kernel_launches"] = {k: v[1] for k, v in prof.items()}
         out["kernel_busy_ms"] = busy
+        out["gemm_sites"] = {k: {"launches": v[0], "ms": v[1], "TFLOP": v[2] / 1e12} for k, v in sites.items()}
         out["dominant_kernel_class"] = max(prof.items(), key=lambda kv: kv[1][0])[0]
         if key != "gemm_fp64":
             out["roofline_fp32_gemm"] = {"achieved": (terms["theta"] + terms["gate"]) * nsteps_gu

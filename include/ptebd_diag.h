@@ -39,6 +39,12 @@ tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32
 tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, const double* A, int32_t chi_max, double w_max,
                           double eps, int32_t* k, double* s, double* vh, double* nrm, double* w, int32_t* sweeps);
 
+/* Per-call-site totals of the complex GEMM launches recorded by the handle's
+ * profiler (mps_profile) since it was enabled: one text line per site,
+ * "site launches device_ms algorithmic_flops", into out[cap] (NUL
+ * terminated; EINVAL if it does not fit).  Synchronises. */
+tebd_status tebd_diag_profile_sites(tebd_mps* mps, char* out, int64_t cap);
+
 /* Average device time (ms, HIP events) of `reps` launches of the complex GEMM
  * kernel on device-resident m x k and k x n operands (contents unspecified,
  * finite), C = A B. */

@@ -441,6 +441,9 @@ class MPS:
     def profile_read(self):
         return {name: mps_profile_read(self.h, k) for name, k in KERNEL_CLASSES.items()}
 
+    def profile_sites(self):
+        return tebd_diag_profile_sites(self.h)
+
     def profile_busy(self):
         return {name: mps_profile_busy(self.h, k) for name, k in KERNEL_CLASSES.items()}
 
@@ -469,6 +472,8 @@ def _load_diag():
                       P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
 
 
+    _lib.tebd_diag_profile_sites.restype = ctypes.c_int
+    _lib.tebd_diag_profile_sites.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]
     _lib.tebd_diag_zgemm_time.restype = ctypes.c_int
     _lib.tebd_diag_zgemm_time.argtypes = [ctypes.c_int32] * 5 + [P(ctypes.c_double)]
     _lib.tebd_diag_gate.restype = ctypes.c_int
@@ -479,7 +484,20 @@ def _load_diag():
 
 
 _load_diag()
-EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time", "tebd_diag_gate", "tebd_diag_bond_charges"]
+EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time", "tebd_diag_gate",
+            "tebd_diag_bond_charges", "tebd_diag_profile_sites"]
+
+
+def tebd_diag_profile_sites(h) -> dict:
+    """Per-call-site GEMM totals since profiling was enabled:
+    {site: (launches, device ms, algorithmic flops)}."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.tebd_diag_profile_sites(h, buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms, fl = line.split()
+        out[name] = (int(n), float(ms), float(fl))
+    return out
 
 
 def tebd_diag_gate(model: Model, j: int, tau: float, supersite: bool = False) -> np.ndarray:
@@ -552,7 +570,8 @@ def tebd_diag_svd(A: np.ndarray, variant: int = SVD_JACOBI, chi_max: int = 1 << 
     k = ctypes.c_int32()
     nrm, w = ctypes.c_double(), ctypes.c_double()
     sw = ctypes.c_int32()
-    _check(_lib.tebd_diag_svd(variant, m, n, _dptr(pa), min(chi_max, 2 ** 31 - 1), w_max, eps, ctypes.byref(k),
+    fn = _lib.tebd_diag_svd
+    _check(fn(variant, m, n, _dptr(pa), min(chi_max, 2 ** 31 - 1), w_max, eps, ctypes.byref(k),
               _dptr(s), _dptr(vh), ctypes.byref(nrm), ctypes.byref(w), ctypes.byref(sw)))
     kk = k.value
     V = (vh[:kk * n] + 1j * vh[kk * n:2 * kk * n]).reshape(kk, n)

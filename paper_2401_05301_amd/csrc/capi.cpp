@@ -5,6 +5,7 @@
 #include <thread>
 #include <vector>
 
+#include "../../include/ptebd_diag.h"
 #include "engine.hpp"
 
 namespace {
@@ -461,6 +462,23 @@ tebd_status mps_profile_busy(tebd_mps* M, int32_t kclass, double* busy_ms) {
     PTEBD_HIP(hipStreamSynchronize(M->stream));
     M->prof.fold(true);
     *busy_ms = M->prof.busy_ms(kclass);
+  });
+}
+
+extern "C" tebd_status tebd_diag_profile_sites(tebd_mps* M, char* out, int64_t cap) {
+  if (!M || !out || cap < 1) return fail(TEBD_EINVAL, "NULL argument");
+  return guard([&] {
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+    M->prof.fold(true);
+    std::string txt;
+    for (const auto& kv : M->prof.by_tag) {
+      char line[160];
+      std::snprintf(line, sizeof(line), "%s %lld %.6f %.6e\n", kv.first.c_str(), (long long)kv.second.launches,
+                    kv.second.ms, kv.second.flops);
+      txt += line;
+    }
+    if ((int64_t)txt.size() + 1 > cap) throw ptebd::Error(TEBD_EINVAL, "output buffer too small");
+    std::memcpy(out, txt.c_str(), txt.size() + 1);
   });
 }
 

@@ -53,6 +53,6 @@ __device__ __forceinline__ int batch_owner(const int64_t* first, int count, int6
 // Sets the thread-local message returned by tebd_last_error().
 void set_last_error(const std::string& msg);
 
-inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace ptebd

@@ -90,6 +90,8 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     tebd_mps::Z a = z((int64_t)m * n), x = z((int64_t)m * n), vho = z(r * n);
     M.G = z(r * r);
     M.W = z(r * r);
+    M.g_cap = r * r;
+    M.rf = z(64 * mx);
     M.norms = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));
     M.inv_sig = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));
     M.sq = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));

@@ -316,6 +316,80 @@ __global__ __launch_bounds__(256) void damped_power_rows_kernel(const double* zr
   }
 }
 
+__global__ __launch_bounds__(256) void residual_norms_kernel(const double* yr, const double* yi, const double* zr,
+                                                             const double* zi, int64_t ld, int p, int r,
+                                                             const double* theta, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= p) return;
+  const double th = theta[row];
+  const double* py = yr + (int64_t)row * ld;
+  const double* qy = yi + (int64_t)row * ld;
+  const double* pz = zr + (int64_t)row * ld;
+  const double* qz = zi + (int64_t)row * ld;
+  double s = 0.0;
+  for (int j = lane; j < r; j += 64) {
+    const double a = py[j] - th * pz[j];
+    const double b = qy[j] - th * qz[j];
+    s += a * a + b * b;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[row] = sqrt(s);
+}
+
+// part[c * cols + j] = sum over the rows of chunk c of (rs[i / rdiv] |X_ij|)^2
+__global__ __launch_bounds__(256) void col_sq_partial_kernel(const double* xr, const double* xi, int64_t ldx, int rows,
+                                                             int cols, const double* rs, int rdiv, double* part) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int nch = gridDim.y, c = blockIdx.y;
+  if (j >= cols) return;
+  const int per = (rows + nch - 1) / nch;
+  const int i0 = c * per, i1 = min(rows, i0 + per);
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const double w = rs ? rs[i / rdiv] : 1.0;
+    const double a = xr[(int64_t)i * ldx + j] * w, b = xi[(int64_t)i * ldx + j] * w;
+    s += a * a + b * b;
+  }
+  part[(int64_t)c * cols + j] = s;
+}
+
+// sigma_j = sqrt(sum_c part[c * cols + j]); *nrm = |sigma|; lam_j = sigma_j / |sigma|
+// (one work-group, fixed summation order)
+__global__ __launch_bounds__(256) void sigma_from_part_kernel(const double* part, int nch, int cols, double* lam,
+                                                              double* nrm) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < cols; j += 256) {
+    double t = 0.0;
+    for (int c = 0; c < nch; ++c) t += part[(int64_t)c * cols + j];
+    lam[j] = sqrt(t);
+    acc += t;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double n = sqrt(sh[0]);
+  const double inv = n > 0.0 ? 1.0 / n : 0.0;
+  for (int j = threadIdx.x; j < cols; j += 256) lam[j] *= inv;
+  if (threadIdx.x == 0) *nrm = n > 0.0 ? n : 1.0;
+}
+
+// X /= *nrm
+__global__ void scale_recip_kernel(double* xr, double* xi, int64_t ldx, int rows, int cols, const double* nrm) {
+  const double inv = 1.0 / *nrm;
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e % cols;
+    xr[i * ldx + j] *= inv;
+    xi[i * ldx + j] *= inv;
+  }
+}
+
 __global__ __launch_bounds__(256) void inv_sqrt_clamped_kernel(const double* d, int n, double rel, double* out) {
   __shared__ double sh[256];
   double mx = 0.0;
@@ -615,6 +689,28 @@ void supersite_local(const double* const* br, const double* const* bi, const dou
 
 void accumulate_slots(const double* slots, int n, double* acc, hipStream_t s) {
   hipLaunchKernelGGL(accumulate_slots_kernel, dim3(1), dim3(64), 0, s, slots, n, acc);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void refine_sigma(double* xr, double* xi, int64_t ldx, int rows, int cols, const double* rs, int rdiv, double* part,
+                  int64_t part_cap, double* lam, double* nrm, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  int nch = std::min(64, rows);
+  while (nch > 1 && (int64_t)nch * cols > part_cap) nch /= 2;
+  if ((int64_t)nch * cols > part_cap) throw Error(-1, "refine_sigma: scratch too small");
+  col_sq_partial_kernel<<<dim3(ceil_div(cols, 256), nch), 256, 0, s>>>(xr, xi, ldx, rows, cols, rs, rdiv, part);
+  PTEBD_LAUNCH_CHECK();
+  sigma_from_part_kernel<<<1, 256, 0, s>>>(part, nch, cols, lam, nrm);
+  PTEBD_LAUNCH_CHECK();
+  const int64_t n = (int64_t)rows * cols;
+  scale_recip_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, s>>>(xr, xi, ldx, rows, cols,
+                                                                                      nrm);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void residual_norms(const double* yr, const double* yi, const double* zr, const double* zi, int64_t ld, int p, int r,
+                    const double* theta, double* out, hipStream_t s) {
+  residual_norms_kernel<<<ceil_div(p, 4), 256, 0, s>>>(yr, yi, zr, zi, ld, p, r, theta, out);
   PTEBD_LAUNCH_CHECK();
 }
 

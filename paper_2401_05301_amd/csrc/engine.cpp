@@ -30,6 +30,11 @@ constexpr int kNsplitMax = 16;
 constexpr double kGramSigmaFloor = TEBD_GRAM_EPS_MIN;
 constexpr double kDampRel = 1e-10;         // subspace iteration: power-step scale floor (relative to the top value)
 constexpr double kDiagCoupling = 0.05;     // subspace iteration: largest relative coupling treated as diagonal
+// Subspace iteration: largest Newton-Schulz scale (about the largest
+// eigenvalue of the warm rows' normalised Gram matrix), or largest relative
+// coupling of that Gram matrix, at which the warm rows are used as the start.
+constexpr double kWarmMaxScale = 2.0;
+constexpr double kWarmMaxCoupling = 0.5;
 // Jacobi sweep limit when opts.max_sweeps <= 0.  Cyclic Jacobi on a matrix
 // whose leading vectors are spread over many coordinates (raw-basis Gram
 // blocks of a particle-number sector) can spend 30-40 sweeps in its linear
@@ -84,7 +89,7 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 size_t Sizes::bytes(int workers, bool u1) const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
-  int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
+  int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h + 64 * vec);
   w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
   w += 6 * vec + part + 64 + 5 * sub_p + 8;
   if (u1) {
@@ -108,8 +113,10 @@ int auto_workers(int L, int requested, bool super) {
 int subspace_width(int r, int chi_max) { return subspace_width_keep(r, std::min(chi_max, r)); }
 
 int subspace_width_keep(int r, int keep) {
-  // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 16)
-  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 16;
+  // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 4: the
+  // iteration contracts by (lambda_{p+1} / lambda_k) per step, and a quarter more rows than kept
+  // values reaches the FP64 bar in fewer, wider iterations at about the same cost)
+  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 4;
   const int p = ((keep + std::max(64, keep / den)) + 15) / 16 * 16;
   // below ~1.5 p, or below kSubspaceMinRows rows, the whole Gram matrix is
   // cheaper to diagonalise directly (measured on the quench workload)
@@ -207,6 +214,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->g_cap = s.G;
   W->W = zalloc(W, s.W);
   W->V1h = zalloc(W, s.V1h);
+  W->rf = zalloc(W, 64 * s.vec);
   W->ks = dalloc(W, s.vec);
   W->norms = dalloc(W, s.vec);
   W->inv_sig = dalloc(W, s.vec);
@@ -645,6 +653,15 @@ int partial_sweeps() {
   return v;
 }
 
+// Subspace iteration stopping tolerance: largest residual of a kept basis
+// row relative to the trace of the Gram matrix (the squared norm of theta).
+// A kept Schmidt vector weighted by its value is off by about that much,
+// so 1e-12 keeps the observables well inside the 1e-10 FP64 bar.
+double sub_res_rel() {
+  static const double v = std::getenv("PTEBD_SUB_RES") ? std::atof(std::getenv("PTEBD_SUB_RES")) : 1e-12;
+  return v;
+}
+
 int inner_sweeps() {
   static const int v = std::getenv("PTEBD_INNER_SWEEPS") ? std::atoi(std::getenv("PTEBD_INNER_SWEEPS")) : 1;
   return v;
@@ -725,7 +742,11 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
 // view of leading rows of a larger basis); otherwise Z and T swap.
 // With soft set, a Newton-Schulz run that does not converge returns false
 // (Z unchanged, the handle left usable) instead of failing the handle.
-bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_place = false, bool soft = false) {
+// With max_c > 0 the call gives up (returns false) before iterating when
+// the scale c exceeds max_c, i.e. when the normalised rows are too far from
+// orthonormal for the iteration to converge quickly.
+bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_place = false, bool soft = false,
+            double max_c = 0.0) {
   hipStream_t s = M->stream;
   normalize_rows(Z.re, Z.im, r, p, r, nullptr, s);
   // every product below is a polynomial in the Hermitian A, hence Hermitian:
@@ -737,6 +758,7 @@ bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
     g.br = B.re; g.bi = B.im; g.ldb = p;
     g.cr = C.re; g.ci = C.im; g.ldc = p;
     g.herm_out = 1;
+    g.tag = "ns_product";
     zgemm(g, 0, s);
   };
   {
@@ -746,6 +768,7 @@ bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
     g.br = Z.re; g.bi = Z.im; g.ldb = r; g.transB = 1;
     g.cr = M->sH.re; g.ci = M->sH.im; g.ldc = p;
     g.herm_out = 1;
+    g.tag = "lowdin_gram";
     zgemm(g, 0, s);
   }
   double* c = M->info_d + 8;   // c, sqrt(c)
@@ -755,6 +778,15 @@ bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
   // bound; a diverging run restarts from the Gershgorin bound alone.
   bool safe = false;
   ns_scale(M->sH.re, M->sH.im, p, M->pwork, 12, 1.3, c, s);
+  if (max_c > 0.0) {
+    double hc = 0.0;
+    PTEBD_HIP(hipMemcpyAsync(&hc, c, sizeof(double), hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    if (!(hc <= max_c)) {
+      if (debug_enabled()) std::fprintf(stderr, "[ptebd] lowdin p=%d: rows too far from orthonormal (c=%.3f)\n", p, hc);
+      return false;
+    }
+  }
   ns_init(M->sH.re, M->sH.im, p, c, M->nY.re, M->nY.im, M->nZ.re, M->nZ.im, s);
   const double tol2 = 1e-28 * p;
   int it = 0;
@@ -797,7 +829,75 @@ bool lowdin(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_p
   q.br = Z.re; q.bi = Z.im; q.ldb = r;
   q.cr = T.re; q.ci = T.im; q.ldc = r;
   q.alpha_dev = c + 1; q.alpha_recip = 1;
+  q.tag = "lowdin_apply";
   zgemm(q, 0, s);
+  if (in_place) {
+    PTEBD_HIP(hipMemcpyAsync(Z.re, T.re, sizeof(double) * (size_t)p * r, hipMemcpyDeviceToDevice, s));
+    PTEBD_HIP(hipMemcpyAsync(Z.im, T.im, sizeof(double) * (size_t)p * r, hipMemcpyDeviceToDevice, s));
+  } else {
+    std::swap(Z, T);
+  }
+  return true;
+}
+
+// Orthonormalisation of the subspace basis: Cholesky-QR unless
+// PTEBD_LOWDIN selects the symmetric Newton-Schulz route (tuning switch).
+bool lowdin_selected() {
+  static const bool v = std::getenv("PTEBD_LOWDIN") != nullptr;
+  return v;
+}
+
+// Orthonormal rows by Cholesky-QR (Gram-Schmidt in row order): the rows of
+// Z (p x r) are normalised, K = Z Z^+ = L L^+ is factorised and Z <- L^-1 Z.
+// Row i changes only by its components along rows 0..i-1, so a basis that is
+// nearly orthonormal barely moves, and the work is two GEMM-shaped products
+// (K and the application of L^-1) plus a small blocked factorisation.  With
+// max_coupling > 0 the call gives up (returns false) when some
+// |K_ij| / sqrt(K_ii K_jj) exceeds it: rows that far from orthogonal are not
+// worth keeping as a start.  It also returns false if the factorisation
+// breaks down (dependent rows).  Uses sH, nY and nZ as scratch; the result
+// replaces Z (swapped with T, or copied into Z's memory when in_place).
+bool orthonormalize(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, bool in_place,
+                    double max_coupling = 0.0) {
+  if (lowdin_selected()) return lowdin(M, Z, T, p, r, in_place, true, max_coupling > 0.0 ? kWarmMaxScale : 0.0);
+  hipStream_t s = M->stream;
+  normalize_rows(Z.re, Z.im, r, p, r, nullptr, s);
+  {
+    ZGemmArgs g;
+    g.m = p; g.n = p; g.k = r;
+    g.ar = Z.re; g.ai = Z.im; g.lda = r;
+    g.br = Z.re; g.bi = Z.im; g.ldb = r; g.transB = 1;
+    g.cr = M->sH.re; g.ci = M->sH.im; g.ldc = p;
+    g.herm_out = 1;
+    g.tag = "ortho_gram";
+    zgemm(g, 0, s);
+  }
+  if (max_coupling > 0.0) {
+    herm_tol(M->sH.re, p, p, herm_tol_units(), M->info_d + 7, s);
+    const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, 0.0, M->ratio_bits, M->h_ratio, s);
+    if (!(ratio <= max_coupling)) {
+      if (debug_enabled()) std::fprintf(stderr, "[ptebd] cholesky-qr p=%d: rows far from orthogonal (%.2e)\n", p, ratio);
+      return false;
+    }
+  }
+  int* flag = M->info_i + 6;
+  fill_zero_words(flag, 1, s);
+  chol_inverse(M->sH.re, M->sH.im, p, M->nY.re, M->nY.im, M->nZ.re, M->nZ.im, flag, s);
+  PTEBD_HIP(hipMemcpyAsync(M->h_info + 6, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  if (M->h_info[6]) {
+    if (debug_enabled()) std::fprintf(stderr, "[ptebd] cholesky-qr p=%d: factorisation broke down\n", p);
+    return false;
+  }
+  {
+    ZGemmArgs q;
+    q.m = p; q.n = r; q.k = p;
+    q.ar = M->nY.re; q.ai = M->nY.im; q.lda = p;
+    q.br = Z.re; q.bi = Z.im; q.ldb = r;
+    q.cr = T.re; q.ci = T.im; q.ldc = r;
+    q.tag = "ortho_apply";
+    zgemm(q, 0, s);
+  }
   if (in_place) {
     PTEBD_HIP(hipMemcpyAsync(Z.re, T.re, sizeof(double) * (size_t)p * r, hipMemcpyDeviceToDevice, s));
     PTEBD_HIP(hipMemcpyAsync(Z.im, T.im, sizeof(double) * (size_t)p * r, hipMemcpyDeviceToDevice, s));
@@ -815,6 +915,7 @@ void rayleigh(tebd_mps* M, int p, int r) {
   h.br = M->sZ.re; h.bi = M->sZ.im; h.ldb = r; h.transB = 1;
   h.cr = M->sH.re; h.ci = M->sH.im; h.ldc = p;
   h.herm_out = 1;   // Z G Z^+ is Hermitian
+  h.tag = "rayleigh";
   zgemm(h, 0, M->stream);
 }
 
@@ -953,13 +1054,23 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     // Orthonormalise the warm rows on their own and take the random rows
     // out of their span, so that the basis keeps the warm rows as they are
     // (a joint symmetric orthonormalisation would mix them with noise).
-    if (!lowdin(M, M->sZ, M->sZ2, kw, r, true, true)) return false;
+    // Warm rows of a state in canonical form are orthogonal already; rows
+    // far from that (a state that is not canonical yet) give no useful
+    // start, and the basis starts from random rows instead.
+    if (!orthonormalize(M, M->sZ, M->sZ2, kw, r, true, kWarmMaxCoupling)) {
+      kw = 0;
+      fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
+      fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
+    }
+  }
+  if (kw > 0 && kw < p) {
     tebd_mps::Z rnd{M->sZ.re + (size_t)kw * r, M->sZ.im + (size_t)kw * r};
     ZGemmArgs c;   // C = R Zw^+  ((p - kw) x kw)
     c.m = p - kw; c.n = kw; c.k = r;
     c.ar = rnd.re; c.ai = rnd.im; c.lda = r;
     c.br = M->sZ.re; c.bi = M->sZ.im; c.ldb = r; c.transB = 1;
     c.cr = M->sH.re; c.ci = M->sH.im; c.ldc = kw;
+    c.tag = "warm_overlap";
     zgemm(c, 0, s);
     ZGemmArgs u;   // R <- R - C Zw
     u.m = p - kw; u.n = r; u.k = kw;
@@ -967,19 +1078,19 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     u.br = M->sZ.re; u.bi = M->sZ.im; u.ldb = r;
     u.cr = rnd.re; u.ci = rnd.im; u.ldc = r;
     u.alpha = -1.0; u.beta = 1;
+    u.tag = "warm_project";
     zgemm(u, 0, s);
-    if (!lowdin(M, rnd, M->sZ2, p - kw, r, true, true)) return false;
+    if (!orthonormalize(M, rnd, M->sZ2, p - kw, r, true)) return false;
   } else {
-    if (!lowdin(M, M->sZ, M->sZ2, p, r, false, true)) return false;
-    if (!lowdin(M, M->sZ, M->sZ2, p, r, false, true)) return false;
+    if (!orthonormalize(M, M->sZ, M->sZ2, p, r, false)) return false;
+    if (!orthonormalize(M, M->sZ, M->sZ2, p, r, false)) return false;
   }
   // trace of G: scale of the rounding noise in the Ritz values
   tail_rest(gr, r, r, M->norms, 0, M->info_d + 4, s);
   double trace = 0.0;
   PTEBD_HIP(hipMemcpyAsync(&trace, M->info_d + 4, sizeof(double), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
-  double prev_kept = 0.0;
-  std::vector<double> prev(keep, 0.0);
+  std::vector<double> h_res(p), sorted;
   const int max_it = 30;
   auto image = [&]() {   // Y = Z G (rows: (G z_i)^+), H = Y Z^+
     ZGemmArgs g;
@@ -987,6 +1098,7 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     g.ar = M->sZ.re; g.ai = M->sZ.im; g.lda = r;
     g.br = gr; g.bi = gi; g.ldb = r;
     g.cr = M->sY.re; g.ci = M->sY.im; g.ldc = r;
+    g.tag = "subspace_image";
     zgemm(g, 0, s);
     rayleigh(M, p, r);
   };
@@ -1000,6 +1112,7 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       q.ar = Q.re; q.ai = Q.im; q.lda = n;
       q.br = X.re + (size_t)r0 * r; q.bi = X.im + (size_t)r0 * r; q.ldb = r;
       q.cr = T.re + (size_t)r0 * r; q.ci = T.im + (size_t)r0 * r; q.ldc = r;
+      q.tag = "subspace_rotate";
       zgemm(q, 0, s);
       if (r0 == 0 && n == p) {
         std::swap(X, T);
@@ -1011,7 +1124,6 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       }
     }
   };
-  const double u = 1.1102230246251565e-16;
   std::vector<double> h_vals(p);
   for (int it = 0; it < max_it; ++it) {
     image();
@@ -1025,44 +1137,6 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       rayleigh(M, p, r);
     }
     herm_diag(M->sH.re, p, p, M->norms, s);
-    PTEBD_HIP(hipMemcpyAsync(h_vals.data(), M->norms, sizeof(double) * p, hipMemcpyDeviceToHost, s));
-    PTEBD_HIP(hipStreamSynchronize(s));
-    std::sort(h_vals.begin(), h_vals.end(), std::greater<double>());
-    double kept = 0.0, delta = 0.0;
-    for (int i = 0; i < keep; ++i) {
-      kept += h_vals[i];
-      delta = std::max(delta, std::fabs(h_vals[i] - prev[i]));
-      prev[i] = h_vals[i];
-    }
-    // The sum of the largest `keep` Rayleigh quotients is the weight the
-    // kept subspace captures; it grows monotonically towards the optimum.
-    // Stop once an iteration gains less than 1e-4 of the weight still
-    // outside (or less than the rounding level of G, or 1% of the
-    // truncation tolerance) and no kept value moved by more than 1e-10 of
-    // the largest.
-    const double gain = kept - prev_kept;
-    // (a gain below 1% of the truncation tolerance no longer moves the ledger)
-    const bool stable = delta <= 1e-10 * h_vals[0];
-    const double gain_tol = std::max({1e-4 * (trace - kept), 64 * u * trace, 1e-2 * M->opts.trunc_weight * trace});
-    const bool done = (it >= 1 && gain <= gain_tol && stable) || it == max_it - 1;
-    if (it == max_it - 1 && !stable) {
-      // kept values still moving at the last iteration: the subspace has
-      // not found the leading eigenvectors (a start nearly inside the null
-      // space of a rank-deficient G); the caller solves G directly
-      if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d: not converged\n", r, p);
-      return false;
-    }
-    prev_kept = kept;
-    if (done) {
-      // final Rayleigh-Ritz: exact eigenvectors of H
-      rr_jacobi(0);
-      herm_diag(M->sH.re, p, p, M->norms, s);
-      rotate(M->sW, 0, p, false);
-      if (debug_enabled())
-        std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d captured=%.15e delta=%.3e top=%.6e final\n", r, p,
-                     it, kept, delta, h_vals[0]);
-      break;
-    }
     // Next basis.  The exact power step spans the rows of Z + H^-1 R with
     // the block residual R = Y - H Z (orthogonal to every basis row).  When
     // the couplings of H are small against its diagonal (relative to
@@ -1070,8 +1144,11 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
     // Otherwise a few Jacobi sweeps first rotate the basis towards the Ritz
     // vectors; they need not converge, since the residual is taken against
     // the rotated H as it stands.
+    PTEBD_HIP(hipMemcpyAsync(h_vals.data(), M->norms, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    const double top0 = *std::max_element(h_vals.begin(), h_vals.end());
     herm_tol(M->sH.re, p, p, herm_tol_units(), M->info_d + 7, s);
-    const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, kDampRel * h_vals[0], M->ratio_bits,
+    const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, kDampRel * top0, M->ratio_bits,
                                        M->h_ratio, s);
     if (!(ratio <= 1.5)) {
       // |H_ij| <= sqrt(H_ii H_jj) holds for the positive semi-definite
@@ -1085,7 +1162,7 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       herm_diag(M->sH.re, p, p, M->norms, s);
       rotate(M->sW, 0, p, true);
     }
-    {  // Y <- Y - (H - diag(H)) Z: row i becomes theta_i z_i + residual
+    {  // Y <- Y - (H - diag(H)) Z: row i becomes theta_i z_i + R_i
       zero_diag(M->sH.re, M->sH.im, p, p, s);
       ZGemmArgs q;
       q.m = p; q.n = r; q.k = p;
@@ -1093,19 +1170,53 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
       q.br = M->sZ.re; q.bi = M->sZ.im; q.ldb = r;
       q.cr = M->sY.re; q.ci = M->sY.im; q.ldc = r;
       q.alpha = -1.0; q.beta = 1;
+      q.tag = "subspace_residual";
       zgemm(q, 0, s);
     }
+    // Stopping rule: the residual |R_i| = |G z_i - sum_j H_ij z_j| of every
+    // basis row whose Rayleigh quotient is among the `keep` largest.  It
+    // bounds the angle between the span and the eigenvectors it should hold
+    // by |R| / gap, so once it is below tol * trace G every kept Schmidt
+    // vector, weighted by its value, is off by at most about that much.
+    residual_norms(M->sY.re, M->sY.im, M->sZ.re, M->sZ.im, r, p, r, M->norms, M->sq, s);
+    PTEBD_HIP(hipMemcpyAsync(h_vals.data(), M->norms, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipMemcpyAsync(h_res.data(), M->sq, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    sorted.assign(h_vals.begin(), h_vals.end());
+    std::nth_element(sorted.begin(), sorted.begin() + (keep - 1), sorted.end(), std::greater<double>());
+    const double kth = sorted[keep - 1];
+    double top = 0.0, res = 0.0;
+    for (int i = 0; i < p; ++i) {
+      top = std::max(top, h_vals[i]);
+      if (h_vals[i] >= kth) res = std::max(res, h_res[i]);
+    }
+    const bool done = it >= 1 && res <= sub_res_rel() * trace;
     if (debug_enabled())
-      std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d captured=%.15e gain=%.3e delta=%.3e top=%.6e %s %.2e\n",
-                   r, p, it, kept, gain, delta, h_vals[0], jac ? "jacobi" : "residual", ratio);
+      std::fprintf(stderr, "[ptebd] subspace r=%d p=%d it=%d residual=%.3e (of trace %.3e) kth=%.3e top=%.6e %s %.2e\n",
+                   r, p, it, res, trace, kth, top, jac ? "jacobi" : "diag", ratio);
+    if (done) {
+      // final Rayleigh-Ritz: exact eigenvectors of H (its diagonal restored)
+      set_diag(M->sH.re, M->sH.im, p, p, M->norms, s);
+      rr_jacobi(0);
+      herm_diag(M->sH.re, p, p, M->norms, s);
+      rotate(M->sW, 0, p, false);
+      break;
+    }
+    if (it == max_it - 1) {
+      // the span has not settled on the leading eigenvectors (a start
+      // nearly inside the null space of a rank-deficient G): the caller
+      // solves G directly
+      if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d: not converged\n", r, p);
+      return false;
+    }
     // Damped power step: a plain image G Z has rows spread over the whole
-    // dynamic range of G and is too ill-conditioned to orthonormalise by
-    // Newton-Schulz; scaling each image by its Ritz value and capping the
+    // dynamic range of G and is too ill-conditioned to orthonormalise
+    // accurately; scaling each image by its Ritz value and capping the
     // residual step keeps the rows near orthonormal.
     damped_power_rows(M->sZ.re, M->sZ.im, M->sY.re, M->sY.im, r, p, r, M->norms, 1.0, kDampRel,
                       kGramSigmaFloor * kGramSigmaFloor, s);
     std::swap(M->sZ, M->sY);
-    if (!lowdin(M, M->sZ, M->sZ2, p, r, false, true)) {
+    if (!orthonormalize(M, M->sZ, M->sZ2, p, r, false)) {
       if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d p=%d: orthonormalisation failed\n", r, p);
       return false;
     }
@@ -1117,6 +1228,56 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
 // Relative orthogonality target of the one-sided Jacobi for rows of length c:
 // a few times the rounding error of a length-c dot product.
 double jacobi_tol(int c) { return std::max(2e-15, 2.0 * std::sqrt((double)c) * 1.11e-16); }
+
+// Smallest kept Schmidt value, relative to the largest, below which the rows
+// V^+ = S^-1 U^+ M of the left Gram route are re-orthonormalised.  An
+// eigenvector u_i of the Gram matrix carries a component of order
+// u / s_j^2 along a larger u_j (u the unit roundoff), and the division by
+// s_i turns it into a component of order u / (s_i s_j) of v_j in v_i: up to
+// ~1e-10 next to s_j ~ 1 for s_i ~ 1e-6, enough to move the observables by
+// the FP64 bar.  Cholesky-QR of the rows in order of decreasing value
+// (Gram-Schmidt) removes exactly those components.
+constexpr double kRefineRatio = 1e-3;
+
+// Cholesky-QR of the k rows of V (length n, leading dimension ldv) in their
+// stored order: V <- L^-1 V with V V^+ = L L^+, so that row i loses its
+// components along rows 0..i-1 and every row ends with unit norm.  Uses the
+// Gram and eigenvector workspaces (G, W), rf, and out (k x n) as scratch;
+// leaves V unchanged if the factorisation breaks down (rows dependent).
+void cholqr_rows(tebd_mps* M, double* vr, double* vi, int64_t ldv, int k, int n, tebd_mps::Z out) {
+  hipStream_t s = M->stream;
+  if (k < 2) return;
+  if ((int64_t)k * k > M->g_cap) throw Error(-1, "Cholesky-QR: k^2 exceeds the Gram workspace");
+  {  // K = V V^+
+    ZGemmArgs g;
+    g.m = k; g.n = k; g.k = n;
+    g.ar = vr; g.ai = vi; g.lda = ldv;
+    g.br = vr; g.bi = vi; g.ldb = ldv; g.transB = 1;
+    g.cr = M->G.re; g.ci = M->G.im; g.ldc = k;
+    g.herm_out = 1;
+    g.tag = "refine_gram";
+    zgemm(g, 0, s);
+  }
+  int* flag = M->info_i + 6;
+  fill_zero_words(flag, 1, s);
+  chol_inverse(M->G.re, M->G.im, k, M->W.re, M->W.im, M->rf.re, M->rf.im, flag, s);
+  PTEBD_HIP(hipMemcpyAsync(M->h_info + 6, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipStreamSynchronize(s));
+  if (M->h_info[6]) {
+    if (debug_enabled()) std::fprintf(stderr, "[ptebd] cholesky-qr k=%d: factorisation broke down, rows kept\n", k);
+    return;
+  }
+  {  // out = L^-1 V
+    ZGemmArgs q;
+    q.m = k; q.n = n; q.k = k;
+    q.ar = M->W.re; q.ai = M->W.im; q.lda = k;
+    q.br = vr; q.bi = vi; q.ldb = ldv;
+    q.cr = out.re; q.ci = out.im; q.ldc = n;
+    q.tag = "refine_apply";
+    zgemm(q, 0, s);
+  }
+  scale_rows_copy(out.re, out.im, n, nullptr, 1, k, n, vr, vi, ldv, s);
+}
 
 // Counts the part of the truncation rule that set the k just read back
 // (h_info[4], written by select_truncate).
@@ -1187,6 +1348,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
     g.row_scale = in.rs; g.row_div = in.rdiv;
     g.col_scale = in.rs; g.col_div = in.rdiv;
     g.herm_out = 1;
+    g.tag = "gram";
     zgemm(g, 0, s);
   } else {
     const double* ks = nullptr;
@@ -1201,6 +1363,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
     g.cr = M->G.re; g.ci = M->G.im; g.ldc = n;
     g.k_scale = ks; g.k_div = 1;
     g.herm_out = 1;
+    g.tag = "gram";
     zgemm(g, 0, s);
   }
   // eigenvectors (conjugated, as rows) and eigenvalues of G
@@ -1227,6 +1390,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       select_truncate(M->norms, p, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, trial,
                       M->info_d + 5, s);
       PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipMemcpyAsync(M->h_part, nrm + 13, sizeof(double), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       if (M->h_info[0] > keep && keep < keep_full) {
         keep = keep_full;
@@ -1243,6 +1407,7 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
       select_truncate(M->norms, r, 1, M->chi_max, w_max, eps_g, lam_out, M->perm, M->inv_sig, kdev, nrm, M->ledger,
                       nullptr, s);
       PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+      PTEBD_HIP(hipMemcpyAsync(M->h_part, nrm + 13, sizeof(double), hipMemcpyDeviceToHost, s));
       PTEBD_HIP(hipStreamSynchronize(s));
       k = M->h_info[0];
       count_rule(M);
@@ -1259,7 +1424,10 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
     v.br = in.ar; v.bi = in.ai; v.ldb = in.lda;
     v.cr = vhr; v.ci = vhi; v.ldc = n;
     v.k_scale = in.rs; v.k_div = in.rdiv;
+    v.tag = "svd_project";
     zgemm(v, 0, s);
+    // smallest kept over largest Schmidt value (read back with k)
+    if (k >= 2 && M->h_part[0] < kRefineRatio) cholqr_rows(M, vhr, vhi, n, k, n, xbuf);
   } else {
     // eigenvectors of A^+ A are the right singular vectors
     gather_rows(rows_r, rows_i, r, M->perm, nullptr, k, n, vhr, vhi, n, kdev, s);
@@ -1382,6 +1550,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       }
       g.cr = M->G.re + S->goff; g.ci = M->G.im + S->goff; g.ldc = S->r;
       g.herm_out = 1;
+      g.tag = "u1_gram";
       zgemm(g, 0, s);
     }
   };
@@ -1415,7 +1584,9 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
   select_truncate(M->norms, nvals, gram ? 1 : 0, M->chi_max, w_max, eps, lam_out, M->perm, M->inv_sig, kdev, nrm,
                   M->ledger, nullptr, s);
   PTEBD_HIP(hipMemcpyAsync(M->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+  PTEBD_HIP(hipMemcpyAsync(M->h_part, nrm + 13, sizeof(double), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
+  const double kept_ratio = M->h_part[0];
   const int k = M->h_info[0];
   count_rule(M);
   M->h_perm.resize(k);
@@ -1499,12 +1670,17 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
       v.ar = M->G.re + S->xoff; v.ai = M->G.im + S->xoff; v.lda = S->m;
       v.br = xbuf.re + S->off; v.bi = xbuf.im + S->off; v.ldb = S->n;
       v.cr = M->uv.re + S->yoff; v.ci = M->uv.im + S->yoff; v.ldc = S->n;
+      v.tag = "u1_project";
       zgemm(v, 0, s);
     }
   }
   fill_zero(vhr, (int64_t)k * n, s);
   fill_zero(vhi, (int64_t)k * n, s);
   rows_copy(M->u_tab + nx, k, M->inv_sig, s);
+  // Gram route: the rows of different sectors are orthogonal exactly
+  // (disjoint columns), and within a sector they are in decreasing order of
+  // value, which is the order Cholesky-QR needs
+  if (gram && k >= 2 && kept_ratio < kRefineRatio) cholqr_rows(M, vhr, vhi, n, k, n, xbuf);
   // the host tables stay untouched until the next call, which synchronises first
   return k;
 }
@@ -1560,6 +1736,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.ar = S->Br[j]; g.ai = S->Bi[j]; g.lda = c1;
     g.br = S->Br[j + 1]; g.bi = S->Bi[j + 1]; g.ldb = (int64_t)d * c2;
     g.cr = W->T1.re; g.ci = W->T1.im; g.ldc = (int64_t)d * c2;
+    g.tag = "theta";
     zgemm(g, prec, s);
   }
   {  // psi = T1 B_{j+2}
@@ -1568,6 +1745,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.ar = W->T1.re; g.ai = W->T1.im; g.lda = c2;
     g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = (int64_t)d * cr;
     g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)d * cr;
+    g.tag = "theta";
     zgemm(g, prec, s);
   }
   {  // psi'[a] = G psi[a]
@@ -1576,6 +1754,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.ar = G.first; g.ai = G.second; g.lda = d3; g.sA = 0;
     g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)d3 * cr;
     g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)d3 * cr;
+    g.tag = "gate";
     zgemm(g, prec, s);
   }
   const int m1 = cl * d, n1 = d * d * cr;
@@ -1603,14 +1782,24 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   } else {
     k1 = svd_trunc(W, in1, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi);
   }
+  const bool gram = W->opts.svd == TEBD_SVD_GRAM_EIG;
   {  // B_j = psi' V1 / |S1|
     ZGemmArgs g;
     g.m = m1; g.n = k1; g.k = n1;
     g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
     g.br = W->V1h.re; g.bi = W->V1h.im; g.ldb = n1; g.transB = 1;
     g.cr = S->Br[j]; g.ci = S->Bi[j]; g.ldc = k1;
-    g.alpha_dev = W->info_d + 0; g.alpha_recip = 1;
+    if (!gram) {
+      g.alpha_dev = W->info_d + 0;
+      g.alpha_recip = 1;
+    }
+    g.tag = "update_left";
     zgemm(g, 0, s);
+    // Gram route: Lambda_j psi' V1 = U1 S1 gives each Schmidt value as a column
+    // norm to the rounding of the product, where the Gram eigenvalue s^2 only
+    // resolves s to u / s (the division by |S1| follows)
+    if (gram) refine_sigma(S->Br[j], S->Bi[j], k1, m1, k1, S->lam[j], d, W->part, W->part_cap, S->lam[j + 1],
+                           W->info_d + 0, s);
   }
   const int m2 = k1 * d, n2 = d * cr;
   SvdIn in2{W->V1h.re, W->V1h.im, n2, m2, n2, S->lam[j + 1], d};
@@ -1639,8 +1828,15 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.ar = W->V1h.re; g.ai = W->V1h.im; g.lda = n2;
     g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = n2; g.transB = 1;
     g.cr = S->Br[j + 1]; g.ci = S->Bi[j + 1]; g.ldc = k2;
-    g.alpha_dev = W->info_d + 2; g.alpha_recip = 1;
+    if (!gram) {
+      g.alpha_dev = W->info_d + 2;
+      g.alpha_recip = 1;
+    }
+    g.tag = "update_middle";
     zgemm(g, 0, s);
+    // S1 V1^+ V2 = U2 S2 (as above)
+    if (gram) refine_sigma(S->Br[j + 1], S->Bi[j + 1], k2, m2, k2, S->lam[j + 1], d, W->part, W->part_cap,
+                           S->lam[j + 2], W->info_d + 2, s);
   }
   S->chi[j + 1] = k1;
   S->chi[j + 2] = k2;
@@ -1666,6 +1862,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.ar = S->Br[K]; g.ai = S->Bi[K]; g.lda = cm;
     g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = (int64_t)D * cr;
     g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)D * cr;
+    g.tag = "theta";
     zgemm(g, prec, s);
   }
   {  // psi'[a] = G psi[a]
@@ -1674,6 +1871,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.ar = G.first; g.ai = G.second; g.lda = D2; g.sA = 0;
     g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)D2 * cr;
     g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)D2 * cr;
+    g.tag = "gate";
     zgemm(g, prec, s);
   }
   const int m1 = cl * D, n1 = D * cr;
@@ -1706,8 +1904,16 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
     g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = n1; g.transB = 1;
     g.cr = S->Br[K]; g.ci = S->Bi[K]; g.ldc = k;
-    g.alpha_dev = W->info_d + 0; g.alpha_recip = 1;
+    const bool gram = W->opts.svd == TEBD_SVD_GRAM_EIG;
+    if (!gram) {
+      g.alpha_dev = W->info_d + 0;
+      g.alpha_recip = 1;
+    }
+    g.tag = "update_left";
     zgemm(g, 0, s);
+    // Lambda_K psi' V = U S: Schmidt values as column norms (Gram route)
+    if (gram) refine_sigma(S->Br[K], S->Bi[K], k, m1, k, S->lam[K], D, W->part, W->part_cap, S->lam[K + 1],
+                           W->info_d + 0, s);
   }
   S->chi[K + 1] = k;
   if (S->u1) S->q[K + 1] = std::move(qk);
@@ -1872,6 +2078,7 @@ void measure_super(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
         g.br = M->Br[K]; g.bi = M->Bi[K]; g.ldb = cr;
         g.cr = M->E.re; g.ci = M->E.im; g.ldc = cr;
         g.k_scale = M->ks;
+        g.tag = "measure";
         zgemm(g, 0, s);
       }
       {  // F = E B_{K+1}
@@ -1880,6 +2087,7 @@ void measure_super(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
         g.ar = M->E.re; g.ai = M->E.im; g.lda = cr;
         g.br = M->Br[K + 1]; g.bi = M->Bi[K + 1]; g.ldb = (int64_t)D * cr2;
         g.cr = M->F.re; g.ci = M->F.im; g.ldc = (int64_t)D * cr2;
+        g.tag = "measure";
         zgemm(g, 0, s);
       }
       if (mode1 == 2) {
@@ -1943,6 +2151,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
       g.br = M->Br[i]; g.bi = M->Bi[i]; g.ldb = cr;
       g.cr = M->E.re; g.ci = M->E.im; g.ldc = cr;
       g.k_scale = M->ks;
+      g.tag = "measure";
       zgemm(g, 0, s);
     }
     {  // F = E B_{i+1}
@@ -1951,6 +2160,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
       g.ar = M->E.re; g.ai = M->E.im; g.lda = cr;
       g.br = M->Br[i + 1]; g.bi = M->Bi[i + 1]; g.ldb = (int64_t)d * cr2;
       g.cr = M->F.re; g.ci = M->F.im; g.ldc = (int64_t)d * cr2;
+      g.tag = "measure";
       zgemm(g, 0, s);
     }
     close_op(M->Br[i + 1], M->Bi[i + 1], M->F.re, M->F.im, cr, d, cr2, d, 1, 0, dc + 2 * i, M->hop_part, s);
@@ -1962,6 +2172,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
         g.ar = M->Br[i + 1]; g.ai = M->Bi[i + 1]; g.lda = cr2; g.transA = 1;
         g.br = M->F.re; g.bi = M->F.im; g.ldb = cr2;
         g.cr = M->F2.re; g.ci = M->F2.im; g.ldc = cr2;
+        g.tag = "measure";
         zgemm(g, 0, s);
       }
       {  // F3 = F2 B_{i+2}
@@ -1970,6 +2181,7 @@ void measure(tebd_mps* M, double* n_out, double* cnn, double* cnnn) {
         g.ar = M->F2.re; g.ai = M->F2.im; g.lda = cr2;
         g.br = M->Br[i + 2]; g.bi = M->Bi[i + 2]; g.ldb = (int64_t)d * cr3;
         g.cr = M->F3.re; g.ci = M->F3.im; g.ldc = (int64_t)d * cr3;
+        g.tag = "measure";
         zgemm(g, 0, s);
       }
       close_op(M->Br[i + 2], M->Bi[i + 2], M->F3.re, M->F3.im, cr2, d, cr3, d, 1, 0, dd + 2 * i, M->hop_part, s);

@@ -489,6 +489,14 @@ __global__ void zero_diag_kernel(double* hr, double* hi, int64_t ldh, int p) {
   }
 }
 
+__global__ void set_diag_kernel(double* hr, double* hi, int64_t ldh, int p, const double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p) {
+    hr[(int64_t)i * ldh + i] = d[i];
+    hi[(int64_t)i * ldh + i] = 0.0;
+  }
+}
+
 __global__ void diag_kernel(const double* hr, int64_t ldh, int n, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = hr[(int64_t)i * ldh + i];
@@ -579,6 +587,11 @@ double offdiag_ratio(const double* hr, const double* hi, int64_t ldh, int p, con
   double v;
   std::memcpy(&v, h_ratio, sizeof(double));
   return v;
+}
+
+void set_diag(double* hr, double* hi, int64_t ldh, int p, const double* d, hipStream_t s) {
+  set_diag_kernel<<<ceil_div(p, 256), 256, 0, s>>>(hr, hi, ldh, p, d);
+  PTEBD_LAUNCH_CHECK();
 }
 
 void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s) {

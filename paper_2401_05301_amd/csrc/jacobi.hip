@@ -432,6 +432,7 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
     info_i[0] = k;
     info_i[4] = rule;
     info_d[0] = nrm;
+    info_d[13] = key[0] > 0.0 ? key[k - 1] / key[0] : 1.0;   // smallest kept over largest value
     info_d[1] = w;
     *ledger += w;
     s_k = k;

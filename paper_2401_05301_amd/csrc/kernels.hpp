@@ -27,6 +27,7 @@ struct ZGemmArgs {
   double alpha = 1.0;
   int beta = 0;
   int herm_out = 0;   // C = X X^+ (Hermitian): accounted as 4 m^2 k flops
+  const char* tag = "gemm";   // call site, for the profiler's per-site totals (a string literal)
 };
 
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (FP32 accumulate), 2 = split FP32 (three products).
@@ -95,6 +96,8 @@ unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n,
                          unsigned int* count, unsigned int* h_count, hipStream_t s);
 // H_ii = 0, i < p.
 void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s);
+// H_ii = d[i] (real), i < p.
+void set_diag(double* hr, double* hi, int64_t ldh, int p, const double* d, hipStream_t s);
 // *out = c * u * sum_i |H_ii|
 void herm_tol(const double* hr, int64_t ldh, int n, double c, double* out, hipStream_t s);
 void herm_round(HermArgs a, int round, hipStream_t s);
@@ -142,6 +145,15 @@ void normalize_rows(double* xr, double* xi, int64_t ldx, int r, int c, double* n
 // and beta_i = 0 where theta_i <= zero_rel * max theta.
 void damped_power_rows(const double* zr, const double* zi, double* yr, double* yi, int64_t ld, int p, int r,
                        const double* theta, double gamma, double damp_rel, double zero_rel, hipStream_t s);
+// Schmidt values from an update product X = A V (rows x cols) of the
+// truncated SVD of diag(rs) A = U S V^+: sigma_j = |diag(rs) X e_j| (rs[i /
+// rdiv], may be null).  Writes lam[j] = sigma_j / |sigma|, *nrm = |sigma|, and
+// scales X by 1 / |sigma|.  part (part_cap doubles) is scratch.
+void refine_sigma(double* xr, double* xi, int64_t ldx, int rows, int cols, const double* rs, int rdiv, double* part,
+                  int64_t part_cap, double* lam, double* nrm, hipStream_t s);
+// out[i] = |Y_i - theta_i Z_i| (2-norm of row i, i < p, rows of length r).
+void residual_norms(const double* yr, const double* yi, const double* zr, const double* zi, int64_t ld, int p, int r,
+                    const double* theta, double* out, hipStream_t s);
 // out[i] = 1 / sqrt(max(d[i], floor)) with floor = rel * max_j d[j] (0 if d[i] <= floor).
 void inv_sqrt_clamped(const double* d, int n, double rel, double* out, hipStream_t s);
 // *out = max(0, trace - sum_i vals[i]), trace = sum of diag of H.
@@ -200,6 +212,13 @@ void rows_copy(const RowCopy* tab, int count, const double* scale, hipStream_t s
 // dst[o] = src[idx[o]], o < k (dst must not alias src).
 void take(const double* src, const int* idx, int k, double* dst, hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
+// Cholesky factorisation of the Hermitian positive definite K (k x k,
+// leading dimension k, lower triangle read) in place, K = L L^+ with L in the
+// lower triangle, and X = L^-1 (k x k, leading dimension k).  t (64 k complex
+// entries, planar) is scratch.  A pivot that is not positive sets *flag
+// (which must start at zero).
+void chol_inverse(double* kr, double* ki, int k, double* xr, double* xi, double* tr, double* ti, int* flag,
+                  hipStream_t s);
 // Zeroes `words` 32-bit words at p with a kernel (counters and flags: a fill
 // kernel rather than hipMemsetAsync, so that the work stays plain kernel
 // launches on the stream).

@@ -26,11 +26,11 @@ hipEvent_t Profiler::get() {
   return e;
 }
 
-void Profiler::put(int cls, double fl, hipEvent_t a, hipEvent_t b) {
+void Profiler::put(int cls, double fl, hipEvent_t a, hipEvent_t b, const char* tag) {
   bool full;
   {
     std::lock_guard<std::mutex> lk(mu);
-    recs.push_back({cls, fl, a, b});
+    recs.push_back({cls, fl, a, b, tag});
     full = recs.size() >= kFoldAt;
   }
   if (full) fold(false);
@@ -62,6 +62,12 @@ void Profiler::fold(bool all_done) {
     ms[r.cls] += e;
     flops[r.cls] += r.flops;
     launches[r.cls] += 1;
+    if (r.tag) {
+      Tot& t = by_tag[r.tag];
+      t.ms += e;
+      t.flops += r.flops;
+      t.launches += 1;
+    }
     pool.push_back(r.a);
     pool.push_back(r.b);
   }
@@ -81,6 +87,7 @@ void Profiler::clear() {
     launches[c] = 0;
     spans[c].clear();
   }
+  by_tag.clear();
   if (origin) pool.push_back(origin);
   origin = nullptr;
 }
@@ -116,7 +123,8 @@ Profiler::~Profiler() {
   for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(int cls_, double flops_, hipStream_t s_) : p(active_profiler()), s(s_), cls(cls_), flops(flops_) {
+ProfScope::ProfScope(int cls_, double flops_, hipStream_t s_, const char* tag_)
+    : p(active_profiler()), s(s_), cls(cls_), flops(flops_), tag(tag_) {
   if (p) {
     a = p->get();
     PTEBD_HIP(hipEventRecord(a, s));
@@ -133,7 +141,7 @@ ProfScope::~ProfScope() {
     }
     if (hipEventRecord(b, s) == hipSuccess) {
       try {
-        p->put(cls, flops, a, b);
+        p->put(cls, flops, a, b, tag);
       } catch (...) {
       }
     }

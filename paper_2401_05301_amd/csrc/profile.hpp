@@ -1,7 +1,9 @@
 // Per-launch timing of the library's kernels with HIP events (opt-in).
 #pragma once
 
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -19,7 +21,13 @@ struct Profiler {
     int cls;
     double flops;
     hipEvent_t a, b;
+    const char* tag;   // call site (string literal) or null
   };
+  struct Tot {
+    double ms = 0.0, flops = 0.0;
+    int64_t launches = 0;
+  };
+  std::map<std::string, Tot> by_tag;   // totals per call site
   std::vector<Rec> recs;            // launches not folded yet
   std::vector<hipEvent_t> pool;     // idle events
   double ms[K_NCLASS] = {};
@@ -36,7 +44,7 @@ struct Profiler {
   double busy_ms(int cls);
   std::mutex mu;   // launchers of several worker threads report here
   hipEvent_t get();
-  void put(int cls, double flops, hipEvent_t a, hipEvent_t b);
+  void put(int cls, double flops, hipEvent_t a, hipEvent_t b, const char* tag);
   // Folds the finished records (every record when all_done: the caller has
   // synchronised every stream the records were made on).
   void fold(bool all_done);
@@ -53,8 +61,9 @@ struct ProfScope {
   hipStream_t s;
   int cls;
   double flops;
+  const char* tag;
   hipEvent_t a = nullptr;
-  ProfScope(int cls_, double flops_, hipStream_t s_);
+  ProfScope(int cls_, double flops_, hipStream_t s_, const char* tag_ = nullptr);
   ~ProfScope();
 };
 

@@ -51,12 +51,24 @@ def assert_close(ores, g, gn, gc, gd, tol):
     assert np.abs(gd - ores["D"]).max() <= tol, np.abs(gd - ores["D"]).max()
 
 
-def assert_spectra(ores, g, tol=1e-10):
+# The Gram route holds Schmidt *weights* s^2 to about 100 u: it takes them
+# from a Gram matrix whose eigenvectors near a cut at small s are fixed only
+# to u / gap, so a value s ~ 1e-5 can sit 1e-9 away from the oracle's while
+# the observables (the FP64 bar) agree to ~1e-11.
+GRAM_WEIGHT_TOL = 1e-12
+
+
+def assert_spectra(ores, g, tol=1e-10, weights=False):
+    """Schmidt values per bond against the oracle's, or their squares
+    (weights=True, the Gram route) to GRAM_WEIGHT_TOL."""
     assert g.bond_dims() == ores["mps"].bond_dims()
     for b in range(1, g.L):
         ls = g.lam(b)
         lo = ores["mps"].lam[b]
-        assert np.abs(ls - lo).max() < tol, (b, np.abs(ls - lo).max())
+        if weights:
+            assert np.abs(ls ** 2 - lo ** 2).max() < GRAM_WEIGHT_TOL, (b, np.abs(ls ** 2 - lo ** 2).max())
+        else:
+            assert np.abs(ls - lo).max() < tol, (b, np.abs(ls - lo).max())
 
 
 def test_exact_chi_config1(pt):
@@ -102,7 +114,7 @@ def test_gram_variant(pt):
     err = max(np.abs(gn - ores["n"]).max(), np.abs(gc - ores["C"]).max(), np.abs(gd - ores["D"]).max())
     note(f"gram variant L=8: max observable error {err:.3e}, min gap {ores['mps'].min_gap:.2e}")
     assert_close(ores, g, gn, gc, gd, bar(ores))
-    assert_spectra(ores, g, bar(ores))
+    assert_spectra(ores, g, weights=True)
 
 
 def test_gram_route_refuses_eps_below_its_floor(pt):
@@ -257,7 +269,10 @@ def test_supersite_two_site_variant(pt, L, d, chi, steps, svd):
     assert np.abs(D - ores["D"][-1]).max() <= tol, np.abs(D - ores["D"][-1]).max()
     assert g.bond_dims() == ores["mps"].bond_dims()
     for b in range(1, L // 2):
-        assert np.abs(g.lam(b) - ores["mps"].lam[b]).max() <= tol, b
+        if svd == 0:
+            assert np.abs(g.lam(b) - ores["mps"].lam[b]).max() <= tol, b
+        else:   # the Gram route resolves weights (see GRAM_WEIGHT_TOL)
+            assert np.abs(g.lam(b) ** 2 - ores["mps"].lam[b] ** 2).max() <= GRAM_WEIGHT_TOL, b
     assert abs(g.discarded_weight() - ores["w_total"][-1]) <= 1e-12 + 1e-6 * ores["w_total"][-1]
     g.close()
 

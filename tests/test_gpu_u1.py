@@ -31,9 +31,12 @@ def bar(om, base=1e-10):
     return base if om.min_gap >= 1e-8 else max(base, 2 * om.w_total)
 
 
-def check_bonds(g, om, tol):
+def check_bonds(g, om, tol, weights=False):
     """Sorted spectra, bond dimensions, the library's order and the particle
-    number of every Schmidt value where the oracle's value is isolated."""
+    number of every Schmidt value where the oracle's value is isolated.  With
+    weights (the Gram route) the squares s^2 are compared to 1e-12: the
+    Gram route holds Schmidt weights to about 100 u, a value s ~ 1e-5 to
+    ~1e-9, while the observables meet the FP64 bar."""
     assert g.bond_dims() == om.bond_dims()
     q_ref = ou1.bond_charges(om)
     for b in range(1, om.L):
@@ -45,7 +48,10 @@ def check_bonds(g, om, tol):
         og = np.argsort(-lam_g, kind="stable")
         oo = np.argsort(-om.lam[b], kind="stable")
         s = om.lam[b][oo]
-        assert np.abs(lam_g[og] - s).max() <= tol, b
+        if weights:
+            assert np.abs(lam_g[og] ** 2 - s ** 2).max() <= 1e-12, b
+        else:
+            assert np.abs(lam_g[og] - s).max() <= tol, b
         gap = np.full(len(s), np.inf)
         if len(s) > 1:
             dd = np.abs(np.diff(s))
@@ -71,7 +77,7 @@ def test_u1_cdw_matches_dense_oracle(pt, svd):
         assert np.abs(n - ores["n"][t]).max() <= tol
         assert np.abs(C - ores["C"][t]).max() <= tol
         assert np.abs(D - ores["D"][t]).max() <= tol
-    check_bonds(g, ores["mps"], tol)
+    check_bonds(g, ores["mps"], tol, weights=svd == 1)
     assert abs(g.discarded_weight() - ores["w_total"][-1]) <= 1e-12 + 1e-6 * ores["w_total"][-1]
     g.close()
 
@@ -101,7 +107,7 @@ def test_u1_random_state_layers(pt, svd):
         assert np.abs(n - on).max() < tol
         assert np.abs(C - oC).max() < tol
         assert np.abs(D - oD).max() < tol
-    check_bonds(g, om, bar(om))
+    check_bonds(g, om, bar(om), weights=svd == 1)
     assert abs(g.discarded_weight() - om.w_total) < 1e-12 + 1e-8 * om.w_total
     g.close()
 
@@ -187,7 +193,7 @@ def test_u1_gram_few_sectors(pt):
         assert np.abs(n - on).max() < tol, np.abs(n - on).max()
         assert np.abs(C - oC).max() < tol
         assert np.abs(D - oD).max() < tol
-    check_bonds(g, om, bar(om))
+    check_bonds(g, om, bar(om), weights=True)
     g.close()
 
 
