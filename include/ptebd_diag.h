@@ -39,6 +39,21 @@ tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32
 tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, const double* A, int32_t chi_max, double w_max,
                           double eps, int32_t* k, double* s, double* vh, double* nrm, double* w, int32_t* sweeps);
 
+/* tebd_diag_svd for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, tight serving loops, harnesses that forbid it):
+ * the same computation, arguments and outputs, but every device buffer
+ * (the input copy, the Jacobi and Gram workspaces, counters, the kept
+ * vectors) is carved from one file-scope device array of 8 MiB that each
+ * GPU holds until the process ends; the call makes no hipMalloc, hipFree or
+ * host-pinned allocation.  Limits: m, n <= 512 and m * n <= 65536, else
+ * TEBD_EINVAL before any device call.  Runs on the calling thread's current
+ * device and its null stream, and synchronises before returning.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several threads) race and must be serialised by the caller. */
+tebd_status tebd_diag_svd_noalloc(int32_t variant, int32_t m, int32_t n, const double* A, int32_t chi_max,
+                                  double w_max, double eps, int32_t* k, double* s, double* vh, double* nrm,
+                                  double* w, int32_t* sweeps);
+
 /* Per-call-site totals of the complex GEMM launches recorded by the handle's
  * profiler (mps_profile) since it was enabled: one text line per site,
  * "site launches device_ms algorithmic_flops", into out[cap] (NUL

@@ -464,7 +464,7 @@ def _load_diag():
     P = ctypes.POINTER
     _lib.tebd_diag_zgemm.restype = ctypes.c_int
     _lib.tebd_diag_zgemm.argtypes = [ctypes.c_int32] * 6 + [P(ctypes.c_double)] * 5 + [ctypes.c_int32, P(ctypes.c_double)]
-    for name in ("tebd_diag_svd",):
+    for name in ("tebd_diag_svd", "tebd_diag_svd_noalloc"):
         f = getattr(_lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
@@ -484,7 +484,7 @@ def _load_diag():
 
 
 _load_diag()
-EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_zgemm_time", "tebd_diag_gate",
+EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_svd_noalloc", "tebd_diag_zgemm_time", "tebd_diag_gate",
             "tebd_diag_bond_charges", "tebd_diag_profile_sites"]
 
 
@@ -560,8 +560,10 @@ def tebd_diag_zgemm(A: np.ndarray, B: np.ndarray, transA: int = 0, transB: int =
 
 
 def tebd_diag_svd(A: np.ndarray, variant: int = SVD_JACOBI, chi_max: int = 1 << 30, w_max: float = 0.0,
-                  eps: float = 0.0):
-    """Truncated SVD on the GPU: returns (s_normalised, vh, nrm, w, sweeps)."""
+                  eps: float = 0.0, noalloc: bool = False):
+    """Truncated SVD on the GPU: returns (s_normalised, vh, nrm, w, sweeps).
+    noalloc selects tebd_diag_svd_noalloc (no device allocation; m, n <= 512,
+    m * n <= 65536)."""
     m, n = A.shape
     r = min(m, n)
     pa = _planar(A)
@@ -570,7 +572,7 @@ def tebd_diag_svd(A: np.ndarray, variant: int = SVD_JACOBI, chi_max: int = 1 << 
     k = ctypes.c_int32()
     nrm, w = ctypes.c_double(), ctypes.c_double()
     sw = ctypes.c_int32()
-    fn = _lib.tebd_diag_svd
+    fn = _lib.tebd_diag_svd_noalloc if noalloc else _lib.tebd_diag_svd
     _check(fn(variant, m, n, _dptr(pa), min(chi_max, 2 ** 31 - 1), w_max, eps, ctypes.byref(k),
               _dptr(s), _dptr(vh), ctypes.byref(nrm), ctypes.byref(w), ctypes.byref(sw)))
     kk = k.value

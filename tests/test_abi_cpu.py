@@ -90,6 +90,17 @@ def test_gram_route_refuses_eps_below_its_floor():
     assert re.search(r"#define TEBD_GRAM_EPS_MIN 1e-6\b", txt)
 
 
+def test_noalloc_svd_rejects_oversize_input_without_gpu():
+    """tebd_diag_svd_noalloc refuses inputs beyond its scratch array before
+    any device call."""
+    import numpy as np
+    import paper_2401_05301_amd as pt
+    for shape in ((600, 8), (300, 300)):
+        with pytest.raises(pt.TebdError) as e:
+            pt.tebd_diag_svd(np.zeros(shape, dtype=np.complex128), variant=0, noalloc=True)
+        assert e.value.status == pt.TEBD_EINVAL and "65536" in str(e.value)
+
+
 def test_footprint_scales_with_chi():
     import paper_2401_05301_amd as pt
     m = pt.make_model(L=64, d=5, U=2.0, Jnnn=0.1)
