@@ -91,7 +91,6 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     M.G = z(r * r);
     M.W = z(r * r);
     M.g_cap = r * r;
-    M.rf = z(64 * mx);
     M.norms = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));
     M.inv_sig = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));
     M.sq = static_cast<double*>(ptebd::dev_alloc(&M, sizeof(double) * mx));

@@ -89,7 +89,7 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 size_t Sizes::bytes(int workers, bool u1) const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
-  int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h + 64 * vec);
+  int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
   w += 2 * (4 * sub_p * sub_r + 6 * sub_p * sub_p);
   w += 6 * vec + part + 64 + 5 * sub_p + 8;
   if (u1) {
@@ -214,7 +214,6 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->g_cap = s.G;
   W->W = zalloc(W, s.W);
   W->V1h = zalloc(W, s.V1h);
-  W->rf = zalloc(W, 64 * s.vec);
   W->ks = dalloc(W, s.vec);
   W->norms = dalloc(W, s.vec);
   W->inv_sig = dalloc(W, s.vec);
@@ -720,13 +719,16 @@ int run_herm_jacobi(tebd_mps* M, double* hr, double* hi, int64_t ldh, int n, dou
       std::fprintf(stderr, "[ptebd] herm-jacobi n=%d sweep=%d rotated_pairs=%u\n", n, sweep, *M->h_counter);
     }
   }
-  if (sweep_cap > 0) return sweep_cap;
+  if (sweep_cap > 0) {
+    M->last_sweeps = sweep_cap;
+    M->total_sweeps += sweep_cap;
+    return sweep_cap;
+  }
   if (converged()) {
     M->last_sweeps = max_sweeps;
     M->total_sweeps += max_sweeps;
     return max_sweeps;
   }
-  if (sweep_cap > 0) return sweep_cap;
   M->failed = true;
   throw Error(-4, "Hermitian Jacobi did not converge within max_sweeps (n " + std::to_string(n) + ")");
 }
@@ -1242,12 +1244,13 @@ constexpr double kRefineRatio = 1e-3;
 // Cholesky-QR of the k rows of V (length n, leading dimension ldv) in their
 // stored order: V <- L^-1 V with V V^+ = L L^+, so that row i loses its
 // components along rows 0..i-1 and every row ends with unit norm.  Uses the
-// Gram and eigenvector workspaces (G, W), rf, and out (k x n) as scratch;
+// Gram and eigenvector workspaces (G, W) and out (k x n, n >= k) as scratch;
 // leaves V unchanged if the factorisation breaks down (rows dependent).
 void cholqr_rows(tebd_mps* M, double* vr, double* vi, int64_t ldv, int k, int n, tebd_mps::Z out) {
   hipStream_t s = M->stream;
   if (k < 2) return;
   if ((int64_t)k * k > M->g_cap) throw Error(-1, "Cholesky-QR: k^2 exceeds the Gram workspace");
+  if (n < k) throw Error(-1, "Cholesky-QR: fewer columns than rows");
   {  // K = V V^+
     ZGemmArgs g;
     g.m = k; g.n = k; g.k = n;
@@ -1260,7 +1263,7 @@ void cholqr_rows(tebd_mps* M, double* vr, double* vi, int64_t ldv, int k, int n,
   }
   int* flag = M->info_i + 6;
   fill_zero_words(flag, 1, s);
-  chol_inverse(M->G.re, M->G.im, k, M->W.re, M->W.im, M->rf.re, M->rf.im, flag, s);
+  chol_inverse(M->G.re, M->G.im, k, M->W.re, M->W.im, out.re, out.im, flag, s);
   PTEBD_HIP(hipMemcpyAsync(M->h_info + 6, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
   if (M->h_info[6]) {

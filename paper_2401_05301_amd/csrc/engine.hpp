@@ -42,7 +42,6 @@ struct tebd_mps {
   // workspace (planar complex buffers: re, im)
   struct Z { double* re = nullptr; double* im = nullptr; };
   Z T1, psi, psip, X2, G, W, V1h;
-  Z rf;                         // Cholesky-QR scratch (64 x vec)
   Z sZ, sY, sZ2, sY2, sH, sW;   // subspace iteration: bases (p x r) and p x p blocks
   Z nY, nZ, nY2, nZ2;           // Newton-Schulz iterates (p x p)
   double* ns_part = nullptr;    // Newton-Schulz residual partial sums (256)

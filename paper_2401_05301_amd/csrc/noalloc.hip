@@ -92,7 +92,6 @@ extern "C" tebd_status tebd_diag_svd_noalloc(int32_t variant, int32_t m, int32_t
     M.G = c.z(r * r);
     M.W = c.z(r * r);
     M.g_cap = r * r;
-    M.rf = c.z(64 * mx);
     M.norms = c.take(mx);
     M.inv_sig = c.take(mx);
     M.sq = c.take(mx);
