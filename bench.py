@@ -200,6 +200,74 @@ def u1_sample(pt, torch, args, eps):
     return out
 
 
+def precision_batching(pt, torch, args):
+    """The same chi = 1024 state stepped four ways on this build: FP64 with
+    one gate worker (the plain per-gate form), FP64 with four concurrent
+    workers (the batched form), and the batched form with the theta/gate
+    products in FP32 and in split FP32.  Chain L = 16, d = 5 (its central
+    bonds at chi = 1024), one Strang step each from the same canonical
+    input.  Rates in gate-updates/s; for each FP32 form the largest
+    differences of n, C and D from the FP64 result on the same state (the
+    per-observable errors against the oracle at chi = 1024 are what the
+    full-size parity test checks)."""
+    import numpy as np
+    from workloads import CONFIGS, random_mps_device
+    cfg = CONFIGS["bulk_L64_chi1024"]
+    mdl, dt = cfg["model"], cfg["dt"]
+    L, d, chi = 16, mdl.d, args.chi
+    model = pt.make_model(L, d, mdl.U, mdl.J, mdl.Jnnn, mdl.K, (L + 1) / 2.0)
+    B, lam = random_mps_device(L, d, chi, seed=args.seed, tau=args.tau, bias=args.bias)
+    stream = torch.cuda.Stream()
+
+    def opts(prec, workers):
+        return pt.make_opts(chi, 1e-12, pt.GRAM_EPS_MIN, prec=prec, svd=pt.SVD_GRAM_EIG, stream=stream.cuda_stream,
+                            workers=workers)
+
+    g = pt.MPS.from_tensors(model, opts(pt.FP64, 4), B, lam)
+    del B, lam
+    g.canonicalize()
+    g.sync()
+    Bc = [g.site(i) for i in range(L)]
+    lc = [g.lam(b) for b in range(L + 1)]
+    g.close()
+    per_step = gate_updates_per_step(L)
+    res, obs = {}, {}
+    for name, prec, workers in [("fp64_plain_1_worker", pt.FP64, 1), ("fp64_batched_4_workers", pt.FP64, 4),
+                                ("fp32_batched_4_workers", pt.FP32, 4), ("split_batched_4_workers", pt.FP32_SPLIT, 4)]:
+        h = pt.MPS.from_tensors(model, opts(prec, workers), Bc, lc)
+        h.prepare(dt)
+        h.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        h.step(dt)
+        n, C, D = h.measure()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        obs[name] = (np.asarray(n), np.asarray(C), np.asarray(D))
+        res[name] = {"gate_updates_per_s": per_step / (ms / 1e3), "ms_per_step": ms,
+                     "discarded_weight": h.discarded_weight()}
+        h.close()
+        log(f"precision/batching leg: {name} {res[name]['gate_updates_per_s']:.2f} gate-updates/s")
+    ref = obs["fp64_batched_4_workers"]
+    for name in res:
+        if name == "fp64_batched_4_workers":
+            continue
+        n, C, D = obs[name]
+        res[name]["max_abs_diff_vs_fp64_batched"] = {
+            "n": float(np.abs(n - ref[0]).max()), "C": float(np.abs(C - ref[1]).max()),
+            "D": float(np.abs(D - ref[2]).max())}
+    plain = res["fp64_plain_1_worker"]["gate_updates_per_s"]
+    best = max(res[k]["gate_updates_per_s"] for k in res if k != "fp64_plain_1_worker")
+    return {"workload": f"L={L}, d={d}, chi={chi}, one Strang step ({per_step} gate updates) from the same "
+                        f"canonical random state (seed {args.seed})",
+            "forms": res, "batched_over_plain": best / plain,
+            "batched_mixed_precision_beats_plain_fp64": bool(
+                max(res["fp32_batched_4_workers"]["gate_updates_per_s"],
+                    res["split_batched_4_workers"]["gate_updates_per_s"]) > plain)}
+
+
 def measured_traffic():
     """HBM bytes per launch of the FP64 GEMM from the committed rocprofv3
     counter summary, or None when it is missing or the kernel source has
@@ -279,6 +347,8 @@ def main():
                     help="U(1) block-sparse SVDs on a random state of L/2 bosons with definite numbers per bond index")
     ap.add_argument("--no-square-gemm", action="store_true",
                     help="skip the square-GEMM reference (it launches this library's GEMM after the timed step)")
+    ap.add_argument("--no-precision-leg", action="store_true",
+                    help="skip the plain/batched FP64 vs batched FP32 comparison on an L = 16 chain")
     ap.add_argument("--no-u1-sample", action="store_true",
                     help="skip the U(1) step reported under u1_sample in the default run")
     ap.add_argument("--sigma", type=float, default=2.0,
@@ -489,6 +559,9 @@ def main():
     g.close()
     if not args.no_square_gemm and time_left():
         out["measured_square_gemm"] = measured_gemm_peak(pt, torch)
+    if not args.u1 and not args.no_precision_leg and args.prec == "fp64" and time_left():
+        log("precision/batching leg: plain FP64, batched FP64, batched FP32 and split FP32 on one state")
+        out["precision_batching"] = precision_batching(pt, torch, args)
     if not args.u1 and not args.no_u1_sample and time_left():
         log("U(1) sample: one step of the same chain with particle-number sectors")
         out["u1_sample"] = u1_sample(pt, torch, args, pt.GRAM_EPS_MIN)

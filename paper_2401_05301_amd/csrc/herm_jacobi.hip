@@ -55,14 +55,32 @@ struct Rot {
 
 // cs^2 + sn^2 = 1 and |e| = 1 hold to rounding whatever the accuracy of t,
 // since cs and e come from reciprocal square roots of the very quantities
-// they normalise; t only sets the angle.
+// they normalise; t only sets the angle.  So t = tan(angle) is taken from
+// the hardware reciprocal and reciprocal-square-root approximations, which
+// shortens the dependent chain of every step: an angle off in its last bits
+// leaves the rotation exactly unitary, and the remaining coupling is removed
+// by the following sweeps like any other.
 __device__ __forceinline__ Rot make_rot(double app, double aqq, double cre, double cim, double thr) {
   Rot r{1.0, 0.0, 1.0, 0.0};
   const double c2 = cre * cre + cim * cim;
   if (c2 > thr * thr) {
     const double rc = rsqrt(c2);   // 1 / |C_pq|
     const double tau = 0.5 * (aqq - app) * rc;
-    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double at = fabs(tau);
+    double t;
+    if (at < 1e150) {
+      // one Newton step on each hardware estimate
+      const double q = 1.0 + tau * tau;
+      const double y = __builtin_amdgcn_rsq(q);
+      double sq = q * y;
+      sq = fma(0.5 * y, fma(-sq, sq, q), sq);   // sqrt(q)
+      const double den = at + sq;
+      const double t0 = __builtin_amdgcn_rcp(den);
+      t = fma(t0, fma(-den, t0, 1.0), t0);      // 1 / den
+    } else {
+      t = 0.5 / at;
+    }
+    t = tau >= 0.0 ? t : -t;
     r.cs = rsqrt(1.0 + t * t);
     r.sn = t * r.cs;
     r.er = cre * rc;
