@@ -505,6 +505,7 @@ def main():
         "trunc_rule_counts": {k: rules1[k] - rules0[k] for k in rules1},
         "smallest_kept_lambda_ratio": lam_min,
         "jacobi_sweeps_per_gate_update": (sweeps1 - sweeps0) / (nsteps_gu * steps_run),
+        "theta_tile_tuner": g.tile_tuner(),
         "max_bond": max(chis),
     }
 

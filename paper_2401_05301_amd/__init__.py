@@ -444,6 +444,9 @@ class MPS:
     def profile_sites(self):
         return tebd_diag_profile_sites(self.h)
 
+    def tile_tuner(self):
+        return tebd_diag_tile_tuner(self.h)
+
     def profile_busy(self):
         return {name: mps_profile_busy(self.h, k) for name, k in KERNEL_CLASSES.items()}
 
@@ -474,6 +477,8 @@ def _load_diag():
 
     _lib.tebd_diag_profile_sites.restype = ctypes.c_int
     _lib.tebd_diag_profile_sites.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]
+    _lib.tebd_diag_tile_tuner.restype = ctypes.c_int
+    _lib.tebd_diag_tile_tuner.argtypes = [ctypes.c_void_p, P(ctypes.c_int64)]
     _lib.tebd_diag_zgemm_time.restype = ctypes.c_int
     _lib.tebd_diag_zgemm_time.argtypes = [ctypes.c_int32] * 5 + [P(ctypes.c_double)]
     _lib.tebd_diag_gate.restype = ctypes.c_int
@@ -485,7 +490,14 @@ def _load_diag():
 
 _load_diag()
 EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_svd_noalloc", "tebd_diag_zgemm_time", "tebd_diag_gate",
-            "tebd_diag_bond_charges", "tebd_diag_profile_sites"]
+            "tebd_diag_bond_charges", "tebd_diag_profile_sites", "tebd_diag_tile_tuner"]
+
+
+def tebd_diag_tile_tuner(h) -> dict:
+    """The handle's theta/gate tile tuner: shapes timed and later launches per tile."""
+    c = (ctypes.c_int64 * 3)()
+    _check(_lib.tebd_diag_tile_tuner(h, c))
+    return {"shapes_tuned": int(c[0]), "launches_64": int(c[1]), "launches_128": int(c[2])}
 
 
 def tebd_diag_profile_sites(h) -> dict:

@@ -482,6 +482,15 @@ extern "C" tebd_status tebd_diag_profile_sites(tebd_mps* M, char* out, int64_t c
   });
 }
 
+extern "C" tebd_status tebd_diag_tile_tuner(const tebd_mps* M, int64_t* counts) {
+  if (!M || !counts) return fail(TEBD_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(M->tuner->mu);
+  counts[0] = M->tuner->shapes_tuned;
+  counts[1] = M->tuner->launches_64;
+  counts[2] = M->tuner->launches_128;
+  return TEBD_OK;
+}
+
 tebd_status mps_sync(tebd_mps* M) {
   if (!M) return fail(TEBD_EINVAL, "handle is NULL");
   return guard([&] { PTEBD_HIP(hipStreamSynchronize(M->stream)); });

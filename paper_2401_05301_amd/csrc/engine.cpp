@@ -1727,6 +1727,59 @@ std::vector<std::vector<int>> infer_charges(const tebd_mps* M, const int* chi, c
 namespace {
 
 // One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
+bool autotune_enabled() {
+  static const bool v = std::getenv("PTEBD_NO_AUTOTUNE") == nullptr;
+  return v;
+}
+
+// A theta or gate product with the tile shape the handle's tuner picked for
+// its (m, n, k, batch).  A shape seen for the first time is run three times
+// with each FP64 tile on the worker's stream (the products overwrite their
+// output and read only their inputs, so the repetitions leave the result as
+// one launch would) and the faster tile is kept for the life of the handle.
+// Both tiles accumulate every output element in the same K order, so the
+// choice does not change the result.  FP32 products have one tile shape.
+void tuned_gemm(tebd_mps* S, ZGemmArgs g, int prec, hipStream_t s) {
+  ptebd::TileTuner& T = *S->tuner;
+  if (prec != 0 || !autotune_enabled() || g.beta) {
+    zgemm(g, prec, s);
+    return;
+  }
+  const std::array<int64_t, 4> key{g.m, g.n, g.k, g.batch};
+  {
+    std::lock_guard<std::mutex> lk(T.mu);
+    auto it = T.best.find(key);
+    if (it != T.best.end()) {
+      g.tile = it->second;
+      (g.tile == 128 ? T.launches_128 : T.launches_64) += 1;
+    }
+  }
+  if (g.tile) {
+    zgemm(g, prec, s);
+    return;
+  }
+  hipEvent_t e[3];
+  for (auto& x : e) PTEBD_HIP(hipEventCreate(&x));
+  float ms[2] = {0.f, 0.f};
+  const int tiles[2] = {64, 128};
+  for (int v = 0; v < 2; ++v) {
+    g.tile = tiles[v];
+    zgemm(g, prec, s);   // warm
+    PTEBD_HIP(hipEventRecord(e[0], s));
+    for (int r = 0; r < 3; ++r) zgemm(g, prec, s);
+    PTEBD_HIP(hipEventRecord(e[1], s));
+    PTEBD_HIP(hipEventSynchronize(e[1]));
+    PTEBD_HIP(hipEventElapsedTime(&ms[v], e[0], e[1]));
+  }
+  for (auto& x : e) PTEBD_HIP(hipEventDestroy(x));
+  const int pick = ms[1] < ms[0] ? 128 : 64;
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.best.emplace(key, pick).second) ++T.shapes_tuned;
+  if (debug_enabled())
+    std::fprintf(stderr, "[ptebd] tile tuner m=%ld n=%ld k=%ld batch=%ld: 64 %.3f ms, 128 %.3f ms -> %d\n",
+                 (long)g.m, (long)g.n, (long)g.k, (long)g.batch, ms[0] / 3, ms[1] / 3, pick);
+}
+
 // stream and settings of worker W.
 void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {
   hipStream_t s = W->stream;
@@ -1740,7 +1793,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.br = S->Br[j + 1]; g.bi = S->Bi[j + 1]; g.ldb = (int64_t)d * c2;
     g.cr = W->T1.re; g.ci = W->T1.im; g.ldc = (int64_t)d * c2;
     g.tag = "theta";
-    zgemm(g, prec, s);
+    tuned_gemm(S, g, prec, s);
   }
   {  // psi = T1 B_{j+2}
     ZGemmArgs g;
@@ -1749,7 +1802,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = (int64_t)d * cr;
     g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)d * cr;
     g.tag = "theta";
-    zgemm(g, prec, s);
+    tuned_gemm(S, g, prec, s);
   }
   {  // psi'[a] = G psi[a]
     ZGemmArgs g;
@@ -1758,7 +1811,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)d3 * cr;
     g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)d3 * cr;
     g.tag = "gate";
-    zgemm(g, prec, s);
+    tuned_gemm(S, g, prec, s);
   }
   const int m1 = cl * d, n1 = d * d * cr;
   SvdIn in1{W->psip.re, W->psip.im, n1, m1, n1, S->lam[j], d};
@@ -1866,7 +1919,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = (int64_t)D * cr;
     g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)D * cr;
     g.tag = "theta";
-    zgemm(g, prec, s);
+    tuned_gemm(S, g, prec, s);
   }
   {  // psi'[a] = G psi[a]
     ZGemmArgs g;
@@ -1875,7 +1928,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)D2 * cr;
     g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)D2 * cr;
     g.tag = "gate";
-    zgemm(g, prec, s);
+    tuned_gemm(S, g, prec, s);
   }
   const int m1 = cl * D, n1 = D * cr;
   SvdIn in{W->psip.re, W->psip.im, n1, m1, n1, S->lam[K], D};

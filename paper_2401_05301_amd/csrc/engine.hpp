@@ -1,7 +1,10 @@
 // MPS store and gate-update driver (host side).
 #pragma once
 
+#include <array>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -11,7 +14,19 @@
 #include "kernels.hpp"
 #include "profile.hpp"
 
+namespace ptebd {
+// Tile shapes of the theta and gate products chosen by measurement: for
+// every (m, n, k, batch) seen, the faster of the 64 x 64 and 128 x 128 FP64
+// tiles, timed on the real operands at first use.
+struct TileTuner {
+  std::mutex mu;
+  std::map<std::array<int64_t, 4>, int> best;
+  int64_t shapes_tuned = 0, launches_128 = 0, launches_64 = 0;
+};
+}  // namespace ptebd
+
 struct tebd_mps {
+  std::unique_ptr<ptebd::TileTuner> tuner = std::make_unique<ptebd::TileTuner>();
   ptebd::ModelP model{};
   tebd_opts opts{};
   hipStream_t stream = nullptr;

@@ -324,6 +324,7 @@ int64_t tiles(const ZGemmArgs& a, int bm, int bn) {
 void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
   if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return;
   if (a.k <= 0) throw Error(-1, "zgemm: k must be positive");
+  if (a.tile != 0 && a.tile != 64 && a.tile != 128) throw Error(-1, "zgemm: tile must be 0, 64 or 128");
   if (a.herm_out) {
     // C = X X^+ is Hermitian: only tiles on or below the diagonal are computed
     if (a.m != a.n || a.beta || a.col_scale != a.row_scale || a.col_div != a.row_div)
@@ -337,7 +338,7 @@ void zgemm(const ZGemmArgs& a, int prec, hipStream_t s) {
     case 0: {
       // 128 x 128 tiles halve the operand traffic per flop; they pay off
       // when the launch fills the chip with them without a thin last wave
-      if (wide_tiles_pay(tiles(a, 128, 128)))
+      if (a.tile == 128 || (a.tile == 0 && wide_tiles_pay(tiles(a, 128, 128))))
         launch<0, 128, 128, 16, 4, 2>(a, s);
       else
         launch<0, 64, 64, 16, 2, 2>(a, s);

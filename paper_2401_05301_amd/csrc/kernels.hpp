@@ -28,6 +28,7 @@ struct ZGemmArgs {
   int beta = 0;
   int herm_out = 0;   // C = X X^+ (Hermitian): accounted as 4 m^2 k flops
   const char* tag = "gemm";   // call site, for the profiler's per-site totals (a string literal)
+  int tile = 0;               // FP64 tile edge: 0 = the launch rule, 64 or 128 = that tile
 };
 
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (FP32 accumulate), 2 = split FP32 (three products).

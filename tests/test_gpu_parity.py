@@ -210,6 +210,25 @@ def test_layer_workers_give_identical_results(pt):
     assert a[4] == b[4]
 
 
+def test_theta_tile_tuner(pt):
+    """The theta/gate tile tuner times each new (m, n, k, batch) once per
+    handle and reuses its choice; the FP64 result does not depend on the tile
+    (both tiles accumulate every element in the same K order), which the
+    worker test above also sees, since each handle tunes on its own."""
+    L, d, chi = 12, 5, 96
+    B, lam = random_mps(L, d, chi, seed=4, tau=20.0)
+    m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, 1e-12, GRAM_EPS, svd=1, workers=1), B, lam)
+    g.layer(2, 0.01)
+    t1 = g.tile_tuner()
+    g.layer(2, 0.01)
+    t2 = g.tile_tuner()
+    note(f"tile tuner after one layer {t1}, after two {t2}")
+    g.close()
+    assert t1["shapes_tuned"] > 0
+    assert t2["launches_64"] + t2["launches_128"] > t1["launches_64"] + t1["launches_128"]
+
+
 @pytest.mark.parametrize("L,N,d,chi,steps", [(41, 11, 3, 24, 6), (121, 27, 5, 16, 3)])
 def test_centred_cdw_quasi_local(pt, L, N, d, chi, steps):
     """The experiment's workload shape (Sec. II B): a centred CDW with empty
