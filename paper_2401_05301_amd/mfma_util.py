@@ -30,6 +30,12 @@ SETTINGS = {
 }
 
 
+
+def launch_flops(roof: dict) -> float:
+    """Algorithmic flops one GEMM launch issues on average in the profiled
+    step (bench.py's issued_flops_per_launch; older lines: flops_per_launch)."""
+    return float(roof.get("issued_flops_per_launch", roof.get("flops_per_launch")))
+
 def command(prec: str) -> str:
     counter, _, flags, _ = SETTINGS[prec]
     return (f"rocprofv3 --pmc MfmaUtil {counter} --kernel-include-regex zgemm_kernel --output-format csv "
@@ -87,8 +93,8 @@ def main():
         "mfma_util_percent_mean": util_mean,
         "mfma_util_percent_time_weighted": util_w,
         f"mfma_flops_{a.prec}_per_launch": flops_launch,
-        "algorithmic_flops_per_launch": roof["flops_per_launch"],
-        "executed_over_algorithmic": flops_launch / roof["flops_per_launch"],
+        "algorithmic_flops_per_launch": launch_flops(roof),
+        "executed_over_algorithmic": flops_launch / launch_flops(roof),
         "serialised_rate_TFLOPs": (sum(flops) / sum(ns) / 1e3) if timed else None,
     }
     with open(a.out + ".json", "w") as f:
@@ -108,7 +114,7 @@ def main():
         f"- MfmaUtil (matrix cores busy, share of SIMD cycles): {util_mean:.1f}% averaged over launches"
         + (f", {util_w:.1f}% weighted by launch duration." if timed else "."),
         f"- {width} flops executed on the matrix cores per launch: {flops_launch / 1e9:.2f} GFLOP, "
-        f"{out['executed_over_algorithmic']:.3f} times the {roof['flops_per_launch'] / 1e9:.2f} GFLOP algorithmic "
+        f"{out['executed_over_algorithmic']:.3f} times the {launch_flops(roof) / 1e9:.2f} GFLOP algorithmic "
         + ("count (the excess is the whole diagonal tiles of the Hermitian Gram products, which count as half, "
            "and the zero-padded edges of partial tiles)." if a.prec == "fp64" else
            "count (the excess is the zero-padded edges of partial tiles)."),

@@ -25,6 +25,12 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+
+def launch_flops(roof: dict) -> float:
+    """Algorithmic flops one GEMM launch issues on average in the profiled
+    step (bench.py's issued_flops_per_launch; older lines: flops_per_launch)."""
+    return float(roof.get("issued_flops_per_launch", roof.get("flops_per_launch")))
+
 def gemm_source_hash() -> str:
     with open(os.path.join(HERE, "csrc", "gemm.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
@@ -80,8 +86,8 @@ def main():
         "traffic_bytes_per_launch": per_launch,
         "fetch_scale": f_scale,
         "write_scale": w_scale,
-        "flops_per_launch": roof["flops_per_launch"],
-        "flop_per_hbm_byte": roof["flops_per_launch"] / per_launch,
+        "flops_per_launch": launch_flops(roof),
+        "flop_per_hbm_byte": launch_flops(roof) / per_launch,
         "gemm_source_sha256": gemm_source_hash(),
     }
     with open(a.out + ".json", "w") as f:
@@ -93,9 +99,9 @@ def main():
         "",
         "```",
         "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_fetch -- python -u bench.py --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm",
+        "-o bench_fetch -- python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
         "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_write -- python -u bench.py --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm",
+        "-o bench_write -- python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc -o copy_fetch -- python -u bench.py "
         "--copy-calibration 1024",
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc -o copy_write -- python -u bench.py "
@@ -111,7 +117,7 @@ def main():
         f"{w_scale:.4f} (write).",
         f"- GEMM launches of the timed step: {n}.",
         f"- Per launch: {read_b / 1e6:.1f} MB read, {write_b / 1e6:.1f} MB written from/to HBM; "
-        f"{roof['flops_per_launch'] / 1e9:.2f} GFLOP algorithmic; {out['flop_per_hbm_byte']:.0f} flop per HBM byte "
+        f"{launch_flops(roof) / 1e9:.2f} GFLOP algorithmic; {out['flop_per_hbm_byte']:.0f} flop per HBM byte "
         "(the FP64 MFMA ridge is 78.6e12 / 8e12 = 9.8).",
         f"- gemm.hip sha256 {out['gemm_source_sha256'][:16]}...: bench.py reports this traffic only while the "
         "kernel source is unchanged.",
