@@ -19,6 +19,7 @@ namespace ptebd {
 namespace {
 
 constexpr int CB = 64;
+constexpr int kBlockThreads = 1024;   // 64 rows x 16 column lanes
 
 // Factorises the nb x nb diagonal block at (b0, b0) of K in place (L in the
 // lower triangle, zeros above) and writes its inverse into the same block of
@@ -30,17 +31,17 @@ constexpr int CB = 64;
 // only column j and the pivot, so one barrier per column suffices; the
 // columns are scaled by 1 / sqrt(a_jj) afterwards.  The inverse follows by
 // the same right-looking pattern: row p of X is final once the earlier rows
-// have been subtracted, and is scaled at the end.  Thread (r, q) of 64 x 4
-// owns row r and every fourth column of the trailing block.
+// have been subtracted, and is scaled at the end.  Thread (r, q) of 64 x 16
+// owns row r and every sixteenth column of the trailing block.
 __device__ __forceinline__ double fixed_pivot(double d) { return (d > 0.0 && d < 1e300) ? d : 1.0; }
 
-__global__ __launch_bounds__(256) void chol_block_kernel(double* kr, double* ki, int64_t ld, int b0, int nb,
+__global__ __launch_bounds__(kBlockThreads) void chol_block_kernel(double* kr, double* ki, int64_t ld, int b0, int nb,
                                                          double* xr, double* xi, int* flag) {
   __shared__ double Ar[CB][CB + 1], Ai[CB][CB + 1];
   __shared__ double Xr[CB][CB + 1], Xi[CB][CB + 1];
   const int tid = threadIdx.x;
-  const int r = tid >> 2, q = tid & 3;
-  for (int idx = tid; idx < nb * nb; idx += 256) {
+  const int r = tid >> 4, q = tid & 15;
+  for (int idx = tid; idx < nb * nb; idx += kBlockThreads) {
     const int i = idx / nb, c = idx % nb;
     const int64_t o = (int64_t)(b0 + i) * ld + b0 + c;
     Ar[i][c] = c <= i ? kr[o] : 0.0;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(double* kr, double* ki,
     const int i = j + 1 + r;
     if (i < nb) {
       const double lr = Ar[i][j] * rd, li = Ai[i][j] * rd;
-      for (int c = j + 1 + q; c <= i; c += 4) {
+      for (int c = j + 1 + q; c <= i; c += 16) {
         const double mr = Ar[c][j], mi = Ai[c][j];
         Ar[i][c] -= lr * mr + li * mi;
         Ai[i][c] -= li * mr - lr * mi;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(double* kr, double* ki,
     for (int j = 0; j < nb; ++j)
       if (!(Ar[j][j] > 0.0 && Ar[j][j] < 1e300)) *flag = 1;
   // scale column c by 1 / sqrt(pivot) (rows below the diagonal), pivot -> sqrt
-  for (int idx = tid; idx < nb * nb; idx += 256) {
+  for (int idx = tid; idx < nb * nb; idx += kBlockThreads) {
     const int i = idx / nb, c = idx % nb;
     if (i > c) {
       const double s = 1.0 / sqrt(fixed_pivot(Ar[c][c]));
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(double* kr, double* ki,
     if (i < nb) {
       const double d = 1.0 / Ar[p][p];
       const double lr = Ar[i][p] * d, li = Ai[i][p] * d;
-      for (int c = q; c <= p; c += 4) {
+      for (int c = q; c <= p; c += 16) {
         const double yr = Xr[p][c], yi = Xi[p][c];
         Xr[i][c] -= lr * yr - li * yi;
         Xi[i][c] -= lr * yi + li * yr;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(double* kr, double* ki,
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < nb * nb; idx += 256) {
+  for (int idx = tid; idx < nb * nb; idx += kBlockThreads) {
     const int i = idx / nb, c = idx % nb;
     const int64_t o = (int64_t)(b0 + i) * ld + b0 + c;
     const double d = 1.0 / Ar[i][i];
@@ -115,7 +116,7 @@ void chol_inverse(double* kr, double* ki, int k, double* xr, double* xi, double*
   fill_zero(xi, (int64_t)k * k, s);
   for (int b0 = 0; b0 < k; b0 += CB) {
     const int nb = std::min(CB, k - b0);
-    chol_block_kernel<<<1, 256, 0, s>>>(kr, ki, ld, b0, nb, xr, xi, flag);
+    chol_block_kernel<<<1, kBlockThreads, 0, s>>>(kr, ki, ld, b0, nb, xr, xi, flag);
     PTEBD_LAUNCH_CHECK();
     const int rest = k - b0 - nb;
     if (rest <= 0) break;
