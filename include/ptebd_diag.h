@@ -60,13 +60,14 @@ tebd_status tebd_diag_svd_noalloc(int32_t variant, int32_t m, int32_t n, const d
  * terminated; EINVAL if it does not fit).  Synchronises. */
 tebd_status tebd_diag_profile_sites(tebd_mps* mps, char* out, int64_t cap);
 
-/* The handle's tile tuner for the theta and gate products (FP64): counts[0]
- * = (m, n, k, batch) shapes timed so far (each with both the 64 x 64 and the
- * 128 x 128 tile, three launches apiece, the faster kept), counts[1] and
- * counts[2] = later launches that took the 64 x 64 and the 128 x 128 tile.
- * The environment variable PTEBD_NO_AUTOTUNE switches the tuner off (the
- * fixed launch rule then picks every tile).  Host only. */
-tebd_status tebd_diag_tile_tuner(const tebd_mps* mps, int64_t* counts);
+/* The process-wide tile tuner of the theta and gate products (FP64, shared
+ * by every handle): counts[0] = (device, m, n, k, batch) shapes timed so far
+ * (each with both the 64 x 64 and the 128 x 128 tile, three launches apiece,
+ * the faster kept), counts[1] and counts[2] = later launches that took the
+ * 64 x 64 and the 128 x 128 tile.  The environment variable
+ * PTEBD_NO_AUTOTUNE switches the tuner off (the fixed launch rule then picks
+ * every tile).  Host only. */
+tebd_status tebd_diag_tile_tuner(int64_t* counts);
 
 /* Average device time (ms, HIP events) of `reps` launches of the complex GEMM
  * kernel on device-resident m x k and k x n operands (contents unspecified,

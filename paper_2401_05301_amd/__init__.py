@@ -445,7 +445,7 @@ class MPS:
         return tebd_diag_profile_sites(self.h)
 
     def tile_tuner(self):
-        return tebd_diag_tile_tuner(self.h)
+        return tebd_diag_tile_tuner()
 
     def profile_busy(self):
         return {name: mps_profile_busy(self.h, k) for name, k in KERNEL_CLASSES.items()}
@@ -478,7 +478,7 @@ def _load_diag():
     _lib.tebd_diag_profile_sites.restype = ctypes.c_int
     _lib.tebd_diag_profile_sites.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]
     _lib.tebd_diag_tile_tuner.restype = ctypes.c_int
-    _lib.tebd_diag_tile_tuner.argtypes = [ctypes.c_void_p, P(ctypes.c_int64)]
+    _lib.tebd_diag_tile_tuner.argtypes = [P(ctypes.c_int64)]
     _lib.tebd_diag_zgemm_time.restype = ctypes.c_int
     _lib.tebd_diag_zgemm_time.argtypes = [ctypes.c_int32] * 5 + [P(ctypes.c_double)]
     _lib.tebd_diag_gate.restype = ctypes.c_int
@@ -493,10 +493,10 @@ EXPORTS += ["tebd_diag_zgemm", "tebd_diag_svd", "tebd_diag_svd_noalloc", "tebd_d
             "tebd_diag_bond_charges", "tebd_diag_profile_sites", "tebd_diag_tile_tuner"]
 
 
-def tebd_diag_tile_tuner(h) -> dict:
-    """The handle's theta/gate tile tuner: shapes timed and later launches per tile."""
+def tebd_diag_tile_tuner() -> dict:
+    """The process-wide theta/gate tile tuner: shapes timed and later launches per tile."""
     c = (ctypes.c_int64 * 3)()
-    _check(_lib.tebd_diag_tile_tuner(h, c))
+    _check(_lib.tebd_diag_tile_tuner(c))
     return {"shapes_tuned": int(c[0]), "launches_64": int(c[1]), "launches_128": int(c[2])}
 
 

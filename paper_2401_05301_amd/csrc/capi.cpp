@@ -482,12 +482,13 @@ extern "C" tebd_status tebd_diag_profile_sites(tebd_mps* M, char* out, int64_t c
   });
 }
 
-extern "C" tebd_status tebd_diag_tile_tuner(const tebd_mps* M, int64_t* counts) {
-  if (!M || !counts) return fail(TEBD_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(M->tuner->mu);
-  counts[0] = M->tuner->shapes_tuned;
-  counts[1] = M->tuner->launches_64;
-  counts[2] = M->tuner->launches_128;
+extern "C" tebd_status tebd_diag_tile_tuner(int64_t* counts) {
+  if (!counts) return fail(TEBD_EINVAL, "NULL argument");
+  ptebd::TileTuner& T = ptebd::tile_tuner();
+  std::lock_guard<std::mutex> lk(T.mu);
+  counts[0] = T.shapes_tuned;
+  counts[1] = T.launches_64;
+  counts[2] = T.launches_128;
   return TEBD_OK;
 }
 

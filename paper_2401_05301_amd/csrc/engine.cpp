@@ -1724,28 +1724,35 @@ std::vector<std::vector<int>> infer_charges(const tebd_mps* M, const int* chi, c
   return q;
 }
 
+TileTuner& tile_tuner() {
+  static TileTuner t;
+  return t;
+}
+
 namespace {
 
-// One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
 bool autotune_enabled() {
   static const bool v = std::getenv("PTEBD_NO_AUTOTUNE") == nullptr;
   return v;
 }
 
-// A theta or gate product with the tile shape the handle's tuner picked for
-// its (m, n, k, batch).  A shape seen for the first time is run three times
-// with each FP64 tile on the worker's stream (the products overwrite their
-// output and read only their inputs, so the repetitions leave the result as
-// one launch would) and the faster tile is kept for the life of the handle.
-// Both tiles accumulate every output element in the same K order, so the
-// choice does not change the result.  FP32 products have one tile shape.
-void tuned_gemm(tebd_mps* S, ZGemmArgs g, int prec, hipStream_t s) {
-  ptebd::TileTuner& T = *S->tuner;
+// A theta or gate product with the tile shape the tuner picked for its
+// (device, m, n, k, batch).  A shape seen for the first time is run three
+// times with each FP64 tile on the worker's stream (the products overwrite
+// their output and read only their inputs, so the repetitions leave the
+// result as one launch would) and the faster tile is kept for the life of
+// the process, for every handle.  Both tiles accumulate every output element
+// in the same K order, so the choice does not change the result.  FP32
+// products have one tile shape.
+void tuned_gemm(ZGemmArgs g, int prec, hipStream_t s) {
+  ptebd::TileTuner& T = tile_tuner();
   if (prec != 0 || !autotune_enabled() || g.beta) {
     zgemm(g, prec, s);
     return;
   }
-  const std::array<int64_t, 4> key{g.m, g.n, g.k, g.batch};
+  int dev = 0;
+  PTEBD_HIP(hipGetDevice(&dev));
+  const std::array<int64_t, 5> key{dev, g.m, g.n, g.k, g.batch};
   {
     std::lock_guard<std::mutex> lk(T.mu);
     auto it = T.best.find(key);
@@ -1780,6 +1787,7 @@ void tuned_gemm(tebd_mps* S, ZGemmArgs g, int prec, hipStream_t s) {
                  (long)g.m, (long)g.n, (long)g.k, (long)g.batch, ms[0] / 3, ms[1] / 3, pick);
 }
 
+// One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
 // stream and settings of worker W.
 void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {
   hipStream_t s = W->stream;
@@ -1793,7 +1801,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.br = S->Br[j + 1]; g.bi = S->Bi[j + 1]; g.ldb = (int64_t)d * c2;
     g.cr = W->T1.re; g.ci = W->T1.im; g.ldc = (int64_t)d * c2;
     g.tag = "theta";
-    tuned_gemm(S, g, prec, s);
+    tuned_gemm(g, prec, s);
   }
   {  // psi = T1 B_{j+2}
     ZGemmArgs g;
@@ -1802,7 +1810,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = (int64_t)d * cr;
     g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)d * cr;
     g.tag = "theta";
-    tuned_gemm(S, g, prec, s);
+    tuned_gemm(g, prec, s);
   }
   {  // psi'[a] = G psi[a]
     ZGemmArgs g;
@@ -1811,7 +1819,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)d3 * cr;
     g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)d3 * cr;
     g.tag = "gate";
-    tuned_gemm(S, g, prec, s);
+    tuned_gemm(g, prec, s);
   }
   const int m1 = cl * d, n1 = d * d * cr;
   SvdIn in1{W->psip.re, W->psip.im, n1, m1, n1, S->lam[j], d};
@@ -1919,7 +1927,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = (int64_t)D * cr;
     g.cr = W->psi.re; g.ci = W->psi.im; g.ldc = (int64_t)D * cr;
     g.tag = "theta";
-    tuned_gemm(S, g, prec, s);
+    tuned_gemm(g, prec, s);
   }
   {  // psi'[a] = G psi[a]
     ZGemmArgs g;
@@ -1928,7 +1936,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.br = W->psi.re; g.bi = W->psi.im; g.ldb = cr; g.sB = (int64_t)D2 * cr;
     g.cr = W->psip.re; g.ci = W->psip.im; g.ldc = cr; g.sC = (int64_t)D2 * cr;
     g.tag = "gate";
-    tuned_gemm(S, g, prec, s);
+    tuned_gemm(g, prec, s);
   }
   const int m1 = cl * D, n1 = D * cr;
   SvdIn in{W->psip.re, W->psip.im, n1, m1, n1, S->lam[K], D};

@@ -15,18 +15,18 @@
 #include "profile.hpp"
 
 namespace ptebd {
-// Tile shapes of the theta and gate products chosen by measurement: for
-// every (m, n, k, batch) seen, the faster of the 64 x 64 and 128 x 128 FP64
-// tiles, timed on the real operands at first use.
+// Tile shapes of the theta and gate products chosen by measurement, for the
+// whole process: for every (device, m, n, k, batch) seen, the faster of the
+// 64 x 64 and 128 x 128 FP64 tiles, timed on the real operands at first use.
 struct TileTuner {
   std::mutex mu;
-  std::map<std::array<int64_t, 4>, int> best;
+  std::map<std::array<int64_t, 5>, int> best;
   int64_t shapes_tuned = 0, launches_128 = 0, launches_64 = 0;
 };
+TileTuner& tile_tuner();
 }  // namespace ptebd
 
 struct tebd_mps {
-  std::unique_ptr<ptebd::TileTuner> tuner = std::make_unique<ptebd::TileTuner>();
   ptebd::ModelP model{};
   tebd_opts opts{};
   hipStream_t stream = nullptr;
