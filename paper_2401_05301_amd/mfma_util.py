@@ -30,17 +30,17 @@ SETTINGS = {
 }
 
 
-
 def launch_flops(roof: dict) -> float:
     """Algorithmic flops one GEMM launch issues on average in the profiled
     step (bench.py's issued_flops_per_launch; older lines: flops_per_launch)."""
     return float(roof.get("issued_flops_per_launch", roof.get("flops_per_launch")))
 
+
 def command(prec: str) -> str:
     counter, _, flags, _ = SETTINGS[prec]
     return (f"rocprofv3 --pmc MfmaUtil {counter} --kernel-include-regex zgemm_kernel --output-format csv "
-            f"-d <dir>/mfma -o bench_mfma -- python -u bench.py --no-cpu-baseline --serve 0 --no-u1-sample "
-            f"--no-square-gemm{flags}")
+            f"-d <dir>/mfma -o bench_mfma -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline "
+            f"--serve 0 --no-u1-sample --no-square-gemm --no-precision-leg{flags}")
 
 
 def dispatches(path: str, name_part: str):
@@ -121,8 +121,7 @@ def main():
     ]
     if timed:
         md.append(f"- Executed rate over the profiled dispatches: {out['serialised_rate_TFLOPs']:.1f} TFLOP/s "
-                  "(counter collection runs the dispatches one at a time, so the four gate workers do not overlap "
-                  "here).")
+                  "(counter collection runs the dispatches one at a time, so launches do not overlap here).")
     md.append("")
     with open(a.out + ".md", "w") as f:
         f.write("\n".join(md))

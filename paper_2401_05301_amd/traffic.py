@@ -25,11 +25,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-
 def launch_flops(roof: dict) -> float:
     """Algorithmic flops one GEMM launch issues on average in the profiled
     step (bench.py's issued_flops_per_launch; older lines: flops_per_launch)."""
     return float(roof.get("issued_flops_per_launch", roof.get("flops_per_launch")))
+
 
 def gemm_source_hash() -> str:
     with open(os.path.join(HERE, "csrc", "gemm.hip"), "rb") as f:
@@ -99,9 +99,9 @@ def main():
         "",
         "```",
         "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_fetch -- python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
+        "-o bench_fetch -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
         "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_write -- python -u bench.py --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
+        "-o bench_write -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc -o copy_fetch -- python -u bench.py "
         "--copy-calibration 1024",
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc -o copy_write -- python -u bench.py "
