@@ -102,8 +102,8 @@ typedef struct {
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
   int32_t workers;        /* gate workspaces run concurrently within a layer (own stream and host
-                             thread each); 0 = min(4, gates per layer).  Device memory grows by one
-                             gate workspace per worker. */
+                             thread each); 0 = min(6, gates per layer), or min(4, gates per layer)
+                             with u1.  Device memory grows by one gate workspace per worker. */
   int32_t supersite;      /* 1: the paper's super-site chain (Sec. II B): every two physical sites
                              form one site of dimension d^2 and two-site gates act on neighbouring
                              super sites, Strang A(dt/2) B(dt) A(dt/2) over gates K even / K odd.

@@ -400,11 +400,11 @@ tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t
       return fail(TEBD_EINVAL, "a super-site chain needs an even number of physical sites, at least 4");
     const int Ls = model->L / 2;
     *bytes = ptebd::plan_sizes2(Ls, model->d * model->d, opts->chi_max)
-                 .bytes(ptebd::auto_workers(Ls, opts->workers, true), opts->u1 != 0);
+                 .bytes(ptebd::auto_workers(Ls, opts->workers, true, opts->u1 != 0), opts->u1 != 0);
     return TEBD_OK;
   }
   *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max)
-               .bytes(ptebd::auto_workers(model->L, opts->workers), opts->u1 != 0);
+               .bytes(ptebd::auto_workers(model->L, opts->workers, false, opts->u1 != 0), opts->u1 != 0);
   return TEBD_OK;
 }
 

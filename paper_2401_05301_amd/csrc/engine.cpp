@@ -104,20 +104,33 @@ size_t Sizes::bytes(int workers, bool u1) const {
 
 int gates_per_layer(int L, bool super) { return super ? L / 2 : (L - 2 + 2) / 3; }
 
-int auto_workers(int L, int requested, bool super) {
+int auto_workers(int L, int requested, bool super, bool u1) {
   const int per_layer = std::max(1, gates_per_layer(L, super));
-  const int w = requested > 0 ? requested : 4;
+  // dense: six workers measured fastest on the bulk chi = 1024 chain (24.1 s per step
+  // against 26.0 s with four and 24.6 s with eight); the latency-bound sector solves of
+  // the U(1) route ran 27% slower with six than with four
+  const int w = requested > 0 ? requested : (u1 ? 4 : 6);
   return std::max(1, std::min(w, per_layer));
 }
 
-int subspace_width(int r, int chi_max) { return subspace_width_keep(r, std::min(chi_max, r)); }
+int subspace_width(int r, int chi_max) {
+  const int keep = std::min(chi_max, r);
+  return std::max(subspace_width_keep(r, keep, false), subspace_width_keep(r, keep, true));
+}
 
-int subspace_width_keep(int r, int keep) {
-  // oversampling: keep / den extra rows, at least 64 (den from PTEBD_OVERSAMPLE_DEN, default 4: the
-  // iteration contracts by (lambda_{p+1} / lambda_k) per step, and a quarter more rows than kept
-  // values reaches the FP64 bar in fewer, wider iterations at about the same cost)
-  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 4;
-  const int p = ((keep + std::max(64, keep / den)) + 15) / 16 * 16;
+int subspace_width_keep(int r, int keep, bool wide) {
+  // Oversampling: the narrow basis has keep / den extra rows, at least omin (den from
+  // PTEBD_OVERSAMPLE_DEN, omin from PTEBD_OVERSAMPLE_MIN); the wide one keep / 4, at least 64.
+  // The iteration contracts by lambda_{p+1} / lambda_k per step, so more rows mean fewer
+  // iterations, but every iteration and every Jacobi sweep of its Rayleigh-Ritz grows with p.
+  // On the bulk chi = 1024 workload the narrow basis is the faster one once the evolution
+  // is under way, while the first gates after a canonicalisation converge only with the
+  // wide one: the narrow basis runs first with a short iteration cap and the wide one
+  // takes over when it has not converged.
+  static const int den = std::getenv("PTEBD_OVERSAMPLE_DEN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_DEN"))) : 16;
+  static const int omin = std::getenv("PTEBD_OVERSAMPLE_MIN") ? std::max(1, std::atoi(std::getenv("PTEBD_OVERSAMPLE_MIN"))) : 64;
+  const int extra = wide ? std::max(64, keep / 4) : std::max(omin, keep / den);
+  const int p = ((keep + extra) + 15) / 16 * 16;
   // below ~1.5 p, or below kSubspaceMinRows rows, the whole Gram matrix is
   // cheaper to diagonalise directly (measured on the quench workload)
   return (3 * p < 2 * r && r >= kSubspaceMinRows) ? p : 0;
@@ -296,7 +309,7 @@ void mps_allocate(tebd_mps* M) {
   PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
   fill_zero(M->ledger, 1, M->stream);
-  const int nw = auto_workers(L, M->opts.workers, M->super);
+  const int nw = auto_workers(L, M->opts.workers, M->super, M->opts.u1 != 0);
   for (int w = 0; w < nw; ++w) {
     tebd_mps* W = new tebd_mps();
     M->workers.push_back(W);
@@ -1038,7 +1051,8 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
 // does not converge, a Rayleigh matrix that is not positive semi-definite, or
 // kept values still moving at the last iteration: a start nearly inside the
 // null space of a rank-deficient G); the caller then solves G directly.
-bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w) {
+bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p, int keep, const WarmStart& w,
+                   int max_it) {
   hipStream_t s = M->stream;
   fill_random(M->sZ.re, (int64_t)p * r, 0x5eed1234abcdull, s);
   fill_random(M->sZ.im, (int64_t)p * r, 0x0bad5eedfeedull, s);
@@ -1093,7 +1107,6 @@ bool subspace_topk(tebd_mps* M, const double* gr, const double* gi, int r, int p
   PTEBD_HIP(hipMemcpyAsync(&trace, M->info_d + 4, sizeof(double), hipMemcpyDeviceToHost, s));
   PTEBD_HIP(hipStreamSynchronize(s));
   std::vector<double> h_res(p), sorted;
-  const int max_it = 30;
   auto image = [&]() {   // Y = Z G (rows: (G z_i)^+), H = Y Z^+
     ZGemmArgs g;
     g.m = p; g.n = r; g.k = r;
@@ -1241,6 +1254,12 @@ double jacobi_tol(int c) { return std::max(2e-15, 2.0 * std::sqrt((double)c) * 1
 // (Gram-Schmidt) removes exactly those components.
 constexpr double kRefineRatio = 1e-3;
 
+// Iteration caps of the subspace iteration: the narrow basis gives up early
+// (the wide one converges where it does not), the wide one before the direct
+// solve of the whole Gram matrix.
+constexpr int kNarrowIters = 10;
+constexpr int kWideIters = 30;
+
 // Cholesky-QR of the k rows of V (length n, leading dimension ldv) in their
 // stored order: V <- L^-1 V with V V^+ = L L^+, so that row i loses its
 // components along rows 0..i-1 and every row ends with unit norm.  Uses the
@@ -1384,9 +1403,20 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   if (in.warm.kind == 2 && in.warm.src_cols == r) kw = in.warm.src_rows;
   int keep = kw > 0 ? std::min(keep_full, kw + std::max(16, kw / 8)) : keep_full;
   int k = -1;
+  bool wide = false;
   while (k < 0) {
-    const int p = (M->sub_p > 0 && !no_sub) ? subspace_width_keep(r, keep) : 0;
-    if (p > 0 && p <= M->sub_p && subspace_topk(M, M->G.re, M->G.im, r, p, keep, in.warm)) {
+    const int p = (M->sub_p > 0 && !no_sub) ? subspace_width_keep(r, keep, wide) : 0;
+    bool sub_ok = p > 0 && p <= M->sub_p &&
+                  subspace_topk(M, M->G.re, M->G.im, r, p, keep, in.warm, wide ? kWideIters : kNarrowIters);
+    if (!sub_ok && !wide && p > 0) {
+      const int pw = subspace_width_keep(r, keep, true);
+      if (pw > 0 && pw <= M->sub_p) {
+        if (debug_enabled()) std::fprintf(stderr, "[ptebd] subspace r=%d: narrow basis p=%d failed, wide p=%d\n", r, p, pw);
+        wide = true;
+        continue;
+      }
+    }
+    if (sub_ok) {
       // the ledger is charged once the width is known to be enough
       double* trial = M->info_d + 12;
       fill_zero(trial, 1, s);

@@ -150,7 +150,7 @@ struct Sizes {
 // Number of gate workers of a handle: opts.workers if positive, else 4,
 // at most the number of gates in a layer (L sites of the chain the MPS lives
 // on; two-site gates on a super-site chain).
-int auto_workers(int L, int requested, bool super = false);
+int auto_workers(int L, int requested, bool super = false, bool u1 = false);
 
 Sizes plan_sizes(int L, int d, int chi_max);
 // Sizes of a super-site chain of Ls sites of dimension D (two-site gates).
@@ -158,8 +158,9 @@ Sizes plan_sizes2(int Ls, int D, int chi_max);
 // Width of the subspace used for the top-k eigenpairs of an r x r Gram
 // matrix when keeping at most chi_max values (0: solve the whole matrix).
 int subspace_width(int r, int chi_max);
-// The same for a given number of values to keep.
-int subspace_width_keep(int r, int keep);
+// The same for a given number of values to keep, with the narrow or the wide
+// oversampling (0 where the whole matrix is solved directly).
+int subspace_width_keep(int r, int keep, bool wide);
 void mps_allocate(tebd_mps* M);
 void mps_release(tebd_mps* M);
 void upload_product(tebd_mps* M, const int* occ);

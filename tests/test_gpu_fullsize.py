@@ -1,5 +1,5 @@
 """Full-size checks in the configuration bench.py times (d = 5, chi = 1024,
-Gram route, four gate workers, w_max = 1e-12, eps = 1e-6): one layer on the
+Gram route, six gate workers, w_max = 1e-12, eps = 1e-6): one layer on the
 GPU; the oracle applies only the central gate, whose four bonds are all at
 chi = 1024, and the outputs that depend on that gate alone are compared
 (the Schmidt spectra on its two inner bonds and the observables inside its
@@ -50,7 +50,7 @@ def test_bulk_gate_chi1024_sampled(dense_case, prec):
     B, lam, om, on, oC, oD = dense_case
     note(f"full size: GPU layer at chi=1024, theta/gate precision {prec}")
     g = pt.MPS.from_tensors(pt.make_model(L, D, MODEL.U, MODEL.J, MODEL.Jnnn, MODEL.K, MODEL.centre()),
-                            pt.make_opts(CHI, 1e-12, 1e-6, prec=prec, svd=pt.SVD_GRAM_EIG, workers=4), B, lam)
+                            pt.make_opts(CHI, 1e-12, 1e-6, prec=prec, svd=pt.SVD_GRAM_EIG, workers=6), B, lam)
     g.layer(J % 3, TAU)
     n, C, D_ = g.measure()
     lam_g = [g.lam(J + 1), g.lam(J + 2)]
@@ -76,7 +76,7 @@ def test_bulk_gate_chi1024_sampled_u1():
     assert all(B[i].shape[0] == CHI for i in range(J, J + 4))
     note(f"full size U(1): bonds {[b.shape[0] for b in B]}")
     g = pt.MPS.from_tensors(pt.make_model(L, D, MODEL.U, MODEL.J, MODEL.Jnnn, MODEL.K, MODEL.centre()),
-                            pt.make_opts(CHI, 1e-12, 1e-6, svd=pt.SVD_GRAM_EIG, workers=4, u1=True), B, lam)
+                            pt.make_opts(CHI, 1e-12, 1e-6, svd=pt.SVD_GRAM_EIG, workers=6, u1=True), B, lam)
     g.layer(J % 3, TAU)
     n, C, D_ = g.measure()
     lam_g = [np.sort(g.lam(J + 1))[::-1], np.sort(g.lam(J + 2))[::-1]]
