@@ -168,8 +168,8 @@ def quench_run(pt, torch, args):
 
 def u1_sample(pt, torch, args, eps):
     """One timed Strang step of the same chain (L, d = 5, chi) with U(1)
-    sectors: a random state of L/2 bosons (sector width sigma), canonicalised,
-    tebd_opts.u1 = 1, Gram route."""
+    sectors: a random state of L/2 bosons (sector width sigma), canonicalised
+    and evolved by one untimed step, tebd_opts.u1 = 1, Gram route."""
     from workloads import CONFIGS, random_mps_u1
     cfg = CONFIGS["bulk_L64_chi1024"]
     mdl, dt = cfg["model"], cfg["dt"]
@@ -182,6 +182,7 @@ def u1_sample(pt, torch, args, eps):
     del B, lam
     g.canonicalize()
     g.prepare(dt)
+    g.step(dt)      # untimed: the first step after a canonicalisation, and the tile tuner's first look at new shapes
     g.sync()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -194,7 +195,7 @@ def u1_sample(pt, torch, args, eps):
     ms = e0.elapsed_time(e1)
     out = {"value": gate_updates_per_step(L) / (ms / 1e3), "unit": "gate-updates/s", "ms_per_step": ms,
            "input": f"random right-orthonormal MPS of {L // 2} bosons (seed {args.seed}, sector width sigma "
-                    f"{args.sigma:g}, right-index weight exp(-b/{args.bias:g})), canonicalised",
+                    f"{args.sigma:g}, right-index weight exp(-b/{args.bias:g})), canonicalised, one untimed step",
            "max_bond": max(g.bond_dims())}
     g.close()
     return out
