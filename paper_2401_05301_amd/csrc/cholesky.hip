@@ -8,7 +8,7 @@
 //
 // Blocks of 64: each diagonal block is factorised and inverted in LDS by one
 // work-group; the panel below it and the trailing update are complex GEMMs;
-// the off-diagonal blocks of X follow by block forward substitution.
+// the off-diagonal blocks of X follow by recursive doubling over the blocks.
 #include <utility>
 #include <vector>
 
@@ -36,7 +36,7 @@ constexpr int kBlockThreads = 1024;   // 64 rows x 16 column lanes
 __device__ __forceinline__ double fixed_pivot(double d) { return (d > 0.0 && d < 1e300) ? d : 1.0; }
 
 __global__ __launch_bounds__(kBlockThreads) void chol_block_kernel(double* kr, double* ki, int64_t ld, int b0, int nb,
-                                                         double* xr, double* xi, int* flag) {
+                                                                   double* xr, double* xi, int* flag) {
   __shared__ double Ar[CB][CB + 1], Ai[CB][CB + 1];
   __shared__ double Xr[CB][CB + 1], Xi[CB][CB + 1];
   const int tid = threadIdx.x;
