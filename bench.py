@@ -202,7 +202,7 @@ def u1_sample(pt, torch, args, eps):
 
 
 def precision_batching(pt, torch, args):
-    """The same chi = 1024 state stepped four ways on this build: FP64 with
+    """The same chi = 1024 state stepped four ways with one library: FP64 with
     one gate worker (the plain per-gate form), FP64 with six concurrent
     workers (the batched form), and the batched form with the theta/gate
     products in FP32 and in split FP32.  Chain L = 16, d = 5 (its central
@@ -547,7 +547,7 @@ def main():
                 "busy_ms": gemm_busy, "summed_launch_ms": gemm_ms,
                 "achieved_over_busy_TFLOPs": credited / (gemm_busy / 1e3) / 1e12,
                 "frac_over_busy": credited / (gemm_busy / 1e3) / 1e12 / PEAK_FP64,
-                "note": ("achieved = credited GEMM flops of the profiled step (SURVEY unit terms x gate "
+                "note": ("achieved = credited GEMM flops of the profiled step (algorithmic unit terms x gate "
                          "updates) / summed HIP-event launch time; gate workers run concurrently, so "
                          "launches overlap: busy_ms is the union of the launch intervals")}
         if prec == pt.FP64 and L == 64 and chi == 1024 and args.svd == "gram" and not args.u1:

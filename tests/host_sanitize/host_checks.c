@@ -4,8 +4,8 @@
  * from several threads at once, the footprint planner, and the serving
  * scheduler's admission threads (each request fails at its first device
  * allocation, so every thread runs its error path concurrently).
- * Prints one line per group and "host driver: ok" at the end; any check
- * that fails prints its line and the driver exits with status 1. */
+ * Prints one line per group and "host checks: ok" at the end; any check
+ * that fails prints its line and the program exits with status 1. */
 #include <math.h>
 #include <pthread.h>
 #include <stdio.h>
@@ -171,9 +171,9 @@ int main(void) {
   gates();
   serving();
   if (failures) {
-    printf("host driver: %d failures\n", failures);
+    printf("host checks: %d failures\n", failures);
     return 1;
   }
-  printf("host driver: ok\n");
+  printf("host checks: ok\n");
   return 0;
 }

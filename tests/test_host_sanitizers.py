@@ -3,7 +3,7 @@ and under ThreadSanitizer, on the CPU.
 
 Every source of the library is compiled with the sanitizers on its host side
 only (the device code is built as usual and never runs here), and linked with
-the C driver in tests/host_sanitize/, which exercises:
+the C program in tests/host_sanitize/host_checks.c, which exercises:
   - the argument validation and error paths of the C ABI;
   - the host gate builder (Eq. (1) split into three-site terms, diagonalised
     and exponentiated in FP64) from six threads at once;
@@ -11,8 +11,8 @@ the C driver in tests/host_sanitize/, which exercises:
     slots, each on its own thread; without a GPU every request fails at its
     first device allocation, so the admission loop, the condition variable
     and the per-request error paths all run concurrently.
-A sanitizer report makes the driver exit non-zero, and the test fails with it.
-On a machine with a GPU the same driver would also run the device paths; the
+A sanitizer report makes the program exit non-zero, and the test fails with it.
+On a machine with a GPU the same program would also run the device paths; the
 test is meant for the CPU-only suite and is skipped when a GPU is visible.
 """
 import os
@@ -37,7 +37,7 @@ def _gpu_visible():
 
 
 def _build(tmp, kind):
-    """Objects of every library source plus the driver, linked into one
+    """Objects of every library source plus the check program, linked into one
     executable; `kind` is "address+undefined" or "thread"."""
     sans = kind.split("+")
     host_flags = []
@@ -57,11 +57,11 @@ def _build(tmp, kind):
     for p in procs:
         out, _ = p.communicate(timeout=600)
         assert p.returncode == 0, out[-3000:]
-    drv = os.path.join(tmp, "host_driver.o")
+    drv = os.path.join(tmp, "host_checks.o")
     subprocess.run([HIPCC, "-x", "c"] + common + host_flags +
-                   ["-c", os.path.join(HERE, "host_sanitize", "host_driver.c"), "-o", drv],
+                   ["-c", os.path.join(HERE, "host_sanitize", "host_checks.c"), "-o", drv],
                    check=True, capture_output=True, timeout=300)
-    exe = os.path.join(tmp, "host_driver")
+    exe = os.path.join(tmp, "host_checks")
     link = [CLANG] + ["-fsanitize=" + s for s in sans] + objs + [drv, "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib",
                                                                 "-lamdhip64", "-lpthread", "-o", exe]
     r = subprocess.run(link, capture_output=True, text=True, timeout=300)
@@ -84,6 +84,6 @@ def test_host_code_under_sanitizers(tmp_path, kind):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     report = r.stdout[-4000:] + r.stderr[-4000:]
     assert r.returncode == 0, report
-    assert "host driver: ok" in r.stdout, report
+    assert "host checks: ok" in r.stdout, report
     for word in ("ERROR: AddressSanitizer", "runtime error:", "WARNING: ThreadSanitizer"):
         assert word not in r.stderr, report
