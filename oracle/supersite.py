@@ -127,7 +127,7 @@ def step2(mps: MPS, gates: SupersiteGates, dt: float, tr: Trunc) -> None:
 
 def step4_2(mps: MPS, gates: SupersiteGates, dt: float, tr: Trunc) -> None:
     """Fourth-order step of the super-site chain: five second-order steps
-    with the Suzuki weights of ``oracle.tebd.suzuki4_weights`` (reading C21)."""
+    with the Suzuki weights of ``oracle.tebd.suzuki4_weights``."""
     for w in suzuki4_weights():
         step2(mps, gates, w * dt, tr)
 

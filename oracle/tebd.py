@@ -172,7 +172,7 @@ def step(mps: MPS, gates: GateCache, dt: float, tr: Trunc) -> None:
 
 
 def suzuki4_weights() -> List[float]:
-    """Time weights of the fourth-order step (reading C21).
+    """Time weights of the fourth-order step (Suzuki's symmetric fractal composition).
 
     The appendix on numerical convergence (time step) checks the
     second-order results against fourth-order pTEBD without naming the

@@ -361,7 +361,7 @@ def test_random_state_layer_gram_subspace_chi256(pt):
 
 
 def test_fourth_order_step(pt):
-    """tebd_step4 (five Strang steps of Suzuki's weights, reading C21) against
+    """tebd_step4 (five Strang steps with Suzuki's weights) against
     the oracle's step4 on the exact-chi L=8 chain with NNN hopping and trap,
     and on a truncating chi=20 chain."""
     for m, tr, steps in [

@@ -10,7 +10,7 @@ truncating three-site gate update is, by definition:
   psi'  = (1 x G x 1) psi                                  (gate on j..j+2)
   psi1  = top-k1 Schmidt part of psi' across bond j+1, normalised
   psi2  = top-k2 Schmidt part of psi1 across bond j+2, normalised
-          (reading C9: bond j+1 first, then bond j+2)
+          (the cut across bond j+1 first, then the one across bond j+2)
 
 Everything below is written here from that definition with numpy's SVD on
 the dense vector (L = 6, d = 3, 729 amplitudes), independently of the
@@ -144,7 +144,7 @@ def test_truncating_gate_update_equals_dense_definition(seed, j, chi):
     # the updated MPS is the truncated, renormalised state amplitude by amplitude
     v = contract(mps.B, mps.lam[0])
     assert np.abs(v - p2t).max() < 1e-12, np.abs(v - p2t).max()
-    # the local measurement (orthonormality assumed, reading C12) differs from
+    # the local measurement (canonical form assumed by its formulas) differs from
     # the exact expectation values of that state by at most O(w)
     n, C, D = otebd.measure(mps)
     ne, Ce, De = dense_observables(p2t, L, d)
