@@ -70,15 +70,22 @@ typedef enum {
 } tebd_precision;
 
 typedef enum {
-  TEBD_SVD_JACOBI = 0,   /* one-sided block Jacobi on the rows of theta (no Gram matrix) */
-  TEBD_SVD_GRAM_EIG = 1  /* Hermitian Gram matrix + block Jacobi eigensolver; faster, squares the condition number */
+  TEBD_SVD_JACOBI = 0,    /* one-sided block Jacobi on the rows of theta (no Gram matrix) */
+  TEBD_SVD_GRAM_EIG = 1,  /* Hermitian Gram matrix + block Jacobi eigensolver; faster, squares the condition number;
+                             large Gram matrices use a subspace iteration started from the Schmidt basis
+                             before the gate (warm start) */
+  TEBD_SVD_RANDOMIZED = 2 /* the Gram route without the warm start: every subspace iteration starts from
+                             counter-hash random rows (a randomised range finder with power steps and
+                             Rayleigh-Ritz, Sec. V's randomised truncation), with the same stopping rule, eps
+                             floor and FP64 results; for states whose previous Schmidt basis says little
+                             about the next one */
 } tebd_svd;
 
-/* Smallest relative tolerance eps (tebd_opts.trunc_rel) the Gram route
- * accepts.  The Gram matrix squares the singular values, so values below
+/* Smallest relative tolerance eps (tebd_opts.trunc_rel) the Gram routes
+ * accept.  The Gram matrix squares the singular values, so values below
  * about sqrt(u) s_0 (u = 2^-53) sit at its rounding level and cannot be told
  * apart from zero; eps >= 1e-6 keeps every cut the rule k_eps makes well
- * above that level.  With TEBD_SVD_GRAM_EIG a smaller trunc_rel is refused
+ * above that level.  With TEBD_SVD_GRAM_EIG or TEBD_SVD_RANDOMIZED a smaller trunc_rel is refused
  * with TEBD_EINVAL (mps_init_*, mps_footprint, tebd_serve); the one-sided
  * Jacobi route takes any eps >= 0. */
 #define TEBD_GRAM_EPS_MIN 1e-6
@@ -93,7 +100,7 @@ typedef struct {
 typedef struct {
   int32_t chi_max;        /* bond cap (>= 1) */
   double trunc_weight;    /* w_max (>= 0) */
-  double trunc_rel;       /* eps (>= 0; >= TEBD_GRAM_EPS_MIN with TEBD_SVD_GRAM_EIG) */
+  double trunc_rel;       /* eps (>= 0; >= TEBD_GRAM_EPS_MIN with the Gram routes) */
   int32_t prec;           /* tebd_precision */
   int32_t svd;            /* tebd_svd */
   int32_t max_sweeps;     /* Jacobi sweep limit; <= 0 selects the default (80) */

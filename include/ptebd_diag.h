@@ -29,8 +29,10 @@ tebd_status tebd_diag_zgemm(int32_t prec, int32_t m, int32_t n, int32_t k, int32
                             const double* col_scale, int32_t herm, double* C);
 
 /* Truncated SVD of A (m x n) with the library's Jacobi engine and the
- * truncation rule of ptebd.h.  variant is a tebd_svd; the Gram route needs
- * eps >= TEBD_GRAM_EPS_MIN (else TEBD_EINVAL).  Outputs: *k kept
+ * truncation rule of ptebd.h.  variant is a tebd_svd; the Gram routes need
+ * eps >= TEBD_GRAM_EPS_MIN (else TEBD_EINVAL).  A single SVD has no warm
+ * start, so TEBD_SVD_RANDOMIZED computes what TEBD_SVD_GRAM_EIG does.
+ * Outputs: *k kept
  * values, s[0..k) the kept singular values renormalised to unit 2-norm,
  * vh (planar, k x n) the kept right singular vectors as rows, *nrm the
  * 2-norm of the kept values before renormalisation, *w the relative

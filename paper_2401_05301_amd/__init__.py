@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libptebd.so")
 
 TEBD_OK, TEBD_EINVAL, TEBD_ENOMEM, TEBD_EDEVICE, TEBD_ENOCONV, TEBD_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP32_SPLIT = 0, 1, 2
-SVD_JACOBI, SVD_GRAM_EIG = 0, 1
+SVD_JACOBI, SVD_GRAM_EIG, SVD_RANDOMIZED = 0, 1, 2
 GRAM_EPS_MIN = 1e-6   # TEBD_GRAM_EPS_MIN: smallest trunc_rel the Gram route accepts
 
 EXPORTS = [

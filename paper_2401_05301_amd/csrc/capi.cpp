@@ -68,8 +68,8 @@ tebd_status check_opts(const tebd_opts* o, int d) {
   if (!finite(o->trunc_weight) || o->trunc_weight < 0) return fail(TEBD_EINVAL, "trunc_weight must be >= 0");
   if (!finite(o->trunc_rel) || o->trunc_rel < 0) return fail(TEBD_EINVAL, "trunc_rel must be >= 0");
   if (o->prec < TEBD_FP64 || o->prec > TEBD_FP32_SPLIT) return fail(TEBD_EINVAL, "bad precision");
-  if (o->svd < TEBD_SVD_JACOBI || o->svd > TEBD_SVD_GRAM_EIG) return fail(TEBD_EINVAL, "bad svd variant");
-  if (o->svd == TEBD_SVD_GRAM_EIG && !(o->trunc_rel >= TEBD_GRAM_EPS_MIN))
+  if (o->svd < TEBD_SVD_JACOBI || o->svd > TEBD_SVD_RANDOMIZED) return fail(TEBD_EINVAL, "bad svd variant");
+  if (o->svd != TEBD_SVD_JACOBI && !(o->trunc_rel >= TEBD_GRAM_EPS_MIN))
     return fail(TEBD_EINVAL,
                 "the Gram route resolves singular values down to 1e-6 of the largest: trunc_rel must be >= "
                 "TEBD_GRAM_EPS_MIN (1e-6); use TEBD_SVD_JACOBI for a smaller eps");

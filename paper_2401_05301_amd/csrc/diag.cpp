@@ -64,10 +64,10 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
                                      double w_max, double eps, int32_t* k, double* s, double* vh, double* nrm,
                                      double* w, int32_t* sweeps) {
   if (m < 1 || n < 1 || !A || !k || !s || !vh || !nrm || !w || !sweeps || chi_max < 1) return TEBD_EINVAL;
-  if (variant != TEBD_SVD_JACOBI && variant != TEBD_SVD_GRAM_EIG) return TEBD_EINVAL;
+  if (variant < TEBD_SVD_JACOBI || variant > TEBD_SVD_RANDOMIZED) return TEBD_EINVAL;
   if (std::min(m, n) > 8192) return TEBD_EINVAL;
   if (!(eps >= 0.0) || !(w_max >= 0.0)) return TEBD_EINVAL;
-  if (variant == TEBD_SVD_GRAM_EIG && !(eps >= TEBD_GRAM_EPS_MIN)) {
+  if (variant != TEBD_SVD_JACOBI && !(eps >= TEBD_GRAM_EPS_MIN)) {
     ptebd::set_last_error("the Gram route needs eps >= TEBD_GRAM_EPS_MIN (1e-6)");
     return TEBD_EINVAL;
   }
@@ -97,7 +97,7 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     M.perm = static_cast<int*>(ptebd::dev_alloc(&M, sizeof(int) * mx));
     M.flags = static_cast<int*>(ptebd::dev_alloc(&M, sizeof(int) * mx));
     const int sp = ptebd::subspace_width((int)r, chi_max);
-    if (variant == TEBD_SVD_GRAM_EIG && sp > 0) {
+    if (variant != TEBD_SVD_JACOBI && sp > 0) {
       M.sub_p = sp;
       M.sZ = z((int64_t)sp * r);
       M.sY = z((int64_t)sp * r);

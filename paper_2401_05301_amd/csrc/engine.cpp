@@ -234,7 +234,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
   W->perm = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
   W->flags = static_cast<int*>(dev_alloc(W, sizeof(int) * s.vec));
   W->flags_cap = s.vec;
-  if (s.sub_p > 0 && W->opts.svd == TEBD_SVD_GRAM_EIG) {
+  if (s.sub_p > 0 && W->opts.svd != TEBD_SVD_JACOBI) {
     const int64_t sp = s.sub_p;
     W->sub_p = (int)sp;
     W->sub_r = (int)s.sub_r;
@@ -1313,7 +1313,7 @@ void count_rule(tebd_mps* M) {
 int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf) {
   hipStream_t s = M->stream;
   const int m = in.m, n = in.n;
-  const bool gram = M->opts.svd == TEBD_SVD_GRAM_EIG;
+  const bool gram = M->opts.svd != TEBD_SVD_JACOBI;
   double* nrm = M->info_d + 2 * slot;
   int* kdev = M->info_i + slot;
   const double eps = M->opts.trunc_rel;
@@ -1398,16 +1398,19 @@ int svd_trunc(tebd_mps* M, const SvdIn& in, double* lam_out, double* vhr, double
   // spends its iterations on rounding-level eigenvalues without a gap), and
   // widened to chi_max when more values turn out to be kept.
   const int keep_full = std::min(M->chi_max, r);
+  // the randomised route ignores the warm start: every basis starts from random rows
+  WarmStart warm = in.warm;
+  if (M->opts.svd == TEBD_SVD_RANDOMIZED) warm.kind = 0;
   int kw = 0;
-  if (in.warm.kind == 1 && in.warm.src_rows == r) kw = in.warm.src_cols;
-  if (in.warm.kind == 2 && in.warm.src_cols == r) kw = in.warm.src_rows;
+  if (warm.kind == 1 && warm.src_rows == r) kw = warm.src_cols;
+  if (warm.kind == 2 && warm.src_cols == r) kw = warm.src_rows;
   int keep = kw > 0 ? std::min(keep_full, kw + std::max(16, kw / 8)) : keep_full;
   int k = -1;
   bool wide = false;
   while (k < 0) {
     const int p = (M->sub_p > 0 && !no_sub) ? subspace_width_keep(r, keep, wide) : 0;
     bool sub_ok = p > 0 && p <= M->sub_p &&
-                  subspace_topk(M, M->G.re, M->G.im, r, p, keep, in.warm, wide ? kWideIters : kNarrowIters);
+                  subspace_topk(M, M->G.re, M->G.im, r, p, keep, warm, wide ? kWideIters : kNarrowIters);
     if (!sub_ok && !wide && p > 0) {
       const int pw = subspace_width_keep(r, keep, true);
       if (pw > 0 && pw <= M->sub_p) {
@@ -1482,7 +1485,7 @@ int svd_trunc_u1(tebd_mps* M, const SvdIn& in, const std::vector<int>& rq, const
                  double* lam_out, double* vhr, double* vhi, int slot, tebd_mps::Z xbuf, std::vector<int>& kept_q) {
   hipStream_t s = M->stream;
   const int m = in.m, n = in.n;
-  const bool gram = M->opts.svd == TEBD_SVD_GRAM_EIG;
+  const bool gram = M->opts.svd != TEBD_SVD_JACOBI;
   double* nrm = M->info_d + 2 * slot;
   int* kdev = M->info_i + slot;
   const double eps = M->opts.trunc_rel;   // >= TEBD_GRAM_EPS_MIN on the Gram route (checked at creation)
@@ -1876,7 +1879,7 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   } else {
     k1 = svd_trunc(W, in1, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi);
   }
-  const bool gram = W->opts.svd == TEBD_SVD_GRAM_EIG;
+  const bool gram = W->opts.svd != TEBD_SVD_JACOBI;
   {  // B_j = psi' V1 / |S1|
     ZGemmArgs g;
     g.m = m1; g.n = k1; g.k = n1;
@@ -1998,7 +2001,7 @@ void gate_update2(tebd_mps* S, tebd_mps* W, int K, std::pair<double*, double*> G
     g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
     g.br = S->Br[K + 1]; g.bi = S->Bi[K + 1]; g.ldb = n1; g.transB = 1;
     g.cr = S->Br[K]; g.ci = S->Bi[K]; g.ldc = k;
-    const bool gram = W->opts.svd == TEBD_SVD_GRAM_EIG;
+    const bool gram = W->opts.svd != TEBD_SVD_JACOBI;
     if (!gram) {
       g.alpha_dev = W->info_d + 0;
       g.alpha_recip = 1;

@@ -67,14 +67,14 @@ extern "C" tebd_status tebd_diag_svd_noalloc(int32_t variant, int32_t m, int32_t
                                              double w_max, double eps, int32_t* k, double* s, double* vh, double* nrm,
                                              double* w, int32_t* sweeps) {
   if (m < 1 || n < 1 || !A || !k || !s || !vh || !nrm || !w || !sweeps || chi_max < 1) return TEBD_EINVAL;
-  if (variant != TEBD_SVD_JACOBI && variant != TEBD_SVD_GRAM_EIG) return TEBD_EINVAL;
+  if (variant < TEBD_SVD_JACOBI || variant > TEBD_SVD_RANDOMIZED) return TEBD_EINVAL;
   if (m > kMaxSide || n > kMaxSide || (int64_t)m * n > kMaxElems) {
     ptebd::set_last_error("tebd_diag_svd_noalloc: m and n must be <= 512 and m * n <= 65536 (the scratch array "
                           "holds 8 MiB per device)");
     return TEBD_EINVAL;
   }
   if (!(eps >= 0.0) || !(w_max >= 0.0)) return TEBD_EINVAL;
-  if (variant == TEBD_SVD_GRAM_EIG && !(eps >= TEBD_GRAM_EPS_MIN)) {
+  if (variant != TEBD_SVD_JACOBI && !(eps >= TEBD_GRAM_EPS_MIN)) {
     ptebd::set_last_error("the Gram route needs eps >= TEBD_GRAM_EPS_MIN (1e-6)");
     return TEBD_EINVAL;
   }

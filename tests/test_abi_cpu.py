@@ -90,6 +90,21 @@ def test_gram_route_refuses_eps_below_its_floor():
     assert re.search(r"#define TEBD_GRAM_EPS_MIN 1e-6\b", txt)
 
 
+def test_randomized_route_options():
+    """TEBD_SVD_RANDOMIZED (the Gram route without the warm start) takes the
+    Gram routes' eps floor; variants beyond it are refused."""
+    import paper_2401_05301_amd as pt
+    m = pt.make_model(L=8, d=3, U=1.0)
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_footprint(m, pt.make_opts(chi_max=16, eps=1e-12, svd=pt.SVD_RANDOMIZED))
+    assert e.value.status == pt.TEBD_EINVAL
+    assert pt.mps_footprint(m, pt.make_opts(chi_max=16, eps=pt.GRAM_EPS_MIN, svd=pt.SVD_RANDOMIZED)) == \
+        pt.mps_footprint(m, pt.make_opts(chi_max=16, eps=pt.GRAM_EPS_MIN, svd=pt.SVD_GRAM_EIG))
+    with pytest.raises(pt.TebdError) as e:
+        pt.mps_footprint(m, pt.make_opts(chi_max=16, eps=pt.GRAM_EPS_MIN, svd=3))
+    assert e.value.status == pt.TEBD_EINVAL
+
+
 def test_noalloc_svd_rejects_oversize_input_without_gpu():
     """tebd_diag_svd_noalloc refuses inputs beyond its scratch array before
     any device call."""

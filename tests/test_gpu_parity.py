@@ -334,18 +334,20 @@ def ores_like(om):
     return {"mps": om, "w_total": [om.w_total]}
 
 
-def test_random_state_layer_gram_subspace_chi256(pt):
+@pytest.mark.parametrize("svd", [1, 2])
+def test_random_state_layer_gram_subspace_chi256(pt, svd):
     """Gram route where SVD #1 of the central gate has a 1280 x 1280 Gram
-    matrix and chi_max = 256: the kept eigenpairs come from the warm-started
-    subspace iteration.  One layer on a random right-orthonormal state,
-    against the oracle with the same singular-value floor."""
+    matrix and chi_max = 256: the kept eigenpairs come from the subspace
+    iteration, warm-started (svd = 1) or from random rows only (svd = 2, the
+    randomised route).  One layer on a random right-orthonormal state,
+    against the oracle with the same eps."""
     L, d, chi = 10, 5, 256
     B, lam = random_mps(L, d, chi, seed=3, tau=40.0)
     m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.0)
     tr = Trunc(chi_max=chi, w_max=1e-12, eps=GRAM_EPS)
     om = otebd.MPS([b.copy() for b in B], [l.copy() for l in lam])
-    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, tr.w_max, tr.eps, svd=1), B, lam)
-    note("gram subspace chi=256 layer group=1")
+    g = pt.MPS.from_tensors(gpu_model(pt, m), pt.make_opts(chi, tr.w_max, tr.eps, svd=svd), B, lam)
+    note(f"gram subspace chi=256 layer group=1 svd={svd}")
     otebd.apply_layer(om, otebd.GateCache(m), 1, 0.01, tr)
     g.layer(1, 0.01)
     n, C, D = g.measure()
