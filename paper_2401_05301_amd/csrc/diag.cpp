@@ -99,6 +99,7 @@ extern "C" tebd_status tebd_diag_svd(int32_t variant, int32_t m, int32_t n, cons
     const int sp = ptebd::subspace_width((int)r, chi_max);
     if (variant != TEBD_SVD_JACOBI && sp > 0) {
       M.sub_p = sp;
+      M.sub_r = (int)r;
       M.sZ = z((int64_t)sp * r);
       M.sY = z((int64_t)sp * r);
       M.sZ2 = z((int64_t)sp * r);

@@ -338,6 +338,19 @@ __global__ __launch_bounds__(256) void residual_norms_kernel(const double* yr, c
   if (lane == 0) out[row] = sqrt(s);
 }
 
+// out[e] = sum over the slices i < ns (in order) of in[i * n + e], planar.
+__global__ void sum_slices_kernel(const double* ir, const double* ii, int64_t n, int ns, double* orr, double* oi) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double sr = 0.0, si = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    sr += ir[(int64_t)i * n + e];
+    si += ii[(int64_t)i * n + e];
+  }
+  orr[e] = sr;
+  oi[e] = si;
+}
+
 // part[c * cols + j] = sum over the rows of chunk c of (rs[i / rdiv] |X_ij|)^2
 __global__ __launch_bounds__(256) void col_sq_partial_kernel(const double* xr, const double* xi, int64_t ldx, int rows,
                                                              int cols, const double* rs, int rdiv, double* part) {
@@ -711,6 +724,12 @@ void refine_sigma(double* xr, double* xi, int64_t ldx, int rows, int cols, const
 void residual_norms(const double* yr, const double* yi, const double* zr, const double* zi, int64_t ld, int p, int r,
                     const double* theta, double* out, hipStream_t s) {
   residual_norms_kernel<<<ceil_div(p, 4), 256, 0, s>>>(yr, yi, zr, zi, ld, p, r, theta, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void sum_slices(const double* ir, const double* ii, int64_t n, int ns, double* orr, double* oi, hipStream_t s) {
+  if (n <= 0) return;
+  sum_slices_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ir, ii, n, ns, orr, oi);
   PTEBD_LAUNCH_CHECK();
 }
 

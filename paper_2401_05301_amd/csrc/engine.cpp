@@ -862,6 +862,52 @@ bool lowdin_selected() {
   return v;
 }
 
+// Hermitian C = A B^+ (p x p, leading dimension p) for row blocks A and B of
+// p rows of length r (leading dimension r).  With K = r long against the few
+// tiles of C (p ~ 1100 gives 153 work-groups of 64 x 64), the product is
+// split into ns slices of K computed as one batched launch into the scratch
+// (ns p^2 values per plane) and summed slice by slice in a fixed order, so
+// that the result does not depend on timing.
+void herm_product_split(tebd_mps* M, const double* ar, const double* ai, const double* br, const double* bi, int p,
+                        int r, double* cr, double* ci, tebd_mps::Z scratch, int64_t scratch_elems, const char* tag) {
+  hipStream_t s = M->stream;
+  const int64_t tiles = (int64_t)ceil_div(p, 64) * (ceil_div(p, 64) + 1) / 2;
+  int ns = (int)std::min<int64_t>(8, std::max<int64_t>(1, (600 + tiles - 1) / tiles));
+  ns = (int)std::min<int64_t>(ns, scratch_elems / ((int64_t)p * p));
+  ns = std::min(ns, r / 256);   // slices of at least 256
+  ZGemmArgs g;
+  g.m = p; g.n = p;
+  g.ar = ar; g.ai = ai; g.lda = r;
+  g.br = br; g.bi = bi; g.ldb = r; g.transB = 1;
+  g.herm_out = 1;
+  g.tag = tag;
+  if (ns <= 1) {
+    g.k = r;
+    g.cr = cr; g.ci = ci; g.ldc = p;
+    zgemm(g, 0, s);
+    return;
+  }
+  // slices of ceil(r / ns) rounded up to a multiple of 16, the last one shorter:
+  // at most ns slices in all
+  const int slice = ((r + ns - 1) / ns + 15) / 16 * 16;
+  const int nf = r / slice, rest = r - nf * slice;
+  g.k = slice; g.batch = nf;
+  g.sA = slice; g.sB = slice; g.sC = (int64_t)p * p;
+  g.cr = scratch.re; g.ci = scratch.im; g.ldc = p;
+  zgemm(g, 0, s);
+  int total = nf;
+  if (rest > 0) {
+    ZGemmArgs t = g;
+    t.k = rest; t.batch = 1; t.sA = t.sB = t.sC = 0;
+    t.ar = ar + (int64_t)nf * slice; t.ai = ai + (int64_t)nf * slice;
+    t.br = br + (int64_t)nf * slice; t.bi = bi + (int64_t)nf * slice;
+    t.cr = scratch.re + (int64_t)nf * p * p; t.ci = scratch.im + (int64_t)nf * p * p;
+    zgemm(t, 0, s);
+    ++total;
+  }
+  sum_slices(scratch.re, scratch.im, (int64_t)p * p, total, cr, ci, s);
+}
+
 // Orthonormal rows by Cholesky-QR (Gram-Schmidt in row order): the rows of
 // Z (p x r) are normalised, K = Z Z^+ = L L^+ is factorised and Z <- L^-1 Z.
 // Row i changes only by its components along rows 0..i-1, so a basis that is
@@ -877,16 +923,9 @@ bool orthonormalize(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, b
   if (lowdin_selected()) return lowdin(M, Z, T, p, r, in_place, true, max_coupling > 0.0 ? kWarmMaxScale : 0.0);
   hipStream_t s = M->stream;
   normalize_rows(Z.re, Z.im, r, p, r, nullptr, s);
-  {
-    ZGemmArgs g;
-    g.m = p; g.n = p; g.k = r;
-    g.ar = Z.re; g.ai = Z.im; g.lda = r;
-    g.br = Z.re; g.bi = Z.im; g.ldb = r; g.transB = 1;
-    g.cr = M->sH.re; g.ci = M->sH.im; g.ldc = p;
-    g.herm_out = 1;
-    g.tag = "ortho_gram";
-    zgemm(g, 0, s);
-  }
+  // K = Z Z^+ (T is free until the final product and holds the slices)
+  herm_product_split(M, Z.re, Z.im, Z.re, Z.im, p, r, M->sH.re, M->sH.im, T, (int64_t)M->sub_p * M->sub_r,
+                     "ortho_gram");
   if (max_coupling > 0.0) {
     herm_tol(M->sH.re, p, p, herm_tol_units(), M->info_d + 7, s);
     const double ratio = offdiag_ratio(M->sH.re, M->sH.im, p, p, M->info_d + 7, 0.0, M->ratio_bits, M->h_ratio, s);
@@ -922,16 +961,11 @@ bool orthonormalize(tebd_mps* M, tebd_mps::Z& Z, tebd_mps::Z& T, int p, int r, b
   return true;
 }
 
-// H = Y Z^+ (p x p) for the basis rows Z and their images Y = Z G.
+// H = Y Z^+ (p x p) for the basis rows Z and their images Y = Z G (Hermitian:
+// Z G Z^+).  sY2 is free here and holds the slices.
 void rayleigh(tebd_mps* M, int p, int r) {
-  ZGemmArgs h;
-  h.m = p; h.n = p; h.k = r;
-  h.ar = M->sY.re; h.ai = M->sY.im; h.lda = r;
-  h.br = M->sZ.re; h.bi = M->sZ.im; h.ldb = r; h.transB = 1;
-  h.cr = M->sH.re; h.ci = M->sH.im; h.ldc = p;
-  h.herm_out = 1;   // Z G Z^+ is Hermitian
-  h.tag = "rayleigh";
-  zgemm(h, 0, M->stream);
+  herm_product_split(M, M->sY.re, M->sY.im, M->sZ.re, M->sZ.im, p, r, M->sH.re, M->sH.im, M->sY2,
+                     (int64_t)M->sub_p * M->sub_r, "rayleigh");
 }
 
 // Independent Hermitian matrices (H n x n in place, eigenvector rows into W,

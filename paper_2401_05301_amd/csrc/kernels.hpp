@@ -97,6 +97,8 @@ unsigned int count_above(const double* hr, const double* hi, int64_t ldh, int n,
                          unsigned int* count, unsigned int* h_count, hipStream_t s);
 // H_ii = 0, i < p.
 void zero_diag(double* hr, double* hi, int64_t ldh, int p, hipStream_t s);
+// out[e] = sum_{i < ns} in[i * n + e] (planar, slices summed in order).
+void sum_slices(const double* ir, const double* ii, int64_t n, int ns, double* orr, double* oi, hipStream_t s);
 // H_ii = d[i] (real), i < p.
 void set_diag(double* hr, double* hi, int64_t ldh, int p, const double* d, hipStream_t s);
 // *out = c * u * sum_i |H_ii|
