@@ -147,9 +147,9 @@ struct Sizes {
   size_t bytes(int workers, bool u1 = false) const;
 };
 
-// Number of gate workers of a handle: opts.workers if positive, else 4,
-// at most the number of gates in a layer (L sites of the chain the MPS lives
-// on; two-site gates on a super-site chain).
+// Number of gate workers of a handle: opts.workers if positive, else 6 (4 with
+// particle-number sectors), at most the number of gates in a layer (L sites
+// of the chain the MPS lives on; two-site gates on a super-site chain).
 int auto_workers(int L, int requested, bool super = false, bool u1 = false);
 
 Sizes plan_sizes(int L, int d, int chi_max);
