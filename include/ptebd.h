@@ -216,6 +216,27 @@ tebd_status mps_site(const tebd_mps* mps, int32_t site, double* buf, int64_t cap
 /* FP64 ledger: sum of relative discarded weights of all truncations so far. */
 tebd_status mps_discarded_weight(const tebd_mps* mps, double* w_total);
 
+/* Checkpoint, to resume a run later or in another process: the state in
+ * stored form (bond dimensions, Schmidt values, site tensors of the chain the
+ * MPS lives on) and the discarded-weight ledger, written into the host buffer
+ * buf[cap] as a self-describing byte image (format tag, version, sizes, a
+ * 64-bit checksum; no pointers).  *bytes receives the size of the image; with
+ * buf = NULL only the size is returned.  TEBD_EINVAL when cap < *bytes.
+ * Synchronises the handle and leaves it unchanged.  The Hamiltonian, the
+ * options and the elapsed time are the caller's to keep. */
+tebd_status mps_checkpoint(const tebd_mps* mps, void* buf, size_t cap, size_t* bytes);
+
+/* New handle holding a checkpointed state and ledger, for the given model and
+ * options: the physical L and d and opts.supersite must be those of the
+ * checkpointed handle, and every bond must fit the new bond cap; with opts.u1
+ * the particle numbers are inferred from the tensors as in mps_init_state.
+ * Evolving it with the model and options of the original handle continues the
+ * original run.  buf[len] is a host buffer read during the call.  TEBD_EINVAL
+ * when the image is cut short, carries another format tag, version or
+ * checksum, or does not fit model and opts. */
+tebd_status mps_restore(const tebd_model* model, const tebd_opts* opts, const void* buf, size_t len,
+                        tebd_mps** out);
+
 /* Number of Jacobi sweeps used by the last SVD and their running total. */
 tebd_status mps_sweep_stats(const tebd_mps* mps, int64_t* last, int64_t* total);
 

@@ -28,7 +28,7 @@ EXPORTS = [
     "tebd_step_many", "measure_local", "mps_set_model", "mps_bond_dims", "mps_lambda", "mps_site",
     "mps_discarded_weight", "mps_sweep_stats", "mps_footprint", "mps_sync", "mps_free", "tebd_last_error",
     "tebd_prepare", "mps_profile", "mps_profile_read", "mps_canonicalize", "tebd_serve", "measure_quasi_local",
-    "mps_bond_charges", "mps_trunc_stats", "mps_profile_busy",
+    "mps_bond_charges", "mps_trunc_stats", "mps_profile_busy", "mps_checkpoint", "mps_restore",
 ]
 KERNEL_CLASSES = {"gemm_fp64": 0, "gemm_fp32": 1, "herm_eig": 2, "herm_apply": 3, "jac_gram": 4, "jac_rotate": 5}
 
@@ -95,6 +95,8 @@ def _load():
         "mps_bond_charges": (st, [H, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int32)]),
         "mps_site": (st, [H, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int64]),
         "mps_discarded_weight": (st, [H, P(ctypes.c_double)]),
+        "mps_checkpoint": (st, [H, ctypes.c_void_p, ctypes.c_size_t, P(ctypes.c_size_t)]),
+        "mps_restore": (st, [P(Model), P(Opts), ctypes.c_void_p, ctypes.c_size_t, P(H)]),
         "mps_sweep_stats": (st, [H, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "mps_trunc_stats": (st, [H, P(ctypes.c_int64)]),
         "mps_footprint": (st, [P(Model), P(Opts), P(ctypes.c_size_t)]),
@@ -274,6 +276,24 @@ def mps_discarded_weight(h) -> float:
     return w.value
 
 
+def mps_checkpoint(h) -> np.ndarray:
+    """Checkpoint image of the handle's state and ledger (uint8 array)."""
+    n = ctypes.c_size_t()
+    _check(_lib.mps_checkpoint(h, None, 0, ctypes.byref(n)))
+    buf = np.empty(n.value, dtype=np.uint8)
+    _check(_lib.mps_checkpoint(h, buf.ctypes.data, buf.nbytes, ctypes.byref(n)))
+    return buf
+
+
+def mps_restore(model: Model, opts: Opts, image) -> ctypes.c_void_p:
+    """New handle from a checkpoint image (bytes-like or uint8 array)."""
+    buf = np.ascontiguousarray(np.frombuffer(image, dtype=np.uint8))
+    h = ctypes.c_void_p()
+    _check(_lib.mps_restore(ctypes.byref(model), ctypes.byref(opts), buf.ctypes.data, buf.nbytes,
+                            ctypes.byref(h)))
+    return h
+
+
 def mps_sweep_stats(h):
     a, b = ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.mps_sweep_stats(h, ctypes.byref(a), ctypes.byref(b)))
@@ -419,6 +439,22 @@ class MPS:
 
     def discarded_weight(self):
         return mps_discarded_weight(self.h)
+
+    def checkpoint(self) -> np.ndarray:
+        return mps_checkpoint(self.h)
+
+    @classmethod
+    def restore(cls, model: Model, opts: Opts, image):
+        return cls(mps_restore(model, opts, image), model, supersite=opts.supersite)
+
+    def save(self, path: str):
+        """Write the checkpoint image to a file."""
+        self.checkpoint().tofile(path)
+
+    @classmethod
+    def load(cls, path: str, model: Model, opts: Opts):
+        """Handle from a checkpoint file written by save()."""
+        return cls.restore(model, opts, np.fromfile(path, dtype=np.uint8))
 
     def sweeps(self):
         return mps_sweep_stats(self.h)

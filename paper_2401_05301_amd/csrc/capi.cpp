@@ -144,6 +144,54 @@ void strang(tebd_mps* M, double dt) {
   ptebd::layer(M, 0, h);
 }
 
+// Byte image of a checkpoint: a fixed header, then chi[L + 1] (int32, padded
+// to a multiple of 8 bytes), the Schmidt values of bonds 0..L and the site
+// tensors 0..L-1 in stored form, back to back.
+struct CkHeader {
+  char tag[8];                // "ptebdck" and a NUL
+  uint32_t version;
+  int32_t L, d;               // sites and local dimension of the chain the MPS lives on
+  int32_t phys_L, phys_d;     // physical chain
+  int32_t supersite, u1;
+  int32_t reserved;
+  double ledger;
+  uint64_t payload;           // bytes after the header
+  uint64_t checksum;          // over header (this field zero) and payload
+};
+static_assert(sizeof(CkHeader) == 64, "checkpoint header layout");
+constexpr char kCkTag[8] = {'p', 't', 'e', 'b', 'd', 'c', 'k', '\0'};
+constexpr uint32_t kCkVersion = 1;
+
+// 64-bit FNV-1a over 8-byte words (tail bytes one at a time): detects a
+// damaged or truncated image, not tampering.
+uint64_t ck_hash(const unsigned char* p, size_t n, uint64_t h = 14695981039346656037ull) {
+  constexpr uint64_t prime = 1099511628211ull;
+  size_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t w;
+    std::memcpy(&w, p + i, 8);
+    h = (h ^ w) * prime;
+  }
+  for (; i < n; ++i) h = (h ^ p[i]) * prime;
+  return h;
+}
+
+size_t ck_chi_bytes(int L) { return ((size_t)(L + 1) * sizeof(int32_t) + 7) / 8 * 8; }
+
+// Payload bytes of a state with bond dimensions chi[L + 1] and local dimension d.
+size_t ck_payload(const int32_t* chi, int L, int d) {
+  size_t n = 0;
+  for (int b = 0; b <= L; ++b) n += (size_t)chi[b];
+  for (int i = 0; i < L; ++i) n += 2 * (size_t)chi[i] * d * chi[i + 1];
+  return ck_chi_bytes(L) + n * sizeof(double);
+}
+
+uint64_t ck_checksum(const CkHeader& h, const unsigned char* payload) {
+  CkHeader z = h;
+  z.checksum = 0;
+  return ck_hash(payload, h.payload, ck_hash(reinterpret_cast<const unsigned char*>(&z), sizeof z));
+}
+
 }  // namespace
 
 extern "C" {
@@ -375,6 +423,118 @@ tebd_status mps_discarded_weight(const tebd_mps* M, double* w) {
     PTEBD_HIP(hipMemcpyAsync(w, M->ledger, sizeof(double), hipMemcpyDeviceToHost, M->stream));
     PTEBD_HIP(hipStreamSynchronize(M->stream));
   });
+}
+
+tebd_status mps_checkpoint(const tebd_mps* M, void* buf, size_t cap, size_t* bytes) {
+  if (!M || !bytes) return fail(TEBD_EINVAL, "NULL argument");
+  const int L = M->L, d = M->d;
+  const size_t payload = ck_payload(M->chi.data(), L, d);
+  *bytes = sizeof(CkHeader) + payload;
+  if (!buf) return TEBD_OK;
+  if (cap < *bytes) return fail(TEBD_EINVAL, "output capacity smaller than the checkpoint");
+  unsigned char* out = static_cast<unsigned char*>(buf);
+  unsigned char* body = out + sizeof(CkHeader);
+  CkHeader h{};
+  std::memcpy(h.tag, kCkTag, sizeof h.tag);
+  h.version = kCkVersion;
+  h.L = L;
+  h.d = d;
+  h.phys_L = M->phys_L;
+  h.phys_d = M->pd;
+  h.supersite = M->super ? 1 : 0;
+  h.u1 = M->u1 ? 1 : 0;
+  h.payload = payload;
+  std::memset(body, 0, ck_chi_bytes(L));
+  std::memcpy(body, M->chi.data(), sizeof(int32_t) * (L + 1));
+  tebd_status st = guard([&] {
+    // the caller's buffer may sit at any alignment: addressed in bytes
+    unsigned char* v = body + ck_chi_bytes(L);
+    PTEBD_HIP(hipMemcpyAsync(&h.ledger, M->ledger, sizeof(double), hipMemcpyDeviceToHost, M->stream));
+    for (int b = 0; b <= L; ++b) {
+      const size_t n = sizeof(double) * M->chi[b];
+      PTEBD_HIP(hipMemcpyAsync(v, M->lam[b], n, hipMemcpyDeviceToHost, M->stream));
+      v += n;
+    }
+    for (int i = 0; i < L; ++i) {
+      const size_t n = sizeof(double) * (size_t)M->chi[i] * d * M->chi[i + 1];
+      PTEBD_HIP(hipMemcpyAsync(v, M->Br[i], n, hipMemcpyDeviceToHost, M->stream));
+      PTEBD_HIP(hipMemcpyAsync(v + n, M->Bi[i], n, hipMemcpyDeviceToHost, M->stream));
+      v += 2 * n;
+    }
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+  });
+  if (st) return st;
+  h.checksum = ck_checksum(h, body);
+  std::memcpy(out, &h, sizeof h);
+  return TEBD_OK;
+}
+
+tebd_status mps_restore(const tebd_model* model, const tebd_opts* opts, const void* buf, size_t len,
+                        tebd_mps** out) {
+  if (!out) return fail(TEBD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!buf) return fail(TEBD_EINVAL, "buf is NULL");
+  tebd_status st = check_model(model);
+  if (st) return st;
+  st = check_opts(opts, model->d);
+  if (st) return st;
+  if (len < sizeof(CkHeader)) return fail(TEBD_EINVAL, "checkpoint cut short (no header)");
+  const unsigned char* in = static_cast<const unsigned char*>(buf);
+  CkHeader h;
+  std::memcpy(&h, in, sizeof h);
+  if (std::memcmp(h.tag, kCkTag, sizeof h.tag) != 0) return fail(TEBD_EINVAL, "not a checkpoint image");
+  if (h.version != kCkVersion) return fail(TEBD_EINVAL, "unsupported checkpoint version");
+  const bool super = opts->supersite != 0;
+  if (h.supersite != (super ? 1 : 0)) return fail(TEBD_EINVAL, "checkpoint and opts differ in supersite");
+  if (h.phys_L != model->L || h.phys_d != model->d)
+    return fail(TEBD_EINVAL, "checkpoint and model differ in L or d");
+  if (super && (model->L % 2 != 0 || model->L < 4))
+    return fail(TEBD_EINVAL, "a super-site chain needs an even number of physical sites, at least 4");
+  const int L = super ? model->L / 2 : model->L;
+  const int d = super ? model->d * model->d : model->d;
+  if (h.L != L || h.d != d) return fail(TEBD_EINVAL, "checkpoint header is inconsistent");
+  const unsigned char* body = in + sizeof(CkHeader);
+  const size_t avail = len - sizeof(CkHeader);
+  if (avail < ck_chi_bytes(L) || h.payload > avail) return fail(TEBD_EINVAL, "checkpoint cut short");
+  if (h.checksum != ck_checksum(h, body)) return fail(TEBD_EINVAL, "checkpoint checksum mismatch");
+  std::vector<int32_t> chi(L + 1);
+  std::memcpy(chi.data(), body, sizeof(int32_t) * (L + 1));
+  const ptebd::Sizes sz = super ? ptebd::plan_sizes2(L, d, opts->chi_max) : ptebd::plan_sizes(L, d, opts->chi_max);
+  if (chi[0] != 1 || chi[L] != 1) return fail(TEBD_EINVAL, "checkpoint has chi[0] or chi[L] != 1");
+  for (int b = 0; b <= L; ++b)
+    if (chi[b] < 1 || chi[b] > sz.cap[b])
+      return fail(TEBD_EINVAL, "checkpointed bond dimension outside 1..min(d^b, d^(L-b), chi_max)");
+  if (h.payload != ck_payload(chi.data(), L, d)) return fail(TEBD_EINVAL, "checkpoint size does not match its bonds");
+  if (!std::isfinite(h.ledger) || h.ledger < 0) return fail(TEBD_EINVAL, "checkpointed ledger is not a weight");
+  // the image may sit at any alignment: the values are copied out
+  size_t nv = 0;
+  for (int b = 0; b <= L; ++b) nv += (size_t)chi[b];
+  size_t nb = 0;
+  for (int i = 0; i < L; ++i) nb += 2 * (size_t)chi[i] * d * chi[i + 1];
+  std::vector<double> lam, B;
+  st = guard([&] {
+    lam.resize(nv);
+    B.resize(nb);
+  });
+  if (st) return st;
+  const unsigned char* v = body + ck_chi_bytes(L);
+  std::memcpy(lam.data(), v, sizeof(double) * nv);
+  std::memcpy(B.data(), v + sizeof(double) * nv, sizeof(double) * nb);
+  tebd_mps* M = nullptr;
+  st = create(model, opts, out, &M);
+  if (st) return st;
+  const double ledger = h.ledger;
+  st = guard([&] {
+    ptebd::upload_state(M, chi.data(), B.data(), lam.data());
+    PTEBD_HIP(hipMemcpyAsync(M->ledger, &ledger, sizeof(double), hipMemcpyHostToDevice, M->stream));
+    PTEBD_HIP(hipStreamSynchronize(M->stream));
+  });
+  if (st) {
+    mps_free(M);
+    return st;
+  }
+  *out = M;
+  return TEBD_OK;
 }
 
 tebd_status mps_sweep_stats(const tebd_mps* M, int64_t* last, int64_t* total) {

@@ -1,13 +1,15 @@
 /* Host-side checks of the C ABI under AddressSanitizer, UndefinedBehavior-
  * Sanitizer or ThreadSanitizer, on a machine without a GPU: argument
- * validation and error paths of every entry point, the host gate builder
- * from several threads at once, the footprint planner, and the serving
- * scheduler's admission threads (each request fails at its first device
- * allocation, so every thread runs its error path concurrently).
+ * validation and error paths of every entry point, the checkpoint parser on
+ * damaged images, the host gate builder from several threads at once, the
+ * footprint planner, and the serving scheduler's admission threads (each
+ * request fails at its first device allocation, so every thread runs its
+ * error path concurrently).
  * Prints one line per group and "host checks: ok" at the end; any check
  * that fails prints its line and the program exits with status 1. */
 #include <math.h>
 #include <pthread.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -80,6 +82,50 @@ static void validation(void) {
         "diag svd without buffers");
   CHECK(strlen(tebd_last_error()) > 0, "an error message is set");
   printf("validation: %s\n", failures ? "FAILED" : "ok");
+}
+
+/* The checkpoint parser on hostile input: random bytes, images with a
+ * plausible header (right tag, version and sizes, random payload size and
+ * checksum), cut at every length up to 4 KiB and read from an odd address;
+ * each is refused with TEBD_EINVAL before any device call. */
+static uint32_t lcg(uint32_t* s) {
+  *s = *s * 1664525u + 1013904223u;
+  return *s >> 8;
+}
+
+static void checkpoint_images(void) {
+  tebd_model m = model(6, 3);
+  tebd_opts o;
+  tebd_opts_default(&o);
+  o.chi_max = 8;
+  enum { N = 4096 };
+  unsigned char* raw = (unsigned char*)malloc(N + 1);
+  uint32_t seed = 12345u;
+  int bad = 0;
+  for (int rep = 0; rep < 3000; ++rep) {
+    const size_t len = lcg(&seed) % N;
+    unsigned char* img = raw + 1;   /* misaligned on purpose */
+    for (size_t i = 0; i < len; ++i) img[i] = (unsigned char)lcg(&seed);
+    if (rep % 2 == 0 && len >= 64) {
+      const uint32_t version = 1;
+      const int32_t sizes[7] = {6, 3, 6, 3, 0, 0, 0};
+      const uint64_t payload = (rep % 4 == 0) ? (uint64_t)(len - 64) : (uint64_t)lcg(&seed);
+      memcpy(img, "ptebdck", 8);
+      memcpy(img + 8, &version, 4);
+      memcpy(img + 12, sizes, sizeof sizes);
+      memcpy(img + 48, &payload, 8);
+    }
+    tebd_mps* h = NULL;
+    const tebd_status st = mps_restore(&m, &o, img, len, &h);
+    bad |= st != TEBD_EINVAL || h != NULL;
+  }
+  size_t bytes = 0;
+  tebd_mps* h = NULL;
+  CHECK(!bad, "damaged checkpoint images refused");
+  CHECK(mps_checkpoint(NULL, NULL, 0, &bytes) == TEBD_EINVAL, "checkpoint of a NULL handle");
+  CHECK(mps_restore(&m, &o, NULL, 64, &h) == TEBD_EINVAL && h == NULL, "restore from NULL");
+  printf("checkpoint images: %s\n", bad ? "FAILED" : "ok");
+  free(raw);
 }
 
 /* The host gate builder (sector-wise Jacobi eigensolver) from several threads. */
@@ -168,6 +214,7 @@ static void serving(void) {
 
 int main(void) {
   validation();
+  checkpoint_images();
   gates();
   serving();
   if (failures) {

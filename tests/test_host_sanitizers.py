@@ -5,6 +5,8 @@ Every source of the library is compiled with the sanitizers on its host side
 only (the device code is built as usual and never runs here), and linked with
 the C program in tests/host_sanitize/host_checks.c, which exercises:
   - the argument validation and error paths of the C ABI;
+  - the checkpoint parser on random, cut, misaligned and plausible-looking
+    images, all of which must be refused;
   - the host gate builder (Eq. (1) split into three-site terms, diagonalised
     and exponentiated in FP64) from six threads at once;
   - the serving scheduler: twelve requests admitted by footprint with three
