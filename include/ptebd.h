@@ -109,8 +109,9 @@ typedef struct {
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
   int32_t workers;        /* gate workspaces run concurrently within a layer (own stream and host
-                             thread each); 0 = min(6, gates per layer), or min(4, gates per layer)
-                             with u1.  Device memory grows by one gate workspace per worker. */
+                             thread each); 0 = min(6, gates per layer), min(4, gates per layer)
+                             with u1, all gates of a layer with fuse.  Device memory grows by one
+                             gate workspace per worker. */
   int32_t supersite;      /* 1: the paper's super-site chain (Sec. II B): every two physical sites
                              form one site of dimension d^2 and two-site gates act on neighbouring
                              super sites, Strang A(dt/2) B(dt) A(dt/2) over gates K even / K odd.
@@ -127,6 +128,15 @@ typedef struct {
                              numbers).  Product states qualify; mps_init_state infers the numbers
                              from the non-zero entries and fails with TEBD_EINVAL when an index is
                              reached by entries of two numbers or by none.  0: dense (default). */
+  int32_t fuse;           /* 1: fused layers (Sec. I: the gates of a layer are independent, and pTEBD
+                             applies them together): the gates of every layer advance in lockstep
+                             on the handle's stream, one per gate workspace, and their SVDs run as
+                             one batched one-sided Jacobi, with one host read-back per sweep and one
+                             for all truncation ranks instead of one per gate.  Results are the same
+                             bit for bit; it pays where launches and host round trips dominate
+                             (small chi).  Needs svd = TEBD_SVD_JACOBI, u1 = 0 and supersite = 0
+                             (else TEBD_EINVAL); workers = 0 then selects one workspace per gate of
+                             a layer.  0: gates spread over concurrent workers (default). */
 } tebd_opts;
 
 typedef struct tebd_mps tebd_mps;

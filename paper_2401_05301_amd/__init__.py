@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("svd", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p), ("workers", ctypes.c_int32), ("supersite", ctypes.c_int32),
-                ("u1", ctypes.c_int32)]
+                ("u1", ctypes.c_int32), ("fuse", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -139,7 +139,7 @@ def make_model(L: int, d: int, U: float, J: float = 1.0, Jnnn: float = 0.0, K: f
 
 def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int = FP64, svd: int = SVD_JACOBI,
               max_sweeps: int = 80, stream: Optional[int] = None, workers: int = 0, supersite: bool = False,
-              u1: bool = False) -> Opts:
+              u1: bool = False, fuse: bool = False) -> Opts:
     o = Opts()
     _lib.tebd_opts_default(ctypes.byref(o))
     o.chi_max, o.trunc_weight, o.trunc_rel = chi_max, w_max, eps
@@ -148,6 +148,7 @@ def make_opts(chi_max: int, w_max: float = 1e-12, eps: float = 1e-12, prec: int 
     o.workers = workers
     o.supersite = int(bool(supersite))
     o.u1 = int(bool(u1))
+    o.fuse = int(bool(fuse))
     return o
 
 

@@ -74,6 +74,10 @@ tebd_status check_opts(const tebd_opts* o, int d) {
                 "the Gram route resolves singular values down to 1e-6 of the largest: trunc_rel must be >= "
                 "TEBD_GRAM_EPS_MIN (1e-6); use TEBD_SVD_JACOBI for a smaller eps");
   if (o->workers < 0) return fail(TEBD_EINVAL, "workers must be >= 0");
+  if (o->fuse != 0 && o->fuse != 1) return fail(TEBD_EINVAL, "fuse must be 0 or 1");
+  if (o->fuse && (o->svd != TEBD_SVD_JACOBI || o->u1 || o->supersite))
+    return fail(TEBD_EINVAL, "fuse needs the Jacobi route on a dense three-site chain (svd = TEBD_SVD_JACOBI, "
+                             "u1 = 0, supersite = 0)");
   if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr))
     return fail(TEBD_EINVAL, "dev_alloc and dev_free must be given together");
   return TEBD_OK;
@@ -560,11 +564,12 @@ tebd_status mps_footprint(const tebd_model* model, const tebd_opts* opts, size_t
       return fail(TEBD_EINVAL, "a super-site chain needs an even number of physical sites, at least 4");
     const int Ls = model->L / 2;
     *bytes = ptebd::plan_sizes2(Ls, model->d * model->d, opts->chi_max)
-                 .bytes(ptebd::auto_workers(Ls, opts->workers, true, opts->u1 != 0), opts->u1 != 0);
+                 .bytes(ptebd::auto_workers(Ls, opts->workers, true, opts->u1 != 0), opts->u1 != 0);   // fuse is 0 here
     return TEBD_OK;
   }
+  const bool fuse = opts->fuse != 0;
   *bytes = ptebd::plan_sizes(model->L, model->d, opts->chi_max)
-               .bytes(ptebd::auto_workers(model->L, opts->workers, false, opts->u1 != 0), opts->u1 != 0);
+               .bytes(ptebd::auto_workers(model->L, opts->workers, false, opts->u1 != 0, fuse), opts->u1 != 0, fuse);
   return TEBD_OK;
 }
 

@@ -86,7 +86,11 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 
 }  // namespace
 
-size_t Sizes::bytes(int workers, bool u1) const {
+int64_t fused_table_bytes(int L) {
+  return (int64_t)(sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) * (L + 1) + 128;
+}
+
+size_t Sizes::bytes(int workers, bool u1, bool fuse) const {
   int64_t d = 0;
   d += 2 * site_elems + lam_elems + 2 * (2 * meas_sq + 2 * meas_rect) + gates + 64;
   int64_t w = 2 * (T1 + 2 * psi + X2 + G + W + V1h);
@@ -97,6 +101,8 @@ size_t Sizes::bytes(int workers, bool u1) const {
     // batched Jacobi tables
     w += ((int64_t)(std::max(sizeof(HermArgs), sizeof(JacobiArgs)) + 2 * sizeof(int64_t) + 2 * sizeof(int) +
                     sizeof(double)) * (vec / 2 + 1) + 128 + 7) / 8;
+  } else if (fuse) {
+    w += (fused_table_bytes((int)cap.size() - 1) + 7) / 8;
   }
   d += (int64_t)std::max(workers, 1) * w;
   return (size_t)d * sizeof(double);
@@ -104,12 +110,13 @@ size_t Sizes::bytes(int workers, bool u1) const {
 
 int gates_per_layer(int L, bool super) { return super ? L / 2 : (L - 2 + 2) / 3; }
 
-int auto_workers(int L, int requested, bool super, bool u1) {
+int auto_workers(int L, int requested, bool super, bool u1, bool fuse) {
   const int per_layer = std::max(1, gates_per_layer(L, super));
   // dense: six workers measured fastest on the bulk chi = 1024 chain (24.1 s per step
   // against 26.0 s with four and 24.6 s with eight); the latency-bound sector solves of
-  // the U(1) route ran 27% slower with six than with four
-  const int w = requested > 0 ? requested : (u1 ? 4 : 6);
+  // the U(1) route ran 27% slower with six than with four; a fused layer batches one
+  // gate per workspace, so it takes one for every gate of a layer
+  const int w = requested > 0 ? requested : fuse ? per_layer : (u1 ? 4 : 6);
   return std::max(1, std::min(w, per_layer));
 }
 
@@ -266,6 +273,11 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
         (int64_t)(std::max(sizeof(HermArgs), sizeof(JacobiArgs)) + 2 * sizeof(int64_t) + 2 * sizeof(int) +
                   sizeof(double)) * cnt + 128;
     W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
+  } else if (W->opts.fuse) {
+    // batched Jacobi tables of a fused layer (one matrix per worker, at most
+    // one worker per gate of a layer)
+    W->u_batch_cap = fused_table_bytes(W->L);
+    W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
   }
   W->info_i = static_cast<int*>(dev_alloc(W, sizeof(int) * 8));
   W->info_d = dalloc(W, 16);
@@ -309,7 +321,7 @@ void mps_allocate(tebd_mps* M) {
   PTEBD_HIP(hipMemcpyAsync(M->d_bi, M->Bi.data(), sizeof(double*) * L, hipMemcpyHostToDevice, M->stream));
   PTEBD_HIP(hipMemcpyAsync(M->d_lam, M->lam.data(), sizeof(double*) * (L + 1), hipMemcpyHostToDevice, M->stream));
   fill_zero(M->ledger, 1, M->stream);
-  const int nw = auto_workers(L, M->opts.workers, M->super, M->opts.u1 != 0);
+  const int nw = auto_workers(L, M->opts.workers, M->super, M->opts.u1 != 0, M->opts.fuse != 0);
   for (int w = 0; w < nw; ++w) {
     tebd_mps* W = new tebd_mps();
     M->workers.push_back(W);
@@ -556,7 +568,7 @@ void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab) {
   // active[count], counts[count], tiny2[count]
   const size_t need = sizeof(JacobiArgs) * count + 2 * sizeof(int64_t) * (count + 1) + 2 * sizeof(int) * count +
                       sizeof(double) * count + 64;
-  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "U(1) SVD: batched Jacobi tables exceed their buffer");
+  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "batched Jacobi tables exceed their buffer");
   char* base = static_cast<char*>(M->u_batch);
   JacobiArgs* d_tab = reinterpret_cast<JacobiArgs*>(base);
   int64_t* d_gram = reinterpret_cast<int64_t*>(d_tab + count);
@@ -621,7 +633,7 @@ void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab) {
     }
   }
   M->failed = true;
-  throw Error(-4, "batched Jacobi SVD did not converge within max_sweeps (" + std::to_string(count) + " sectors)");
+  throw Error(-4, "batched Jacobi SVD did not converge within max_sweeps (" + std::to_string(count) + " matrices)");
 }
 
 // run_jacobi on every matrix of tab, in groups whose pair Grams fit the
@@ -991,7 +1003,7 @@ void run_herm_jacobi_batched(tebd_mps* M, const std::vector<BatchItem>& items) {
   // active[count], counts[count], tol[count]
   const size_t need = sizeof(HermArgs) * count + 2 * sizeof(int64_t) * (count + 1) + 2 * sizeof(int) * count +
                       sizeof(double) * count + 64;
-  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "U(1) SVD: batched Jacobi tables exceed their buffer");
+  if ((int64_t)need > M->u_batch_cap) throw Error(-1, "batched Jacobi tables exceed their buffer");
   char* base = static_cast<char*>(M->u_batch);
   HermArgs* d_tab = reinterpret_cast<HermArgs*>(base);
   int64_t* d_eig = reinterpret_cast<int64_t*>(d_tab + count);
@@ -1854,10 +1866,9 @@ void tuned_gemm(ZGemmArgs g, int prec, hipStream_t s) {
                  (long)g.m, (long)g.n, (long)g.k, (long)g.batch, ms[0] / 3, ms[1] / 3, pick);
 }
 
-// One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
-// stream and settings of worker W.
-void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {
-  hipStream_t s = W->stream;
+// theta = B_j B_{j+1} B_{j+2} into W->psi and psi' = G psi, batched over
+// the left bond index, into W->psip (Sec. II B).
+void theta_gate(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G, hipStream_t s) {
   const int d = W->d, d3 = d * d * d;
   const int cl = S->chi[j], c1 = S->chi[j + 1], c2 = S->chi[j + 2], cr = S->chi[j + 3];
   const int prec = W->opts.prec;
@@ -1888,6 +1899,42 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     g.tag = "gate";
     tuned_gemm(g, prec, s);
   }
+}
+
+// B_j = psi' V1 / |S1| (m1 x k1); the Jacobi route divides by the norm of
+// the kept values on the device (info_d[0]).
+void update_left_jacobi(tebd_mps* S, tebd_mps* W, int j, int m1, int n1, int k1, hipStream_t s) {
+  ZGemmArgs g;
+  g.m = m1; g.n = k1; g.k = n1;
+  g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
+  g.br = W->V1h.re; g.bi = W->V1h.im; g.ldb = n1; g.transB = 1;
+  g.cr = S->Br[j]; g.ci = S->Bi[j]; g.ldc = k1;
+  g.alpha_dev = W->info_d + 0;
+  g.alpha_recip = 1;
+  g.tag = "update_left";
+  zgemm(g, 0, s);
+}
+
+// B_{j+1} = V1^+ V2 / |S2| (m2 x k2), V2^+ already in B_{j+2}.
+void update_middle_jacobi(tebd_mps* S, tebd_mps* W, int j, int m2, int n2, int k2, hipStream_t s) {
+  ZGemmArgs g;
+  g.m = m2; g.n = k2; g.k = n2;
+  g.ar = W->V1h.re; g.ai = W->V1h.im; g.lda = n2;
+  g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = n2; g.transB = 1;
+  g.cr = S->Br[j + 1]; g.ci = S->Bi[j + 1]; g.ldc = k2;
+  g.alpha_dev = W->info_d + 2;
+  g.alpha_recip = 1;
+  g.tag = "update_middle";
+  zgemm(g, 0, s);
+}
+
+// One gate on sites (j, j+1, j+2) of the state held by S, with the buffers,
+// stream and settings of worker W.
+void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G) {
+  hipStream_t s = W->stream;
+  const int d = W->d;
+  const int cl = S->chi[j], c1 = S->chi[j + 1], c2 = S->chi[j + 2], cr = S->chi[j + 3];
+  theta_gate(S, W, j, G, s);
   const int m1 = cl * d, n1 = d * d * cr;
   SvdIn in1{W->psip.re, W->psip.im, n1, m1, n1, S->lam[j], d};
   // before the gate the left singular space of theta across bond j+1 is
@@ -1914,23 +1961,21 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     k1 = svd_trunc(W, in1, S->lam[j + 1], W->V1h.re, W->V1h.im, 0, W->psi);
   }
   const bool gram = W->opts.svd != TEBD_SVD_JACOBI;
-  {  // B_j = psi' V1 / |S1|
+  if (!gram) {
+    update_left_jacobi(S, W, j, m1, n1, k1, s);
+  } else {  // B_j = psi' V1 / |S1|
     ZGemmArgs g;
     g.m = m1; g.n = k1; g.k = n1;
     g.ar = W->psip.re; g.ai = W->psip.im; g.lda = n1;
     g.br = W->V1h.re; g.bi = W->V1h.im; g.ldb = n1; g.transB = 1;
     g.cr = S->Br[j]; g.ci = S->Bi[j]; g.ldc = k1;
-    if (!gram) {
-      g.alpha_dev = W->info_d + 0;
-      g.alpha_recip = 1;
-    }
     g.tag = "update_left";
     zgemm(g, 0, s);
     // Gram route: Lambda_j psi' V1 = U1 S1 gives each Schmidt value as a column
     // norm to the rounding of the product, where the Gram eigenvalue s^2 only
     // resolves s to u / s (the division by |S1| follows)
-    if (gram) refine_sigma(S->Br[j], S->Bi[j], k1, m1, k1, S->lam[j], d, W->part, W->part_cap, S->lam[j + 1],
-                           W->info_d + 0, s);
+    refine_sigma(S->Br[j], S->Bi[j], k1, m1, k1, S->lam[j], d, W->part, W->part_cap, S->lam[j + 1], W->info_d + 0,
+                 s);
   }
   const int m2 = k1 * d, n2 = d * cr;
   SvdIn in2{W->V1h.re, W->V1h.im, n2, m2, n2, S->lam[j + 1], d};
@@ -1953,21 +1998,19 @@ void gate_update(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
   } else {
     k2 = svd_trunc(W, in2, S->lam[j + 2], S->Br[j + 2], S->Bi[j + 2], 1, W->X2);
   }
-  {  // B_{j+1} = V1^+ V2 / |S2|
+  if (!gram) {
+    update_middle_jacobi(S, W, j, m2, n2, k2, s);
+  } else {  // B_{j+1} = V1^+ V2 / |S2|
     ZGemmArgs g;
     g.m = m2; g.n = k2; g.k = n2;
     g.ar = W->V1h.re; g.ai = W->V1h.im; g.lda = n2;
     g.br = S->Br[j + 2]; g.bi = S->Bi[j + 2]; g.ldb = n2; g.transB = 1;
     g.cr = S->Br[j + 1]; g.ci = S->Bi[j + 1]; g.ldc = k2;
-    if (!gram) {
-      g.alpha_dev = W->info_d + 2;
-      g.alpha_recip = 1;
-    }
     g.tag = "update_middle";
     zgemm(g, 0, s);
     // S1 V1^+ V2 = U2 S2 (as above)
-    if (gram) refine_sigma(S->Br[j + 1], S->Bi[j + 1], k2, m2, k2, S->lam[j + 1], d, W->part, W->part_cap,
-                           S->lam[j + 2], W->info_d + 2, s);
+    refine_sigma(S->Br[j + 1], S->Bi[j + 1], k2, m2, k2, S->lam[j + 1], d, W->part, W->part_cap, S->lam[j + 2],
+                 W->info_d + 2, s);
   }
   S->chi[j + 1] = k1;
   S->chi[j + 2] = k2;
@@ -2057,6 +2100,140 @@ void update_gate(tebd_mps* S, tebd_mps* W, int j, std::pair<double*, double*> G)
     gate_update(S, W, j, G);
 }
 
+// One gate's Jacobi-route SVD of diag(rs) A, split into the steps a fused
+// layer interleaves with the other gates' SVDs.  The calls, arguments and
+// order are those of svd_trunc's Jacobi branch.
+struct JacSvd {
+  tebd_mps* W = nullptr;   // workspace of the gate
+  SvdIn in{};
+  double* lam_out = nullptr;
+  double* vhr = nullptr;
+  double* vhi = nullptr;
+  int slot = 0;
+  tebd_mps::Z xbuf;
+  int k = 0;
+};
+
+// Jacobi on the rows of A_s (m <= n), else on the rows of A_s^+ with the
+// right singular vectors accumulated in W->W.
+bool jac_rows(const SvdIn& in) { return in.m <= in.n; }
+
+void jac_stage(const JacSvd& x, hipStream_t s) {
+  const SvdIn& in = x.in;
+  if (jac_rows(in))
+    scale_rows_copy(in.ar, in.ai, in.lda, in.rs, in.rdiv, in.m, in.n, x.xbuf.re, x.xbuf.im, in.n, s);
+  else
+    conj_transpose_scaled(in.ar, in.ai, in.lda, in.rs, in.rdiv, in.m, in.n, x.xbuf.re, x.xbuf.im, in.m, s);
+}
+
+JacobiArgs jac_entry(const JacSvd& x) {
+  const SvdIn& in = x.in;
+  tebd_mps* W = x.W;
+  JacobiArgs a =
+      jac_rows(in)
+          ? jacobi_args(x.xbuf.re, x.xbuf.im, in.n, nullptr, nullptr, 0, in.m, in.n, jacobi_tol(in.n), 0.0)
+          : jacobi_args(x.xbuf.re, x.xbuf.im, in.m, W->W.re, W->W.im, in.n, in.n, in.m, jacobi_tol(in.m), 0.0);
+  if (jacobi_part(a) > W->part_cap) throw Error(-1, "Jacobi scratch too small");
+  a.part = W->part;
+  return a;
+}
+
+void jac_select(const JacSvd& x, hipStream_t s) {
+  tebd_mps* W = x.W;
+  const bool rows = jac_rows(x.in);
+  const int r = rows ? x.in.m : x.in.n, c = rows ? x.in.n : x.in.m;
+  int* kdev = W->info_i + x.slot;
+  row_norms(x.xbuf.re, x.xbuf.im, c, r, c, W->norms, s);
+  select_truncate(W->norms, r, 0, W->chi_max, W->opts.trunc_weight, W->opts.trunc_rel, x.lam_out, W->perm,
+                  W->inv_sig, kdev, W->info_d + 2 * x.slot, W->ledger, nullptr, s);
+  PTEBD_HIP(hipMemcpyAsync(W->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+void jac_gather(JacSvd& x, hipStream_t s) {
+  tebd_mps* W = x.W;
+  const int n = x.in.n;
+  int* kdev = W->info_i + x.slot;
+  x.k = W->h_info[0];
+  count_rule(W);
+  if (jac_rows(x.in))
+    gather_rows(x.xbuf.re, x.xbuf.im, n, W->perm, W->inv_sig, x.k, n, x.vhr, x.vhi, n, kdev, s);
+  else
+    gather_rows(W->W.re, W->W.im, n, W->perm, nullptr, x.k, n, x.vhr, x.vhi, n, kdev, s);
+}
+
+// The SVDs of v (one per workspace) as one batched one-sided Jacobi on the
+// stream of R, then one read-back of all truncation ranks.
+void jac_batch(tebd_mps* R, std::vector<JacSvd>& v, hipStream_t s) {
+  if (R->stream != s) throw Error(-3, "fused layer: the Jacobi runner must use the layer's stream");
+  for (const JacSvd& x : v) jac_stage(x, s);
+  std::vector<JacobiArgs> tab;
+  tab.reserve(v.size());
+  for (const JacSvd& x : v) tab.push_back(jac_entry(x));
+  run_jacobi_group(R, tab);
+  for (const JacSvd& x : v) jac_select(x, s);
+  PTEBD_HIP(hipStreamSynchronize(s));
+  for (JacSvd& x : v) jac_gather(x, s);
+}
+
+// All gates of one commuting layer on the Jacobi route, in lockstep on the
+// handle's stream, one gate per worker workspace at a time: the theta and
+// gate products of the gates are issued back to back, their SVDs across
+// bond j+1 run as one batched Jacobi (every round launches the pair Grams
+// and rotations of all gates still rotating, and each sweep ends in one
+// read-back for all of them instead of one per gate), and the same again
+// across bond j+2.  Every gate goes through the kernels, launch shapes,
+// tolerances and sweeps it takes in gate_update, so the result is the same
+// bit for bit; what changes is the number of launches and host round trips
+// per layer, which bound the small-chi regime.
+void fused_layer(tebd_mps* M, const std::vector<int>& js, const std::vector<std::pair<double*, double*>>& G) {
+  hipStream_t s = M->stream;
+  tebd_mps* R = M->workers[0];
+  const size_t nw = std::min(M->workers.size(), js.size());
+  const int d = M->d;
+  for (size_t x0 = 0; x0 < js.size(); x0 += nw) {
+    const size_t cnt = std::min(nw, js.size() - x0);
+    std::vector<JacSvd> v(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+      tebd_mps* W = M->workers[i];
+      const int j = js[x0 + i];
+      const int cl = M->chi[j], cr = M->chi[j + 3];
+      W->ledger = M->wslots + j;
+      theta_gate(M, W, j, G[x0 + i], s);
+      JacSvd& x = v[i];
+      x.W = W;
+      x.in = SvdIn{W->psip.re, W->psip.im, (int64_t)d * d * cr, cl * d, d * d * cr, M->lam[j], d};
+      x.lam_out = M->lam[j + 1];
+      x.vhr = W->V1h.re;
+      x.vhi = W->V1h.im;
+      x.slot = 0;
+      x.xbuf = W->psi;
+    }
+    jac_batch(R, v, s);
+    std::vector<int> k1(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+      JacSvd& x = v[i];
+      tebd_mps* W = x.W;
+      const int j = js[x0 + i];
+      const int cr = M->chi[j + 3];
+      k1[i] = x.k;
+      update_left_jacobi(M, W, j, x.in.m, x.in.n, k1[i], s);
+      x.in = SvdIn{W->V1h.re, W->V1h.im, (int64_t)d * cr, k1[i] * d, d * cr, M->lam[j + 1], d};
+      x.lam_out = M->lam[j + 2];
+      x.vhr = M->Br[j + 2];
+      x.vhi = M->Bi[j + 2];
+      x.slot = 1;
+      x.xbuf = W->X2;
+    }
+    jac_batch(R, v, s);
+    for (size_t i = 0; i < cnt; ++i) {
+      const int j = js[x0 + i];
+      update_middle_jacobi(M, v[i].W, j, v[i].in.m, v[i].in.n, v[i].k, s);
+      M->chi[j + 1] = k1[i];
+      M->chi[j + 2] = v[i].k;
+    }
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -2071,7 +2248,14 @@ void run_gates(tebd_mps* M, const std::vector<int>& js, const std::vector<std::p
   const int nw = parallel ? std::min<int>((int)M->workers.size(), (int)js.size()) : 1;
   // A gate that fails leaves the layer half applied: the handle is marked
   // failed whatever the error, so that later calls refuse the state.
-  if (nw <= 1) {
+  if (parallel && M->opts.fuse) {
+    try {
+      fused_layer(M, js, G);
+    } catch (...) {
+      M->failed = true;
+      throw;
+    }
+  } else if (nw <= 1) {
     tebd_mps* W = M->workers[0];
     try {
       for (size_t x = 0; x < js.size(); ++x) {

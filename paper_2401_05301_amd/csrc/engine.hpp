@@ -144,13 +144,16 @@ struct Sizes {
   int64_t sub_p = 0, sub_r = 0;   // subspace iteration width and row length
   int64_t gates = 0;
   int64_t uv = 0, idx = 0;         // U(1) SVD: projected rows (k x n) and sector lists (m + n)
-  size_t bytes(int workers, bool u1 = false) const;
+  size_t bytes(int workers, bool u1 = false, bool fuse = false) const;
 };
 
 // Number of gate workers of a handle: opts.workers if positive, else 6 (4 with
-// particle-number sectors), at most the number of gates in a layer (L sites
-// of the chain the MPS lives on; two-site gates on a super-site chain).
-int auto_workers(int L, int requested, bool super = false, bool u1 = false);
+// particle-number sectors, one per gate of a layer with fused layers), at
+// most the number of gates in a layer (L sites of the chain the MPS lives
+// on; two-site gates on a super-site chain).
+int auto_workers(int L, int requested, bool super = false, bool u1 = false, bool fuse = false);
+// Device bytes of the batched Jacobi tables of a fused layer on L sites.
+int64_t fused_table_bytes(int L);
 
 Sizes plan_sizes(int L, int d, int chi_max);
 // Sizes of a super-site chain of Ls sites of dimension D (two-site gates).

@@ -1,7 +1,7 @@
 """Error contract of the C-ABI on the GPU: an SVD that does not converge
 within max_sweeps returns ENOCONV and leaves the handle refusing further
 evolution and measurement (ESTATE), on every SVD route, with one gate worker
-and with several.  The sweep limit is set from the host, so every kernel
+and with several, and with fused layers.  The sweep limit is set from the host, so every kernel
 still runs its normal, bounded course."""
 import pytest
 
@@ -18,21 +18,23 @@ def pt():
 
 
 CASES = [
-    # (svd route, U(1) sectors, gate workers)
-    (0, False, 1), (0, False, 3), (1, False, 1), (1, False, 3), (0, True, 1), (1, True, 3),
+    # (svd route, U(1) sectors, gate workers, fused layers)
+    (0, False, 1, False), (0, False, 3, False), (1, False, 1, False), (1, False, 3, False), (0, True, 1, False),
+    (1, True, 3, False), (0, False, 0, True),
 ]
 
 
-@pytest.mark.parametrize("svd,u1,workers", CASES)
-def test_unconverged_svd_marks_handle(pt, svd, u1, workers):
-    note(f"ENOCONV svd={svd} u1={u1} workers={workers}")
+@pytest.mark.parametrize("svd,u1,workers,fuse", CASES)
+def test_unconverged_svd_marks_handle(pt, svd, u1, workers, fuse):
+    note(f"ENOCONV svd={svd} u1={u1} workers={workers} fuse={fuse}")
     L, d, chi = 12, 3, 24
     if u1:
         B, lam, _ = random_mps_u1(L, d, chi, L // 2, seed=4, tau=8.0)
     else:
         B, lam = random_mps(L, d, chi, seed=4)
     m = Model(L=L, d=d, U=2.0, J=1.0, Jnnn=0.1, K=0.01)
-    opts = pt.make_opts(chi, 1e-12, 1e-12 if svd == 0 else 1e-6, svd=svd, max_sweeps=1, workers=workers, u1=u1)
+    opts = pt.make_opts(chi, 1e-12, 1e-12 if svd == 0 else 1e-6, svd=svd, max_sweeps=1, workers=workers, u1=u1,
+                        fuse=fuse)
     g = pt.MPS.from_tensors(pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), opts, B, lam)
     with pytest.raises(pt.TebdError) as e:
         g.layer(0, 0.05)
