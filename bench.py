@@ -287,11 +287,14 @@ def measured_traffic():
     return t["traffic_bytes_per_launch"]
 
 
-def serving_sample(pt, n: int, scale: float, eps: float):
+def serving_sample(pt, n: int, scale: float, eps: float, svd: int = None, batched: bool = False):
     """Quench requests of the serving workload (Poisson arrivals, L in
     {16..64}, U in [2, 10], K in [0, 0.01], J_NNN = 0.1, dt = 0.01), with the
     small bond caps {16, 32, 64} and each horizon scaled by `scale`, served
-    concurrently by the library; p50/p99 time from arrival to horizon."""
+    concurrently by the library; p50/p99 time from arrival to horizon.
+    `batched` serves them by continuous batching (Jacobi route only)."""
+    if svd is None:
+        svd = pt.SVD_GRAM_EIG
     import numpy as np
     from workloads import serving_requests
     rate = 2.0
@@ -302,7 +305,10 @@ def serving_sample(pt, n: int, scale: float, eps: float):
         reqs.append(dict(model=pt.make_model(m.L, m.d, m.U, m.J, m.Jnnn, m.K, m.centre()), chi_max=r["chi_max"],
                          dt=r["dt"], steps=steps, arrival=r["arrival"]))
     t0 = time.perf_counter()
-    res = pt.tebd_serve(reqs, max_active=8, svd=pt.SVD_GRAM_EIG, eps=eps)
+    if batched:
+        res = pt.tebd_serve(reqs, max_active=8, svd=svd, eps=eps, batched=True, workers_per_request=0)
+    else:
+        res = pt.tebd_serve(reqs, max_active=8, svd=svd, eps=eps)
     wall = time.perf_counter() - t0
     if any(x["status"] != 0 for x in res):
         raise RuntimeError("a served request failed: " + str([x["status"] for x in res]))
@@ -313,7 +319,9 @@ def serving_sample(pt, n: int, scale: float, eps: float):
             "horizon_scale": scale, "steps_total": sum(r["steps"] for r in reqs),
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "gate_updates_per_s": gu / span, "wall_s": wall,
-            "note": "time-to-horizon = finish - arrival; Gram route; each request on its own handle and stream"}
+            "note": "time-to-horizon = finish - arrival; " + ("Gram" if svd != pt.SVD_JACOBI else "Jacobi") +
+                    (" route; continuous batching: every admitted request stepped together, one fused batch per "
+                     "layer" if batched else " route; each request on its own handle, stream and thread")}
 
 
 def main():
@@ -576,6 +584,14 @@ def main():
     if not args.no_cpu_baseline and time_left():
         log(f"timing the CPU oracle on one chi={args.cpu_chi} gate update")
         out["cpu_baseline"] = cpu_baseline(args.cpu_chi)
+    if args.serve > 0 and time_left():
+        # the same requests and truncation on the Jacobi route, thread per
+        # request against continuous batching
+        log("serving sample, Jacobi route: threads, then continuous batching")
+        out["serving_batching"] = {
+            "threads": serving_sample(pt, args.serve, args.serve_scale, pt.GRAM_EPS_MIN, svd=pt.SVD_JACOBI),
+            "batched": serving_sample(pt, args.serve, args.serve_scale, pt.GRAM_EPS_MIN, svd=pt.SVD_JACOBI,
+                                      batched=True)}
     out["bench_wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out), flush=True)
 

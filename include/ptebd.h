@@ -182,11 +182,15 @@ tebd_status tebd_step(tebd_mps* mps, double dt);
  * time.  Errors as tebd_step. */
 tebd_status tebd_step4(tebd_mps* mps, double dt);
 
-/* One Trotter step for n independent handles, run concurrently: one host
- * thread per handle issues its step on the handle's own stream(s), so that
- * their kernels overlap on the device.  dt[n] per handle.  Handles must be
- * distinct and must not have been created on a shared stream.  Each handle
- * gets exactly the result of tebd_step alone. */
+/* One Trotter step for n independent handles, run concurrently.  When every
+ * handle has opts.fuse set, each Strang layer of all of them is one fused
+ * batch on the stream of mps[0] (the gates of all handles advance in
+ * lockstep and share one batched Jacobi per bond; an error then marks every
+ * handle of the batch ESTATE).  Otherwise one host thread per handle issues
+ * its step on the handle's own stream(s), so that their kernels overlap on
+ * the device.  dt[n] per handle.  Handles must be distinct and must not have
+ * been created on a shared stream.  Each handle gets exactly the result of
+ * tebd_step alone. */
 tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt);
 
 /* Local observables after the last step, FP64, synchronising the handle's stream:
@@ -321,6 +325,13 @@ typedef struct {
   int32_t workers_per_request;  /* gate workers of each request's handle; <= 0 selects 1 */
   int32_t measure_every;      /* measure_local every this many steps as well (0: only at the horizon) */
   int32_t u1;                 /* tebd_opts.u1 for every request (0 or 1) */
+  int32_t batched;            /* 1: continuous batching -- one scheduler thread steps every admitted
+                                 request together, each Strang layer of all of them one fused batch
+                                 (tebd_step_many with tebd_opts.fuse); arrivals join and finished
+                                 requests leave between steps.  Needs svd = TEBD_SVD_JACOBI and
+                                 u1 = 0; workers_per_request <= 0 then gives each request one gate
+                                 workspace per gate of a layer.  A failing step fails every request
+                                 in that batch.  0: a thread per request (default). */
 } tebd_serve_opts;
 
 typedef struct {

@@ -64,7 +64,8 @@ class Request(ctypes.Structure):
 class ServeOpts(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("hbm_budget", ctypes.c_double), ("prec", ctypes.c_int32),
                 ("svd", ctypes.c_int32), ("trunc_weight", ctypes.c_double), ("trunc_rel", ctypes.c_double),
-                ("workers_per_request", ctypes.c_int32), ("measure_every", ctypes.c_int32), ("u1", ctypes.c_int32)]
+                ("workers_per_request", ctypes.c_int32), ("measure_every", ctypes.c_int32), ("u1", ctypes.c_int32),
+                ("batched", ctypes.c_int32)]
 
 
 class ServeResult(ctypes.Structure):
@@ -351,7 +352,7 @@ def mps_free(h):
 
 def tebd_serve(requests, max_active: int = 8, hbm_budget: float = 0.0, prec: int = FP64, svd: int = SVD_JACOBI,
                w_max: float = 1e-12, eps: float = 1e-12, workers_per_request: int = 1, measure_every: int = 0,
-               u1: bool = False):
+               u1: bool = False, batched: bool = False):
     """Serve quench requests concurrently (see tebd_serve in ptebd.h).
 
     ``requests`` are dicts with keys model (a Model), chi_max, dt, steps,
@@ -363,7 +364,8 @@ def tebd_serve(requests, max_active: int = 8, hbm_budget: float = 0.0, prec: int
     for i, r in enumerate(requests):
         req[i] = Request(r["model"], int(r["chi_max"]), float(r["dt"]), int(r["steps"]), float(r["arrival"]),
                          int(r.get("first_occupied", 1)))
-    so = ServeOpts(max_active, hbm_budget, prec, svd, w_max, eps, workers_per_request, measure_every, int(bool(u1)))
+    so = ServeOpts(max_active, hbm_budget, prec, svd, w_max, eps, workers_per_request, measure_every, int(bool(u1)),
+                   int(bool(batched)))
     res = (ServeResult * n)()
     Ls = [r["model"].L for r in requests]
     nn = np.zeros(sum(Ls))

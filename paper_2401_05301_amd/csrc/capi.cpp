@@ -303,6 +303,23 @@ tebd_status tebd_step_many(tebd_mps* const* mps, int32_t n, const double* dt) {
       if (mps[k] == mps[i]) return fail(TEBD_EINVAL, "handles must be distinct");
   }
   if (n == 1) return tebd_step(mps[0], dt[0]);
+  bool fused = n > 1;
+  for (int i = 0; i < n; ++i) fused = fused && mps[i]->opts.fuse != 0 && !mps[i]->super;
+  if (fused) {
+    // one fused batch per layer over all handles: the Strang layers of
+    // tebd_step, each handle with its own dt
+    ProfBind pb(mps[0]);
+    std::vector<tebd_mps*> hs(mps, mps + n);
+    return guard([&] {
+      const int groups[5] = {0, 1, 2, 1, 0};
+      const double frac[5] = {0.5, 0.5, 1.0, 0.5, 0.5};
+      std::vector<double> tau(n);
+      for (int l = 0; l < 5; ++l) {
+        for (int i = 0; i < n; ++i) tau[i] = frac[l] == 1.0 ? dt[i] : 0.5 * dt[i];
+        ptebd::layers_many(hs, groups[l], tau);
+      }
+    });
+  }
   // Each handle runs its own stream(s); one host thread per handle issues its
   // step, so that the handles' kernels overlap on the device.
   std::vector<tebd_status> status(n, TEBD_OK);

@@ -87,7 +87,11 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 }  // namespace
 
 int64_t fused_table_bytes(int L) {
-  return (int64_t)(sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) * (L + 1) + 128;
+  // one entry per gate of a layer, and room for the gates of several handles
+  // stepped together (tebd_step_many)
+  return (int64_t)(sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) *
+             std::max(L + 1, 256) +
+         128;
 }
 
 size_t Sizes::bytes(int workers, bool u1, bool fuse) const {
@@ -274,8 +278,7 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
                   sizeof(double)) * cnt + 128;
     W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
   } else if (W->opts.fuse) {
-    // batched Jacobi tables of a fused layer (one matrix per worker, at most
-    // one worker per gate of a layer)
+    // batched Jacobi tables of a fused layer
     W->u_batch_cap = fused_table_bytes(W->L);
     W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
   }
@@ -2161,23 +2164,36 @@ void jac_gather(JacSvd& x, hipStream_t s) {
     gather_rows(W->W.re, W->W.im, n, W->perm, nullptr, x.k, n, x.vhr, x.vhi, n, kdev, s);
 }
 
-// The SVDs of v (one per workspace) as one batched one-sided Jacobi on the
-// stream of R, then one read-back of all truncation ranks.
+// The SVDs of v (one per workspace) as batched one-sided Jacobi on the
+// stream of R, in as few groups as R's tables allow, then one read-back of
+// all truncation ranks.
 void jac_batch(tebd_mps* R, std::vector<JacSvd>& v, hipStream_t s) {
   if (R->stream != s) throw Error(-3, "fused layer: the Jacobi runner must use the layer's stream");
   for (const JacSvd& x : v) jac_stage(x, s);
-  std::vector<JacobiArgs> tab;
-  tab.reserve(v.size());
-  for (const JacSvd& x : v) tab.push_back(jac_entry(x));
-  run_jacobi_group(R, tab);
+  const size_t per = sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double);
+  const size_t fit = R->u_batch_cap > 128 ? ((size_t)R->u_batch_cap - 128) / per : 0;
+  if (fit == 0) throw Error(-1, "fused layer: no batched Jacobi tables");
+  for (size_t g0 = 0; g0 < v.size(); g0 += fit) {
+    std::vector<JacobiArgs> tab;
+    for (size_t i = g0; i < std::min(v.size(), g0 + fit); ++i) tab.push_back(jac_entry(v[i]));
+    run_jacobi_group(R, tab);
+  }
   for (const JacSvd& x : v) jac_select(x, s);
   PTEBD_HIP(hipStreamSynchronize(s));
   for (JacSvd& x : v) jac_gather(x, s);
 }
 
-// All gates of one commuting layer on the Jacobi route, in lockstep on the
-// handle's stream, one gate per worker workspace at a time: the theta and
-// gate products of the gates are issued back to back, their SVDs across
+// One gate of a fused layer: the state it acts on, the workspace it uses.
+struct FusedJob {
+  tebd_mps* M;
+  tebd_mps* W;
+  int j;
+  std::pair<double*, double*> G;
+};
+
+// Gates on disjoint sites, each with a workspace of its own, in lockstep on
+// stream s (Sec. I: the gates of a layer are independent): the theta and
+// gate products of all of them are issued back to back, their SVDs across
 // bond j+1 run as one batched Jacobi (every round launches the pair Grams
 // and rotations of all gates still rotating, and each sweep ends in one
 // read-back for all of them instead of one per gate), and the same again
@@ -2185,53 +2201,72 @@ void jac_batch(tebd_mps* R, std::vector<JacSvd>& v, hipStream_t s) {
 // tolerances and sweeps it takes in gate_update, so the result is the same
 // bit for bit; what changes is the number of launches and host round trips
 // per layer, which bound the small-chi regime.
-void fused_layer(tebd_mps* M, const std::vector<int>& js, const std::vector<std::pair<double*, double*>>& G) {
-  hipStream_t s = M->stream;
-  tebd_mps* R = M->workers[0];
-  const size_t nw = std::min(M->workers.size(), js.size());
-  const int d = M->d;
-  for (size_t x0 = 0; x0 < js.size(); x0 += nw) {
-    const size_t cnt = std::min(nw, js.size() - x0);
-    std::vector<JacSvd> v(cnt);
-    for (size_t i = 0; i < cnt; ++i) {
-      tebd_mps* W = M->workers[i];
-      const int j = js[x0 + i];
-      const int cl = M->chi[j], cr = M->chi[j + 3];
-      W->ledger = M->wslots + j;
-      theta_gate(M, W, j, G[x0 + i], s);
-      JacSvd& x = v[i];
-      x.W = W;
-      x.in = SvdIn{W->psip.re, W->psip.im, (int64_t)d * d * cr, cl * d, d * d * cr, M->lam[j], d};
-      x.lam_out = M->lam[j + 1];
-      x.vhr = W->V1h.re;
-      x.vhi = W->V1h.im;
-      x.slot = 0;
-      x.xbuf = W->psi;
-    }
-    jac_batch(R, v, s);
-    std::vector<int> k1(cnt);
-    for (size_t i = 0; i < cnt; ++i) {
-      JacSvd& x = v[i];
-      tebd_mps* W = x.W;
-      const int j = js[x0 + i];
-      const int cr = M->chi[j + 3];
-      k1[i] = x.k;
-      update_left_jacobi(M, W, j, x.in.m, x.in.n, k1[i], s);
-      x.in = SvdIn{W->V1h.re, W->V1h.im, (int64_t)d * cr, k1[i] * d, d * cr, M->lam[j + 1], d};
-      x.lam_out = M->lam[j + 2];
-      x.vhr = M->Br[j + 2];
-      x.vhi = M->Bi[j + 2];
-      x.slot = 1;
-      x.xbuf = W->X2;
-    }
-    jac_batch(R, v, s);
-    for (size_t i = 0; i < cnt; ++i) {
-      const int j = js[x0 + i];
-      update_middle_jacobi(M, v[i].W, j, v[i].in.m, v[i].in.n, v[i].k, s);
-      M->chi[j + 1] = k1[i];
-      M->chi[j + 2] = v[i].k;
-    }
+void fused_chunk(const std::vector<FusedJob>& jobs, tebd_mps* R, hipStream_t s) {
+  const size_t cnt = jobs.size();
+  std::vector<JacSvd> v(cnt);
+  for (size_t i = 0; i < cnt; ++i) {
+    const FusedJob& b = jobs[i];
+    tebd_mps *M = b.M, *W = b.W;
+    const int j = b.j, d = M->d;
+    const int cl = M->chi[j], cr = M->chi[j + 3];
+    W->ledger = M->wslots + j;
+    theta_gate(M, W, j, b.G, s);
+    JacSvd& x = v[i];
+    x.W = W;
+    x.in = SvdIn{W->psip.re, W->psip.im, (int64_t)d * d * cr, cl * d, d * d * cr, M->lam[j], d};
+    x.lam_out = M->lam[j + 1];
+    x.vhr = W->V1h.re;
+    x.vhi = W->V1h.im;
+    x.slot = 0;
+    x.xbuf = W->psi;
   }
+  jac_batch(R, v, s);
+  std::vector<int> k1(cnt);
+  for (size_t i = 0; i < cnt; ++i) {
+    const FusedJob& b = jobs[i];
+    tebd_mps *M = b.M, *W = b.W;
+    const int j = b.j, d = M->d;
+    const int cr = M->chi[j + 3];
+    JacSvd& x = v[i];
+    k1[i] = x.k;
+    update_left_jacobi(M, W, j, x.in.m, x.in.n, k1[i], s);
+    x.in = SvdIn{W->V1h.re, W->V1h.im, (int64_t)d * cr, k1[i] * d, d * cr, M->lam[j + 1], d};
+    x.lam_out = M->lam[j + 2];
+    x.vhr = M->Br[j + 2];
+    x.vhi = M->Bi[j + 2];
+    x.slot = 1;
+    x.xbuf = W->X2;
+  }
+  jac_batch(R, v, s);
+  for (size_t i = 0; i < cnt; ++i) {
+    const FusedJob& b = jobs[i];
+    update_middle_jacobi(b.M, b.W, b.j, v[i].in.m, v[i].in.n, v[i].k, s);
+    b.M->chi[b.j + 1] = k1[i];
+    b.M->chi[b.j + 2] = v[i].k;
+  }
+}
+
+// The gates js of one layer of each handle Ms[h] (device gates G[h]), fused
+// on the stream of Ms[0]: chunk c takes, from every handle, the gates
+// c nw_h .. (c + 1) nw_h - 1 of its list, nw_h its number of workspaces.
+void fused_run(const std::vector<tebd_mps*>& Ms, const std::vector<std::vector<int>>& js,
+               const std::vector<std::vector<std::pair<double*, double*>>>& G) {
+  tebd_mps* R = Ms[0]->workers[0];
+  hipStream_t s = Ms[0]->stream;
+  for (size_t c = 0;; ++c) {
+    std::vector<FusedJob> jobs;
+    for (size_t h = 0; h < Ms.size(); ++h) {
+      const size_t nw = Ms[h]->workers.size();
+      for (size_t w = 0; w < nw && c * nw + w < js[h].size(); ++w)
+        jobs.push_back(FusedJob{Ms[h], Ms[h]->workers[w], js[h][c * nw + w], G[h][c * nw + w]});
+    }
+    if (jobs.empty()) return;
+    fused_chunk(jobs, R, s);
+  }
+}
+
+void fused_layer(tebd_mps* M, const std::vector<int>& js, const std::vector<std::pair<double*, double*>>& G) {
+  fused_run({M}, {js}, {G});
 }
 
 }  // namespace
@@ -2331,6 +2366,41 @@ void layer(tebd_mps* M, int group, double tau) {
     G.push_back(device_gate(M, j, tau));
   }
   run_gates(M, js, G, true);
+}
+
+void layers_many(const std::vector<tebd_mps*>& Ms, int group, const std::vector<double>& taus) {
+  const size_t n = Ms.size();
+  hipStream_t s = Ms[0]->stream;
+  std::vector<std::vector<int>> js(n);
+  std::vector<std::vector<std::pair<double*, double*>>> G(n);
+  for (size_t h = 0; h < n; ++h) {
+    js[h] = group_gates(Ms[h], group);
+    for (int j : js[h]) G[h].push_back(device_gate(Ms[h], j, taus[h]));
+  }
+  // stream s starts after the pending work of every handle, and every
+  // handle's stream continues after s (so that freeing a handle, which
+  // drains its own stream, also waits for the fused launches)
+  auto join = [](hipStream_t from, hipStream_t to) {
+    if (from == to) return;
+    hipEvent_t e;
+    PTEBD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    PTEBD_HIP(hipEventRecord(e, from));
+    PTEBD_HIP(hipStreamWaitEvent(to, e, 0));
+    PTEBD_HIP(hipEventDestroy(e));
+  };
+  for (size_t h = 1; h < n; ++h) join(Ms[h]->stream, s);
+  for (tebd_mps* M : Ms) fill_zero(M->wslots, M->L, s);
+  try {
+    fused_run(Ms, js, G);
+  } catch (...) {
+    // every handle of the batch is left half applied; the launches already
+    // queued still touch their buffers, so they drain before anyone frees them
+    for (tebd_mps* M : Ms) M->failed = true;
+    (void)hipStreamSynchronize(s);
+    throw;
+  }
+  for (tebd_mps* M : Ms) accumulate_slots(M->wslots, M->L, M->ledger, s);
+  for (size_t h = 1; h < n; ++h) join(s, Ms[h]->stream);
 }
 
 void canonicalize(tebd_mps* M) {

@@ -152,7 +152,7 @@ struct Sizes {
 // most the number of gates in a layer (L sites of the chain the MPS lives
 // on; two-site gates on a super-site chain).
 int auto_workers(int L, int requested, bool super = false, bool u1 = false, bool fuse = false);
-// Device bytes of the batched Jacobi tables of a fused layer on L sites.
+// Device bytes of the batched Jacobi tables of a fused-layer workspace on L sites.
 int64_t fused_table_bytes(int L);
 
 Sizes plan_sizes(int L, int d, int chi_max);
@@ -170,6 +170,11 @@ void upload_product(tebd_mps* M, const int* occ);
 void upload_state(tebd_mps* M, const int* chi, const double* B, const double* lam);
 void set_model(tebd_mps* M, const ModelP& m);
 void layer(tebd_mps* M, int group, double tau);
+// Layer `group` of every handle in Ms (time slice taus[h] for handle h) as one
+// fused batch on the stream of Ms[0]: every handle has opts.fuse set (three-
+// site chain, Jacobi route).  Each handle's result is the one layer() gives;
+// an error marks every handle of the batch failed.
+void layers_many(const std::vector<tebd_mps*>& Ms, int group, const std::vector<double>& taus);
 // Sweep of identity gates j = 0..L-3: brings a right-orthonormal state into
 // the canonical form with exact Schmidt values (up to truncation).
 void canonicalize(tebd_mps* M);

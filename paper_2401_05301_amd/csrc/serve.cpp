@@ -8,6 +8,13 @@
 // Every request is evolved exactly as tebd_step / measure_local would evolve
 // it alone: handles share no state, so the result of a request does not
 // depend on the mix it ran in.
+//
+// With continuous batching (tebd_serve_opts.batched) one scheduler thread
+// instead steps all admitted requests together: each Strang layer of all of
+// them is one fused batch (tebd_step_many), so their small SVDs share one
+// batched Jacobi and one host read-back per sweep.  Arrivals are admitted
+// and finished requests retired between steps; results are again those of
+// each request alone.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -59,7 +66,8 @@ extern "C" tebd_status tebd_serve(const tebd_request* req, int32_t n, const tebd
     o.prec = so->prec;
     o.svd = so->svd;
     o.u1 = so->u1;
-    o.workers = so->workers_per_request > 0 ? so->workers_per_request : 1;
+    o.fuse = so->batched ? 1 : 0;
+    o.workers = so->workers_per_request > 0 ? so->workers_per_request : (so->batched ? 0 : 1);
     tebd_status st = mps_footprint(&r.model, &o, &footprint[i]);
     if (st) return st;   // message set by mps_footprint
     off_n[i + 1] = off_n[i] + r.model.L;
@@ -83,11 +91,92 @@ extern "C" tebd_status tebd_serve(const tebd_request* req, int32_t n, const tebd
       return TEBD_ENOMEM;
     }
   const int slots = so->max_active > 0 ? so->max_active : 8;
+  if (so->batched != 0 && so->batched != 1) {
+    ptebd::set_last_error("tebd_serve: batched must be 0 or 1");
+    return TEBD_EINVAL;
+  }
 
   // arrival order (stable for equal times)
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return req[a].arrival < req[b].arrival; });
+
+  if (so->batched) {
+    // Continuous batching: admitted requests are stepped together, one
+    // fused batch per Strang layer; requests join and leave between steps.
+    struct Live {
+      int i;
+      tebd_mps* M;
+      int done;
+    };
+    std::vector<Live> live;
+    size_t reserved = 0;
+    const Clock::time_point t0 = Clock::now();
+    const int every = so->measure_every;
+    auto measure = [&](int i, tebd_mps* M) {
+      return measure_local(M, n_out ? n_out + off_n[i] : nullptr, cnn_out ? cnn_out + off_c[i] : nullptr,
+                           cnnn_out ? cnnn_out + off_d[i] : nullptr);
+    };
+    auto finish = [&](int i, tebd_mps* M, tebd_status st) {
+      if (!st) st = measure(i, M);
+      double w = 0.0;
+      if (!st) st = mps_discarded_weight(M, &w);
+      if (M) mps_free(M);
+      res[i].status = st;
+      res[i].discarded_weight = w;
+      res[i].gate_updates = st ? 0 : (int64_t)req[i].steps * gates_per_step(req[i].model.L);
+      res[i].finished = seconds_since(t0);
+      reserved -= footprint[i];
+    };
+    int next = 0;
+    while (next < n || !live.empty()) {
+      while (next < n) {   // admit, first come first served, while a slot and the memory are free
+        const int i = order[next];
+        if (seconds_since(t0) < req[i].arrival || (int)live.size() >= slots || reserved + footprint[i] > budget)
+          break;
+        res[i].arrival = req[i].arrival;
+        res[i].admitted = seconds_since(t0);
+        reserved += footprint[i];
+        ++next;
+        tebd_mps* M = nullptr;
+        tebd_status st = mps_init_cdw(&req[i].model, &opts[i], req[i].first_occupied, &M);
+        if (!st) st = tebd_prepare(M, req[i].dt);
+        if (st || req[i].steps == 0)
+          finish(i, M, st);
+        else
+          live.push_back(Live{i, M, 0});
+      }
+      if (live.empty()) {
+        if (next < n) {
+          const double wait = req[order[next]].arrival - seconds_since(t0);
+          if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+        }
+        continue;
+      }
+      std::vector<tebd_mps*> hs;
+      std::vector<double> dts;
+      for (const Live& x : live) {
+        hs.push_back(x.M);
+        dts.push_back(req[x.i].dt);
+      }
+      const tebd_status st = tebd_step_many(hs.data(), (int32_t)hs.size(), dts.data());
+      std::vector<Live> keep;
+      for (Live& x : live) {
+        tebd_status sx = st;
+        ++x.done;
+        if (!sx && every > 0 && x.done % every == 0 && x.done < req[x.i].steps) sx = measure(x.i, x.M);
+        if (sx || x.done == req[x.i].steps)
+          finish(x.i, x.M, sx);
+        else
+          keep.push_back(x);
+      }
+      live.swap(keep);
+    }
+    tebd_status first = TEBD_OK;
+    for (int i = 0; i < n && !first; ++i) first = (tebd_status)res[i].status;
+    if (first) ptebd::set_last_error("tebd_serve: at least one request failed (see the per-request status)");
+    return first;
+  }
 
   std::mutex mu;
   std::condition_variable cv;

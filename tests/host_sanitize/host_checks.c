@@ -209,6 +209,18 @@ static void serving(void) {
   for (int i = 0; i < N; ++i) finished &= res[i].finished >= res[i].admitted && res[i].admitted >= res[i].arrival;
   CHECK(finished, "every request admitted after arrival and finished after admission");
   printf("serving %d requests (status %d without a device): %s\n", N, (int)st, finished ? "ok" : "FAILED");
+  /* continuous batching: one scheduler thread, the same admission rule */
+  memset(res, 0, sizeof(res));
+  so.batched = 1;
+  so.workers_per_request = 0;
+  const tebd_status st2 = tebd_serve(req, N, &so, res, n_out, NULL, NULL);
+  finished = 1;
+  for (int i = 0; i < N; ++i) finished &= res[i].finished >= res[i].admitted && res[i].admitted >= res[i].arrival;
+  CHECK(finished && st2 != TEBD_OK, "batched serving admits and retires every request");
+  so.svd = TEBD_SVD_GRAM_EIG;
+  so.trunc_rel = TEBD_GRAM_EPS_MIN;
+  CHECK(tebd_serve(req, N, &so, res, n_out, NULL, NULL) == TEBD_EINVAL, "batched serving needs the Jacobi route");
+  printf("batched serving (status %d without a device): %s\n", (int)st2, finished ? "ok" : "FAILED");
   free(n_out);
 }
 

@@ -106,3 +106,47 @@ def test_serving_u1_matches_alone_and_dense(pt):
         # within the parity bar (the test chains keep gaps at the cut)
         assert np.abs(n - nd).max() <= 1e-9
         assert np.abs(C - Cd).max() <= 1e-9
+
+
+def test_fused_step_many_matches_single_steps(pt):
+    """tebd_step_many over fused handles (one fused batch per layer across
+    all of them, each handle with its own dt) against tebd_step on each."""
+    reqs = requests(pt)[:4]
+    dts = [0.01, 0.02, 0.015, 0.01]
+    note("fused tebd_step_many on 4 handles vs tebd_step")
+    hs, ref = [], []
+    for r in reqs:
+        hs.append(pt.MPS.cdw(r["model"], pt.make_opts(r["chi_max"], 1e-12, 1e-12, fuse=True)))
+        ref.append(pt.MPS.cdw(r["model"], pt.make_opts(r["chi_max"], 1e-12, 1e-12, workers=1)))
+    for _ in range(15):
+        pt.tebd_step_many([g.h for g in hs], dts)
+        for g, dt in zip(ref, dts):
+            g.step(dt)
+    for g, q in zip(hs, ref):
+        n1, C1, D1 = g.measure()
+        n2, C2, D2 = q.measure()
+        assert g.bond_dims() == q.bond_dims()
+        assert np.abs(n1 - n2).max() <= 1e-13 and np.abs(C1 - C2).max() <= 1e-13 and np.abs(D1 - D2).max() <= 1e-13
+        assert abs(g.discarded_weight() - q.discarded_weight()) <= 1e-15
+        for b in range(g.sites + 1):
+            assert np.abs(g.lam(b) - q.lam(b)).max() <= 1e-13
+        g.close()
+        q.close()
+
+
+def test_batched_serving_matches_alone(pt):
+    """Continuous batching: the admitted requests step together, one fused
+    batch per layer; every request still gets its result alone."""
+    reqs = requests(pt)
+    note(f"batched serving of {len(reqs)} requests, 4 slots")
+    res = pt.tebd_serve(reqs, max_active=4, hbm_budget=8e9, batched=True, workers_per_request=0, measure_every=5)
+    for r, s in zip(reqs, res):
+        assert s["status"] == pt.TEBD_OK
+        assert s["admitted"] >= s["arrival"] - 1e-9 and s["finished"] >= s["admitted"]
+        gates = sum(len(range(g0, r["model"].L - 2, 3)) for g0 in (0, 1, 2, 1, 0))
+        assert s["gate_updates"] == r["steps"] * gates
+        n, C, D, w = alone(pt, r)
+        assert np.abs(s["n"] - n).max() <= 1e-13
+        assert np.abs(s["c_nn"] - C).max() <= 1e-13
+        assert np.abs(s["c_nnn"] - D).max() <= 1e-13
+        assert abs(s["discarded_weight"] - w) <= 1e-15
