@@ -5,8 +5,8 @@ namespace ptebd {
 
 namespace {
 
-__global__ void scale_rows_copy_kernel(const double* xr, const double* xi, int64_t ldx, const double* rs, int rdiv,
-                                       int rows, int cols, double* yr, double* yi, int64_t ldy) {
+__device__ __forceinline__ void scale_rows_body(const double* xr, const double* xi, int64_t ldx, const double* rs,
+                                                int rdiv, int rows, int cols, double* yr, double* yi, int64_t ldy) {
   const int i = blockIdx.y;
   if (i >= rows) return;
   const double s = rs ? rs[i / rdiv] : 1.0;
@@ -16,11 +16,15 @@ __global__ void scale_rows_copy_kernel(const double* xr, const double* xi, int64
   }
 }
 
+__global__ void scale_rows_copy_kernel(const double* xr, const double* xi, int64_t ldx, const double* rs, int rdiv,
+                                       int rows, int cols, double* yr, double* yi, int64_t ldy) {
+  scale_rows_body(xr, xi, ldx, rs, rdiv, rows, cols, yr, yi, ldy);
+}
+
 // 32 x 32 tiles through LDS so that both the read and the write are coalesced.
-__global__ __launch_bounds__(256) void conj_transpose_kernel(const double* xr, const double* xi, int64_t ldx,
-                                                             const double* rs, int rdiv, int rows, int cols,
-                                                             double* yr, double* yi, int64_t ldy) {
-  __shared__ double tr[32][33], ti[32][33];
+__device__ __forceinline__ void conj_transpose_body(const double* xr, const double* xi, int64_t ldx,
+                                                    const double* rs, int rdiv, int rows, int cols, double* yr,
+                                                    double* yi, int64_t ldy, double (*tr)[33], double (*ti)[33]) {
   const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows per pass
   for (int r = ty; r < 32; r += 8) {
@@ -39,6 +43,27 @@ __global__ __launch_bounds__(256) void conj_transpose_kernel(const double* xr, c
       yi[(int64_t)j * ldy + i] = ti[tx][r];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void conj_transpose_kernel(const double* xr, const double* xi, int64_t ldx,
+                                                             const double* rs, int rdiv, int rows, int cols,
+                                                             double* yr, double* yi, int64_t ldy) {
+  __shared__ double tr[32][33], ti[32][33];
+  conj_transpose_body(xr, xi, ldx, rs, rdiv, rows, cols, yr, yi, ldy, tr, ti);
+}
+
+// the staging of matrix blockIdx.z of a fused batch, by its kind
+__global__ void fused_scale_rows_kernel(const FusedSvdArgs* tab) {
+  const FusedSvdArgs& a = tab[blockIdx.z];
+  if (a.transpose) return;
+  scale_rows_body(a.xr, a.xi, a.ldx, a.rs, a.rdiv, a.rows, a.cols, a.yr, a.yi, a.ldy);
+}
+
+__global__ __launch_bounds__(256) void fused_transpose_kernel(const FusedSvdArgs* tab) {
+  __shared__ double tr[32][33], ti[32][33];
+  const FusedSvdArgs& a = tab[blockIdx.z];
+  if (!a.transpose) return;
+  conj_transpose_body(a.xr, a.xi, a.ldx, a.rs, a.rdiv, a.rows, a.cols, a.yr, a.yi, a.ldy, tr, ti);
 }
 
 __global__ void set_identity_kernel(double* wr, double* wi, int64_t ldw, int r) {
@@ -623,6 +648,14 @@ void conj_transpose_scaled(const double* xr, const double* xi, int64_t ldx, cons
   if (rows <= 0 || cols <= 0) return;
   dim3 g(ceil_div(cols, 32), ceil_div(rows, 32));
   conj_transpose_kernel<<<g, 256, 0, s>>>(xr, xi, ldx, rs, rdiv, rows, cols, yr, yi, ldy);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void fused_stage(const FusedSvdArgs* tab, int count, int max_rows, int max_cols, hipStream_t s) {
+  if (count <= 0 || max_rows <= 0 || max_cols <= 0) return;
+  fused_scale_rows_kernel<<<dim3(std::min(ceil_div(max_cols, 256), 64), max_rows, count), 256, 0, s>>>(tab);
+  PTEBD_LAUNCH_CHECK();
+  fused_transpose_kernel<<<dim3(ceil_div(max_cols, 32), ceil_div(max_rows, 32), count), 256, 0, s>>>(tab);
   PTEBD_LAUNCH_CHECK();
 }
 

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <functional>
 #include <string>
 #include <thread>
 
@@ -88,10 +89,10 @@ tebd_mps::Z zalloc(tebd_mps* M, int64_t n) {
 
 int64_t fused_table_bytes(int L) {
   // one entry per gate of a layer, and room for the gates of several handles
-  // stepped together (tebd_step_many)
+  // stepped together (tebd_step_many); then the SVD descriptors and ranks
   return (int64_t)(sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) *
-             std::max(L + 1, 256) +
-         128;
+             std::max(L + 1, kFusedMax) +
+         128 + (int64_t)kFusedMax * (sizeof(FusedSvdArgs) + 2 * sizeof(int));
 }
 
 size_t Sizes::bytes(int workers, bool u1, bool fuse) const {
@@ -278,9 +279,15 @@ void allocate_work(tebd_mps* W, const Sizes& s) {
                   sizeof(double)) * cnt + 128;
     W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
   } else if (W->opts.fuse) {
-    // batched Jacobi tables of a fused layer
-    W->u_batch_cap = fused_table_bytes(W->L);
+    // batched Jacobi tables of a fused layer, then the SVD descriptors
+    W->u_batch_cap = (int64_t)(sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double)) *
+                         std::max(W->L + 1, kFusedMax) +
+                     128;
     W->u_batch = dev_alloc(W, (size_t)W->u_batch_cap);
+    W->f_tab = static_cast<FusedSvdArgs*>(dev_alloc(W, sizeof(FusedSvdArgs) * kFusedMax));
+    W->f_k = static_cast<int*>(dev_alloc(W, sizeof(int) * 2 * kFusedMax));
+    PTEBD_HIP(hipHostMalloc((void**)&W->h_ftab, sizeof(FusedSvdArgs) * kFusedMax, hipHostMallocDefault));
+    PTEBD_HIP(hipHostMalloc((void**)&W->h_fk, sizeof(int) * 2 * kFusedMax, hipHostMallocDefault));
   }
   W->info_i = static_cast<int*>(dev_alloc(W, sizeof(int) * 8));
   W->info_d = dalloc(W, 16);
@@ -363,6 +370,10 @@ void mps_release(tebd_mps* M) {
   if (M->h_info) (void)hipHostFree(M->h_info);
   if (M->h_part) (void)hipHostFree(M->h_part);
   if (M->h_ratio) (void)hipHostFree(M->h_ratio);
+  if (M->h_ftab) (void)hipHostFree(M->h_ftab);
+  if (M->h_fk) (void)hipHostFree(M->h_fk);
+  M->h_ftab = nullptr;
+  M->h_fk = nullptr;
   M->h_ratio = nullptr;
   M->h_counter = nullptr;
   M->h_info = nullptr;
@@ -564,7 +575,8 @@ int run_jacobi(tebd_mps* M, double* xr, double* xi, int64_t ldx, double* wr, dou
 // device instead of running their latency-bound rounds one after the other.
 // Every matrix takes the launch shape, tolerances and sweeps it would take
 // alone, so its result is the same bit for bit.
-void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab) {
+void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab,
+                      const std::function<void(double* tiny2)>& prologue = nullptr) {
   hipStream_t s = M->stream;
   const int count = (int)tab.size();
   // device layout in u_batch: JacobiArgs[count], gram_first[count+1], rot_first[count+1],
@@ -583,13 +595,18 @@ void run_jacobi_group(tebd_mps* M, std::vector<JacobiArgs>& tab) {
   std::vector<int64_t>& first = M->h_first;
   first.assign(2 * (count + 1), 0);
   int max_nb = 0;
+  // the floor of every matrix into d_tiny2[i] and the identity into its
+  // vectors: one matrix after the other, or in one batch by the caller
+  if (prologue) prologue(d_tiny2);
   for (int i = 0; i < count; ++i) {
     JacobiArgs& a = tab[i];
-    row_norms(a.xr, a.xi, a.ldx, a.r, a.c, M->norms, s);
-    negligible_norm2(M->norms, a.r, d_tiny2 + i, s);
+    if (!prologue) {
+      row_norms(a.xr, a.xi, a.ldx, a.r, a.c, M->norms, s);
+      negligible_norm2(M->norms, a.r, d_tiny2 + i, s);
+      if (a.wr) set_identity(a.wr, a.wi, a.ldw, a.r, s);
+    }
     a.tiny2 = d_tiny2 + i;
     a.rotated = d_counts + i;
-    if (a.wr) set_identity(a.wr, a.wi, a.ldw, a.r, s);
     first[i + 1] = first[i] + (int64_t)(a.nb / 2) * a.nsplit;
     first[count + 1 + i + 1] = first[count + 1 + i] + (int64_t)(a.nb / 2) * a.nuchunks;
     max_nb = std::max(max_nb, a.nb);
@@ -2121,14 +2138,6 @@ struct JacSvd {
 // right singular vectors accumulated in W->W.
 bool jac_rows(const SvdIn& in) { return in.m <= in.n; }
 
-void jac_stage(const JacSvd& x, hipStream_t s) {
-  const SvdIn& in = x.in;
-  if (jac_rows(in))
-    scale_rows_copy(in.ar, in.ai, in.lda, in.rs, in.rdiv, in.m, in.n, x.xbuf.re, x.xbuf.im, in.n, s);
-  else
-    conj_transpose_scaled(in.ar, in.ai, in.lda, in.rs, in.rdiv, in.m, in.n, x.xbuf.re, x.xbuf.im, in.m, s);
-}
-
 JacobiArgs jac_entry(const JacSvd& x) {
   const SvdIn& in = x.in;
   tebd_mps* W = x.W;
@@ -2141,46 +2150,90 @@ JacobiArgs jac_entry(const JacSvd& x) {
   return a;
 }
 
-void jac_select(const JacSvd& x, hipStream_t s) {
+// The arguments of every small step of x's SVD (staging, row norms, the
+// Jacobi prologue, selection, gathering), as svd_trunc's Jacobi branch
+// passes them to the single-matrix launchers; kout receives k and the rule.
+FusedSvdArgs fused_args(const JacSvd& x, int* kout) {
+  const SvdIn& in = x.in;
   tebd_mps* W = x.W;
-  const bool rows = jac_rows(x.in);
-  const int r = rows ? x.in.m : x.in.n, c = rows ? x.in.n : x.in.m;
-  int* kdev = W->info_i + x.slot;
-  row_norms(x.xbuf.re, x.xbuf.im, c, r, c, W->norms, s);
-  select_truncate(W->norms, r, 0, W->chi_max, W->opts.trunc_weight, W->opts.trunc_rel, x.lam_out, W->perm,
-                  W->inv_sig, kdev, W->info_d + 2 * x.slot, W->ledger, nullptr, s);
-  PTEBD_HIP(hipMemcpyAsync(W->h_info, kdev, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+  const bool rows = jac_rows(in);
+  FusedSvdArgs f{};
+  f.xr = in.ar; f.xi = in.ai; f.ldx = in.lda;
+  f.rs = in.rs; f.rdiv = in.rdiv;
+  f.rows = in.m; f.cols = in.n; f.transpose = rows ? 0 : 1;
+  f.yr = x.xbuf.re; f.yi = x.xbuf.im; f.ldy = rows ? in.n : in.m;
+  f.r = rows ? in.m : in.n;
+  f.c = rows ? in.n : in.m;
+  f.norms = W->norms;
+  f.wr = rows ? nullptr : W->W.re;
+  f.wi = rows ? nullptr : W->W.im;
+  f.ldw = in.n;
+  int np2 = 1;
+  while (np2 < f.r) np2 <<= 1;
+  f.npow2 = np2;
+  f.is_gram = 0;
+  f.chi_max = W->chi_max;
+  f.w_max = W->opts.trunc_weight;
+  f.eps = W->opts.trunc_rel;
+  f.extra_tail = nullptr;
+  f.lam_out = x.lam_out; f.perm = W->perm; f.inv_sig = W->inv_sig;
+  f.info_i = W->info_i + x.slot; f.info_d = W->info_d + 2 * x.slot; f.ledger = W->ledger;
+  f.kout = kout;
+  f.gr = rows ? x.xbuf.re : W->W.re;
+  f.gi = rows ? x.xbuf.im : W->W.im;
+  f.ldg = in.n;
+  f.gscale = rows ? 1 : 0;
+  f.gc = in.n;
+  f.dr = x.vhr; f.di = x.vhi; f.ldd = in.n;
+  return f;
 }
 
-void jac_gather(JacSvd& x, hipStream_t s) {
-  tebd_mps* W = x.W;
-  const int n = x.in.n;
-  int* kdev = W->info_i + x.slot;
-  x.k = W->h_info[0];
-  count_rule(W);
-  if (jac_rows(x.in))
-    gather_rows(x.xbuf.re, x.xbuf.im, n, W->perm, W->inv_sig, x.k, n, x.vhr, x.vhi, n, kdev, s);
-  else
-    gather_rows(W->W.re, W->W.im, n, W->perm, nullptr, x.k, n, x.vhr, x.vhi, n, kdev, s);
-}
-
-// The SVDs of v (one per workspace) as batched one-sided Jacobi on the
-// stream of R, in as few groups as R's tables allow, then one read-back of
-// all truncation ranks.
+// The SVDs of v (one per workspace) on the stream of R, in groups of up to
+// kFusedMax: every small step is one launch for the whole group, the Jacobi
+// sweeps run batched, and one read-back per group returns all truncation
+// ranks.
 void jac_batch(tebd_mps* R, std::vector<JacSvd>& v, hipStream_t s) {
   if (R->stream != s) throw Error(-3, "fused layer: the Jacobi runner must use the layer's stream");
-  for (const JacSvd& x : v) jac_stage(x, s);
+  if (!R->f_tab || !R->u_batch) throw Error(-1, "fused layer: the runner has no batch tables");
   const size_t per = sizeof(JacobiArgs) + 2 * sizeof(int64_t) + 2 * sizeof(int) + sizeof(double);
-  const size_t fit = R->u_batch_cap > 128 ? ((size_t)R->u_batch_cap - 128) / per : 0;
+  const size_t fit = std::min<size_t>(kFusedMax, R->u_batch_cap > 128 ? ((size_t)R->u_batch_cap - 128) / per : 0);
   if (fit == 0) throw Error(-1, "fused layer: no batched Jacobi tables");
   for (size_t g0 = 0; g0 < v.size(); g0 += fit) {
+    const int cnt = (int)std::min(fit, v.size() - g0);
+    int max_rows = 0, max_cols = 0, max_r = 0, max_np2 = 1;
     std::vector<JacobiArgs> tab;
-    for (size_t i = g0; i < std::min(v.size(), g0 + fit); ++i) tab.push_back(jac_entry(v[i]));
-    run_jacobi_group(R, tab);
+    tab.reserve(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      const JacSvd& x = v[g0 + i];
+      FusedSvdArgs& f = R->h_ftab[i];
+      f = fused_args(x, R->f_k + 2 * i);
+      max_rows = std::max(max_rows, f.rows);
+      max_cols = std::max(max_cols, f.cols);
+      max_r = std::max(max_r, f.r);
+      max_np2 = std::max(max_np2, f.npow2);
+      tab.push_back(jac_entry(x));
+    }
+    PTEBD_HIP(hipMemcpyAsync(R->f_tab, R->h_ftab, sizeof(FusedSvdArgs) * cnt, hipMemcpyHostToDevice, s));
+    fused_stage(R->f_tab, cnt, max_rows, max_cols, s);
+    run_jacobi_group(R, tab, [&](double* tiny2) {
+      fused_row_norms(R->f_tab, cnt, max_r, s);
+      fused_jacobi_prologue(R->f_tab, cnt, max_r, tiny2, s);
+    });
+    fused_row_norms(R->f_tab, cnt, max_r, s);
+    fused_select(R->f_tab, cnt, max_np2, s);
+    PTEBD_HIP(hipMemcpyAsync(R->h_fk, R->f_k, sizeof(int) * 2 * cnt, hipMemcpyDeviceToHost, s));
+    PTEBD_HIP(hipStreamSynchronize(s));
+    int max_k = 0;
+    for (int i = 0; i < cnt; ++i) {
+      JacSvd& x = v[g0 + i];
+      x.k = R->h_fk[2 * i];
+      x.W->h_info[0] = x.k;
+      x.W->h_info[4] = R->h_fk[2 * i + 1];
+      count_rule(x.W);
+      max_k = std::max(max_k, x.k);
+    }
+    fused_gather(R->f_tab, cnt, max_k, max_cols, s);
   }
-  for (const JacSvd& x : v) jac_select(x, s);
-  PTEBD_HIP(hipStreamSynchronize(s));
-  for (JacSvd& x : v) jac_gather(x, s);
 }
 
 // One gate of a fused layer: the state it acts on, the workspace it uses.

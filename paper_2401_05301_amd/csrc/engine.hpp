@@ -125,6 +125,12 @@ struct tebd_mps {
   void* u_batch = nullptr;        // batched Jacobi tables of the sector eigenproblems
   int64_t u_batch_cap = 0;        // bytes
   int64_t flags_cap = 0;          // entries of flags
+  // Fused layers (opts.fuse): descriptor table of a batch of SVDs (device and
+  // pinned host staging, kFusedMax entries) and their truncation ranks.
+  ptebd::FusedSvdArgs* f_tab = nullptr;
+  ptebd::FusedSvdArgs* h_ftab = nullptr;
+  int* f_k = nullptr;
+  int* h_fk = nullptr;
   std::vector<ptebd::HermArgs> h_herm;
   std::vector<int64_t> h_first;
   std::vector<int> h_active;
@@ -154,6 +160,8 @@ struct Sizes {
 int auto_workers(int L, int requested, bool super = false, bool u1 = false, bool fuse = false);
 // Device bytes of the batched Jacobi tables of a fused-layer workspace on L sites.
 int64_t fused_table_bytes(int L);
+// Largest batch of SVDs one fused step launches together.
+constexpr int kFusedMax = 256;
 
 Sizes plan_sizes(int L, int d, int chi_max);
 // Sizes of a super-site chain of Ls sites of dimension D (two-site gates).

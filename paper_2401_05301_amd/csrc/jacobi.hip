@@ -333,8 +333,9 @@ __global__ __launch_bounds__(256) void jac_rotate_batched(const JacobiArgs* tab,
   jac_rotate_body(a, round, local / a.nuchunks, local % a.nuchunks, L);
 }
 
-__global__ __launch_bounds__(256) void row_norms_kernel(const double* xr, const double* xi, int64_t ldx,
-                                                        int r, int c, double* norms) {
+// One wave per row: the 2-norm of row `row` of the r x c matrix x.
+__device__ __forceinline__ void row_norm_body(const double* xr, const double* xi, int64_t ldx, int r, int c,
+                                              double* norms) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= r) return;
@@ -347,17 +348,24 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const double* xr, const 
   if (lane == 0) norms[row] = sqrt(s);
 }
 
+__global__ __launch_bounds__(256) void row_norms_kernel(const double* xr, const double* xi, int64_t ldx,
+                                                        int r, int c, double* norms) {
+  row_norm_body(xr, xi, ldx, r, c, norms);
+}
+
+// matrix blockIdx.y of the batch
+__global__ __launch_bounds__(256) void fused_row_norms_kernel(const FusedSvdArgs* tab) {
+  const FusedSvdArgs& a = tab[blockIdx.y];
+  row_norm_body(a.yr, a.yi, a.c, a.r, a.c, a.norms);
+}
+
 // Single work-group: bitonic sort (descending value, ascending index on ties),
-// then the truncation rule, sequentially in FP64 by one thread.
-__global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, int npow2, int is_gram,
-                                                     int chi_max, double w_max, double eps, double* lam_out,
-                                                     int* perm, double* inv_sig, int* info_i, double* info_d,
-                                                     double* ledger, const double* extra_tail) {
-  extern __shared__ unsigned char smem[];
-  double* key = reinterpret_cast<double*>(smem);
-  int* idx = reinterpret_cast<int*>(key + npow2);
-  __shared__ int s_k;
-  __shared__ double s_nrm;
+// then the truncation rule, sequentially in FP64 by one thread.  key and idx
+// hold npow2 entries of LDS; s_k and s_nrm are LDS scalars.
+__device__ __forceinline__ void select_body(const double* vals, int r, int npow2, int is_gram, int chi_max,
+                                            double w_max, double eps, double* lam_out, int* perm, double* inv_sig,
+                                            int* info_i, double* info_d, double* ledger, const double* extra_tail,
+                                            double* key, int* idx, int& s_k, double& s_nrm) {
   for (int i = threadIdx.x; i < npow2; i += 256) {
     if (i < r) {
       const double v = vals[i];
@@ -448,8 +456,34 @@ __global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, 
   }
 }
 
-__global__ __launch_bounds__(256) void negligible_kernel(const double* norms, int r, double* out) {
-  __shared__ double sh[256];
+__global__ __launch_bounds__(256) void select_kernel(const double* vals, int r, int npow2, int is_gram,
+                                                     int chi_max, double w_max, double eps, double* lam_out,
+                                                     int* perm, double* inv_sig, int* info_i, double* info_d,
+                                                     double* ledger, const double* extra_tail) {
+  extern __shared__ unsigned char smem[];
+  __shared__ int s_k;
+  __shared__ double s_nrm;
+  double* key = reinterpret_cast<double*>(smem);
+  select_body(vals, r, npow2, is_gram, chi_max, w_max, eps, lam_out, perm, inv_sig, info_i, info_d, ledger,
+              extra_tail, key, reinterpret_cast<int*>(key + npow2), s_k, s_nrm);
+}
+
+// matrix blockIdx.x of the batch; LDS sized for the largest npow2
+__global__ __launch_bounds__(256) void fused_select_kernel(const FusedSvdArgs* tab) {
+  extern __shared__ unsigned char smem[];
+  __shared__ int s_k;
+  __shared__ double s_nrm;
+  const FusedSvdArgs& a = tab[blockIdx.x];
+  double* key = reinterpret_cast<double*>(smem);
+  select_body(a.norms, a.r, a.npow2, a.is_gram, a.chi_max, a.w_max, a.eps, a.lam_out, a.perm, a.inv_sig, a.info_i,
+              a.info_d, a.ledger, a.extra_tail, key, reinterpret_cast<int*>(key + a.npow2), s_k, s_nrm);
+  if (threadIdx.x == 0) {
+    a.kout[0] = s_k;
+    a.kout[1] = a.info_i[4];
+  }
+}
+
+__device__ __forceinline__ void negligible_body(const double* norms, int r, double* out, double* sh) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < r; i += 256) acc += norms[i] * norms[i];
   sh[threadIdx.x] = acc;
@@ -464,8 +498,31 @@ __global__ __launch_bounds__(256) void negligible_kernel(const double* norms, in
   }
 }
 
-__global__ void gather_kernel(const double* sr, const double* si, int64_t lds, const int* perm,
-                              const double* scale, int k, int c, double* dr, double* di, int64_t ldd) {
+__global__ __launch_bounds__(256) void negligible_kernel(const double* norms, int r, double* out) {
+  __shared__ double sh[256];
+  negligible_body(norms, r, out, sh);
+}
+
+// blockIdx.y == 0: negligible_norm2 of matrix blockIdx.z; blockIdx.y > 0:
+// row blockIdx.y - 1 of the identity in its vectors (transposed matrices)
+__global__ __launch_bounds__(256) void fused_prologue_kernel(const FusedSvdArgs* tab, double* out) {
+  __shared__ double sh[256];
+  const FusedSvdArgs& a = tab[blockIdx.z];
+  if (blockIdx.y == 0) {
+    if (blockIdx.x == 0) negligible_body(a.norms, a.r, out + blockIdx.z, sh);
+    return;
+  }
+  const int i = (int)blockIdx.y - 1;
+  if (!a.transpose || i >= a.r) return;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.r; j += gridDim.x * blockDim.x) {
+    a.wr[(int64_t)i * a.ldw + j] = (i == j) ? 1.0 : 0.0;
+    a.wi[(int64_t)i * a.ldw + j] = 0.0;
+  }
+}
+
+__device__ __forceinline__ void gather_body(const double* sr, const double* si, int64_t lds, const int* perm,
+                                            const double* scale, int k, int c, double* dr, double* di,
+                                            int64_t ldd) {
   const int i = blockIdx.y;
   if (i >= k) return;
   const int src = perm[i];
@@ -474,6 +531,17 @@ __global__ void gather_kernel(const double* sr, const double* si, int64_t lds, c
     dr[(int64_t)i * ldd + j] = sr[(int64_t)src * lds + j] * s;
     di[(int64_t)i * ldd + j] = si[(int64_t)src * lds + j] * s;
   }
+}
+
+__global__ void gather_kernel(const double* sr, const double* si, int64_t lds, const int* perm,
+                              const double* scale, int k, int c, double* dr, double* di, int64_t ldd) {
+  gather_body(sr, si, lds, perm, scale, k, c, dr, di, ldd);
+}
+
+// matrix blockIdx.z of the batch, k from its kout
+__global__ void fused_gather_kernel(const FusedSvdArgs* tab) {
+  const FusedSvdArgs& a = tab[blockIdx.z];
+  gather_body(a.gr, a.gi, a.ldg, a.perm, a.gscale ? a.inv_sig : nullptr, a.kout[0], a.gc, a.dr, a.di, a.ldd);
 }
 
 }  // namespace
@@ -538,6 +606,42 @@ void select_truncate(const double* vals, int r, int is_gram, int chi_max, double
   }
   select_kernel<<<1, 256, shm, s>>>(vals, r, np2, is_gram, chi_max, w_max, eps, lam_out, perm, inv_sig, info_i,
                                     info_d, ledger, extra_tail);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void fused_row_norms(const FusedSvdArgs* tab, int count, int max_r, hipStream_t s) {
+  if (count <= 0 || max_r <= 0) return;
+  fused_row_norms_kernel<<<dim3(ceil_div(max_r, 4), count), 256, 0, s>>>(tab);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void fused_jacobi_prologue(const FusedSvdArgs* tab, int count, int max_r, double* out, hipStream_t s) {
+  if (count <= 0 || max_r <= 0) return;
+  fused_prologue_kernel<<<dim3(std::min(ceil_div(max_r, 256), 64), max_r + 1, count), 256, 0, s>>>(tab, out);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void fused_select(const FusedSvdArgs* tab, int count, int max_npow2, hipStream_t s) {
+  if (count <= 0) return;
+  const size_t shm = (size_t)max_npow2 * (sizeof(double) + sizeof(int));
+  constexpr size_t kMaxShm = 96 * 1024 + 1024;
+  if (shm > kMaxShm) throw Error(-1, "select: too many singular values for the on-chip sort");
+  if (shm > 48 * 1024) {
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [] {
+      attr_err = hipFuncSetAttribute((const void*)fused_select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kMaxShm);
+    });
+    PTEBD_HIP(attr_err);
+  }
+  fused_select_kernel<<<count, 256, shm, s>>>(tab);
+  PTEBD_LAUNCH_CHECK();
+}
+
+void fused_gather(const FusedSvdArgs* tab, int count, int max_k, int max_c, hipStream_t s) {
+  if (count <= 0 || max_k <= 0 || max_c <= 0) return;
+  fused_gather_kernel<<<dim3(std::min(ceil_div(max_c, 256), 64), max_k, count), 256, 0, s>>>(tab);
   PTEBD_LAUNCH_CHECK();
 }
 

@@ -60,6 +60,42 @@ void jacobi_round_batched(const JacobiArgs* tab, const int64_t* gram_first, int6
                           const int64_t* rot_first, int64_t rot_total, int count, const int* active, int round,
                           hipStream_t s);
 
+// ------------------------------------------------- fused batches of Jacobi-route SVDs
+// One matrix of a batch of one-sided Jacobi SVDs whose small steps run as one
+// launch for the whole batch (fused layers).  Each step does for every
+// matrix exactly what its single-matrix launcher does.
+struct FusedSvdArgs {
+  // staging: y = diag(rs) x (transpose = 0) or (diag(rs) x)^+ (transpose = 1), x rows x cols
+  const double* xr; const double* xi; int64_t ldx;
+  const double* rs; int rdiv;
+  int rows, cols, transpose;
+  double* yr; double* yi; int64_t ldy;
+  // the Jacobi operand: the r x c rows of y (ld c), and its row norms
+  int r, c;
+  double* norms;
+  double* wr; double* wi; int64_t ldw;      // vectors accumulated with transpose = 1 (set to the identity)
+  // truncation (as select_truncate)
+  int npow2, is_gram, chi_max;
+  double w_max, eps;
+  const double* extra_tail;
+  double* lam_out; int* perm; double* inv_sig; int* info_i; double* info_d; double* ledger;
+  int* kout;                                // [2]: k and the rule, contiguous over the batch
+  // gather: rows perm[0..k) of g (scaled by inv_sig when gscale) into d, gc columns each
+  const double* gr; const double* gi; int64_t ldg;
+  int gscale, gc;
+  double* dr; double* di; int64_t ldd;
+};
+// scale_rows_copy / conj_transpose_scaled of every matrix (max_rows, max_cols over the batch)
+void fused_stage(const FusedSvdArgs* tab, int count, int max_rows, int max_cols, hipStream_t s);
+// row_norms of every Jacobi operand (max_r rows at most)
+void fused_row_norms(const FusedSvdArgs* tab, int count, int max_r, hipStream_t s);
+// negligible_norm2 of every matrix into out[i], and the identity into the vectors of transposed ones
+void fused_jacobi_prologue(const FusedSvdArgs* tab, int count, int max_r, double* out, hipStream_t s);
+// select_truncate of every matrix (npow2 at most max_npow2), k and the rule also into kout
+void fused_select(const FusedSvdArgs* tab, int count, int max_npow2, hipStream_t s);
+// gather_rows of every matrix, k read from kout on the device (max_k over the batch)
+void fused_gather(const FusedSvdArgs* tab, int count, int max_k, int max_c, hipStream_t s);
+
 // ------------------------------------------------- two-sided Hermitian Jacobi
 struct HermArgs {
   double* hr; double* hi; int64_t ldh;      // H (n x n), overwritten towards diagonal
