@@ -235,7 +235,8 @@ tebd_status mps_discarded_weight(const tebd_mps* mps, double* w_total);
  * MPS lives on) and the discarded-weight ledger, written into the host buffer
  * buf[cap] as a self-describing byte image (format tag, version, sizes, a
  * 64-bit checksum; no pointers).  *bytes receives the size of the image; with
- * buf = NULL only the size is returned.  TEBD_EINVAL when cap < *bytes.
+ * buf = NULL only the size is returned.  TEBD_EINVAL when cap < *bytes;
+ * TEBD_ESTATE for a handle left half applied by a failed layer.
  * Synchronises the handle and leaves it unchanged.  The Hamiltonian, the
  * options and the elapsed time are the caller's to keep. */
 tebd_status mps_checkpoint(const tebd_mps* mps, void* buf, size_t cap, size_t* bytes);

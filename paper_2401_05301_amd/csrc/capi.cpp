@@ -447,7 +447,9 @@ tebd_status mps_discarded_weight(const tebd_mps* M, double* w) {
 }
 
 tebd_status mps_checkpoint(const tebd_mps* M, void* buf, size_t cap, size_t* bytes) {
-  if (!M || !bytes) return fail(TEBD_EINVAL, "NULL argument");
+  if (!bytes) return fail(TEBD_EINVAL, "NULL argument");
+  tebd_status st0 = usable(M);   // a half-applied layer is no state to resume from
+  if (st0) return st0;
   const int L = M->L, d = M->d;
   const size_t payload = ck_payload(M->chi.data(), L, d);
   *bytes = sizeof(CkHeader) + payload;

@@ -1,6 +1,6 @@
 """Error contract of the C-ABI on the GPU: an SVD that does not converge
 within max_sweeps returns ENOCONV and leaves the handle refusing further
-evolution and measurement (ESTATE), on every SVD route, with one gate worker
+evolution, measurement and checkpoints (ESTATE), on every SVD route, with one gate worker
 and with several, and with fused layers.  The sweep limit is set from the host, so every kernel
 still runs its normal, bounded course."""
 import pytest
@@ -39,7 +39,7 @@ def test_unconverged_svd_marks_handle(pt, svd, u1, workers, fuse):
     with pytest.raises(pt.TebdError) as e:
         g.layer(0, 0.05)
     assert e.value.status == pt.TEBD_ENOCONV
-    for call in (lambda: g.layer(1, 0.05), g.measure, lambda: g.step(0.05)):
+    for call in (lambda: g.layer(1, 0.05), g.measure, lambda: g.step(0.05), g.checkpoint):
         with pytest.raises(pt.TebdError) as e:
             call()
         assert e.value.status == pt.TEBD_ESTATE
