@@ -201,6 +201,38 @@ def u1_sample(pt, torch, args, eps):
     return out
 
 
+def fused_sample(pt, chi: int = 32, steps: int = 4):
+    """Fused layers against concurrent workers on the same small-chi state:
+    the L = 64, d = 5 chain from a random right-orthonormal MPS at bond
+    dimension chi (cap chi, so every gate truncates), Jacobi route, one
+    untimed step, then `steps` timed Strang steps each way."""
+    import numpy as np
+    from workloads import Model, random_mps
+    L, d, dt = 64, 5, 0.01
+    m = Model(L=L, d=d, U=3.0, J=1.0, Jnnn=0.1, K=0.002)
+    B, lam = random_mps(L, d, chi, seed=2, tau=8.0)
+    res, obs = {}, {}
+    for name, fuse in (("workers", False), ("fused", True)):
+        g = pt.MPS.from_tensors(pt.make_model(L, d, m.U, m.J, m.Jnnn, m.K, m.centre()),
+                                pt.make_opts(chi, 1e-10, 1e-10, fuse=fuse), B, lam)
+        g.prepare(dt)
+        g.step(dt)
+        g.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.step(dt)
+        g.sync()
+        sec = (time.perf_counter() - t0) / steps
+        obs[name] = g.measure()
+        res[name] = {"ms_per_step": 1e3 * sec, "gate_updates_per_s": gate_updates_per_step(L) / sec}
+        g.close()
+    res["speedup"] = res["workers"]["ms_per_step"] / res["fused"]["ms_per_step"]
+    res["bit_identical"] = all(np.array_equal(a, b) for a, b in zip(obs["workers"], obs["fused"]))
+    res["input"] = (f"L={L}, d={d}, random right-orthonormal MPS at chi={chi} (seed 2), cap {chi}, Jacobi route, "
+                    f"w_max = eps = 1e-10, dt={dt}; six workers against one fused batch per layer")
+    return res
+
+
 def precision_batching(pt, torch, args):
     """The same chi = 1024 state stepped four ways with one library: FP64 with
     one gate worker (the plain per-gate form), FP64 with six concurrent
@@ -361,6 +393,8 @@ def main():
                     help="skip the square-GEMM reference (it launches this library's GEMM after the timed step)")
     ap.add_argument("--no-precision-leg", action="store_true",
                     help="skip the plain/batched FP64 vs batched FP32 comparison on an L = 16 chain")
+    ap.add_argument("--no-fused-sample", action="store_true",
+                    help="skip the fused-layer sample (chi = 32, fused against concurrent workers)")
     ap.add_argument("--no-u1-sample", action="store_true",
                     help="skip the U(1) step reported under u1_sample in the default run")
     ap.add_argument("--sigma", type=float, default=2.0,
@@ -462,6 +496,7 @@ def main():
     e0.record(stream)
     steps_run = 0
     est = t_warm
+    step_s = []
     for k in range(max(1, args.steps)):
         if steps_run >= 1 and est is not None and (time.perf_counter() - t0) + est > args.budget:
             break
@@ -470,6 +505,7 @@ def main():
         n, C, D = g.measure()
         steps_run += 1
         est = time.perf_counter() - ts
+        step_s.append(est)
         log(f"timed step {k + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)")
     e1.record(stream)
     torch.cuda.synchronize()
@@ -513,6 +549,9 @@ def main():
                           # figure is then a dense-equivalent rate, not work done
                           "dense_equivalent": bool(args.u1)},
         "wall_s": wall,
+        # host wall time of every timed step (step plus measurement, which reads the
+        # observables back): the spread of the timed steps
+        "seconds_per_step": [round(t, 3) for t in step_s],
         "discarded_weight_per_step": (w1 - w0) / steps_run,
         "trunc_rule_counts": {k: rules1[k] - rules0[k] for k in rules1},
         "smallest_kept_lambda_ratio": lam_min,
@@ -584,6 +623,9 @@ def main():
     if not args.no_cpu_baseline and time_left():
         log(f"timing the CPU oracle on one chi={args.cpu_chi} gate update")
         out["cpu_baseline"] = cpu_baseline(args.cpu_chi)
+    if not args.no_fused_sample and time_left():
+        log("fused layers against concurrent workers at chi = 32")
+        out["fused_layers"] = fused_sample(pt)
     if args.serve > 0 and time_left():
         # the same requests and truncation on the Jacobi route, thread per
         # request against continuous batching
