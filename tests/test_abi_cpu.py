@@ -182,6 +182,17 @@ def test_serve_validation_without_gpu():
     with pytest.raises(pt.TebdError) as e:
         pt.tebd_serve(big, hbm_budget=1024.0)
     assert e.value.status == pt.TEBD_ENOMEM
+    # continuous batching fuses layers, which needs the Jacobi route and dense tensors
+    for kw in (dict(svd=pt.SVD_GRAM_EIG, eps=pt.GRAM_EPS_MIN), dict(u1=True)):
+        with pytest.raises(pt.TebdError) as e:
+            pt.tebd_serve(big, hbm_budget=1e9, batched=True, **kw)
+        assert e.value.status == pt.TEBD_EINVAL and "fuse" in str(e.value)
+    # and its requests reserve one gate workspace per gate of a layer
+    assert big[0]["model"].L == 8
+    foot_fused = pt.mps_footprint(m, pt.make_opts(8, fuse=True))
+    with pytest.raises(pt.TebdError) as e:
+        pt.tebd_serve(big, hbm_budget=float(foot_fused - 1), batched=True, workers_per_request=0)
+    assert e.value.status == pt.TEBD_ENOMEM
 
 
 def test_headers_compile_as_c(tmp_path):
