@@ -356,9 +356,10 @@ def tebd_serve(requests, max_active: int = 8, hbm_budget: float = 0.0, prec: int
     """Serve quench requests concurrently (see tebd_serve in ptebd.h).
 
     ``requests`` are dicts with keys model (a Model), chi_max, dt, steps,
-    arrival (s) and optionally first_occupied.  Returns one dict per request
-    with arrival/admitted/finished times, discarded weight, gate updates,
-    status and the observables n, c_nn, c_nnn at the horizon."""
+    arrival (s) and optionally first_occupied.  ``batched`` serves them by
+    continuous batching (Jacobi route, dense tensors).  Returns one dict per
+    request with arrival/admitted/finished times, discarded weight, gate
+    updates, status and the observables n, c_nn, c_nnn at the horizon."""
     n = len(requests)
     req = (Request * n)()
     for i, r in enumerate(requests):
