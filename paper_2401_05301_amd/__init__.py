@@ -513,8 +513,6 @@ def _load_diag():
         f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
                       ctypes.c_double, ctypes.c_double, P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double),
                       P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
-
-
     _lib.tebd_diag_profile_sites.restype = ctypes.c_int
     _lib.tebd_diag_profile_sites.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]
     _lib.tebd_diag_tile_tuner.restype = ctypes.c_int

@@ -245,3 +245,22 @@ def test_binding_structs_match_the_c_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_binding_argument_counts_match_the_header():
+    """Every declared entry point that the binding types takes as many
+    arguments in the binding as in its C prototype."""
+    import paper_2401_05301_amd as pt
+    checked = 0
+    for h in ("ptebd.h", "ptebd_diag.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for name, params in re.findall(r"\b(?:tebd_status|void|const char\*)\s+\**\s*(\w+)\s*\(([^)]*)\)\s*;", txt):
+            params = " ".join(params.split())
+            n = 0 if params in ("", "void") else params.count(",") + 1
+            f = getattr(pt._lib, name)
+            if f.argtypes is None:
+                continue
+            assert len(f.argtypes) == n, (name, len(f.argtypes), n)
+            checked += 1
+    assert checked >= 35
