@@ -40,7 +40,7 @@ def command(prec: str) -> str:
     counter, _, flags, _ = SETTINGS[prec]
     return (f"rocprofv3 --pmc MfmaUtil {counter} --kernel-include-regex zgemm_kernel --output-format csv "
             f"-d <dir>/mfma -o bench_mfma -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline "
-            f"--serve 0 --no-u1-sample --no-square-gemm --no-precision-leg{flags}")
+            f"--serve 0 --no-u1-sample --no-square-gemm --no-precision-leg --no-fused-sample{flags}")
 
 
 def dispatches(path: str, name_part: str):

@@ -99,9 +99,9 @@ def main():
         "",
         "```",
         "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_fetch -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
+        "-o bench_fetch -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg --no-fused-sample",
         "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex zgemm_kernel --output-format csv -d <dir>/pmc "
-        "-o bench_write -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg",
+        "-o bench_write -- python -u bench.py --workers 1 --steps 1 --warmup 0 --no-cpu-baseline --serve 0 --no-u1-sample --no-square-gemm --no-precision-leg --no-fused-sample",
         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc -o copy_fetch -- python -u bench.py "
         "--copy-calibration 1024",
         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc -o copy_write -- python -u bench.py "
